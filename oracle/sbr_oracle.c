@@ -1,0 +1,562 @@
+/*
+ * sbr_oracle.c -- FP64 reference of the specular-only SBR radio map.
+ *
+ * TEST INFRASTRUCTURE.  This file is the correctness oracle of the project:
+ * only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may build, load or call it.  The HIP library never links it, and the two
+ * share no code, header, table or helper.
+ *
+ * It is deliberately plain and slow: one thread, double precision,
+ * std C99 complex arithmetic, brute-force intersection against every
+ * triangle, and a field representation that differs from the GPU path
+ * (a complex 3-vector in global coordinates instead of a 2x2 transfer
+ * matrix in per-ray local bases).
+ *
+ * What it computes (citations are to the Sionna RT technical report,
+ * arXiv 2504.21719, v2.1):
+ *   - ray directions on the spherical Fibonacci lattice
+ *     (Sec. "Sampling Initial Ray Directions");
+ *   - the transmitted field C_T = sqrt(G) F rotated into the global frame
+ *     (App. A: eq. rotation, eq. theta_phi_prime, eq. F_prime_2_F, eq. C);
+ *   - closest hit per segment by brute force (Sec. "Generating Candidates by
+ *     SBR": intersect, deactivate on a miss);
+ *   - specular reflection: reflected direction (eq. path-solver-scatter-dir,
+ *     eq. reflected_refracted_vectors), TE/TM bases (eq. fresnel_in_vectors,
+ *     eq. fresnel_out_vectors), vacuum Fresnel coefficients (eq. fresnel_vac)
+ *     with the complex relative permittivity of eq. eta;
+ *   - the Monte-Carlo radio-map estimator eq. radio-map-solver-ci-all-2-
+ *     estimator for specular chains only (no diffuse reflection, so n_S = 0 and
+ *     the interaction probability is 1), in which the squared ray-tube length
+ *     r^2 of the change of variables dA = r^2/|n^T k| d(omega) cancels the
+ *     1/r^2 of the spherical spreading of the path gain eq. radio-map-solver-
+ *     path-gain; every depth l = 0..L that crosses the plane contributes.
+ *
+ * Parity aids: per-segment hit ids, per-segment ambiguity flags (edge, tie,
+ * grazing, near-origin, polar ray) and per-crossing records.
+ *
+ * Gradients: forward-mode tangents of the field w.r.t. (eps_r[m], sigma[m]
+ * for every material, yaw, pitch, roll).  Fresnel derivatives are taken by the
+ * quotient rule on eq. fresnel_vac with d(eta)/d(eps_r) = 1 and
+ * d(eta)/d(sigma) = -j/(eps0 omega) from eq. eta; transmitter-angle
+ * derivatives use dual numbers through eq. rotation and eq. theta_phi_prime.
+ *
+ * Readings where the paper is silent (stated once here, used throughout):
+ *   - only specular reflection is enabled, so q(R) = 1 and Pr(chi) = 1;
+ *   - half-space (vacuum-incidence) Fresnel coefficients, no slab thickness;
+ *   - c0 = 299792458 m/s, eps0 = 8.8541878128e-12 F/m, phi_g = (1+sqrt 5)/2;
+ *   - the plane is two-sided and non-occluding; a segment contributes iff
+ *     0 < t_plane < t_hit (t_hit = inf on a miss); cells are half-open;
+ *   - segments l = 0..L are traced; segment L is traced to its first hit (or
+ *     infinity) for the crossing test and is not reflected;
+ *   - spawned rays exclude the primitive just hit and accept t > t_min;
+ *   - equal-t ties go to the smallest primitive index;
+ *   - the normal is flipped toward the incident side;
+ *   - at normal incidence the TE direction is k x a, with a the coordinate
+ *     axis least aligned with k;
+ *   - the complex square root is the principal branch.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define OR_C0 299792458.0
+#define OR_EPS0 8.8541878128e-12
+#define OR_PI 3.14159265358979323846
+
+/* flag bits per (ray, segment) */
+#define OR_FLAG_EDGE 1u
+#define OR_FLAG_TIE 2u
+#define OR_FLAG_GRAZING 4u
+#define OR_FLAG_NEAR 8u
+#define OR_FLAG_POLAR 16u
+
+#define OR_MAX_PARAMS 64
+#define OR_MAX_DEPTH 64
+
+/* ---------------------------------------------------------------- vectors */
+typedef struct { double x, y, z; } vec3;
+typedef struct { cplx x, y, z; } cvec3;
+
+static vec3 mk(double x, double y, double z) { vec3 r = {x, y, z}; return r; }
+static vec3 vsub(vec3 a, vec3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static vec3 vadd(vec3 a, vec3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static vec3 vscale(vec3 a, double s) { return mk(a.x * s, a.y * s, a.z * s); }
+static double vdot(vec3 a, vec3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static vec3 vcross(vec3 a, vec3 b) {
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+static double vnorm(vec3 a) { return sqrt(vdot(a, a)); }
+static vec3 vunit(vec3 a) { return vscale(a, 1.0 / vnorm(a)); }
+
+static cvec3 cv_zero(void) { cvec3 r = {0, 0, 0}; return r; }
+static cplx cv_dot_real(vec3 e, cvec3 E) { return e.x * E.x + e.y * E.y + e.z * E.z; }
+static cvec3 cv_axpy(cvec3 acc, cplx a, vec3 e) {
+    acc.x += a * e.x; acc.y += a * e.y; acc.z += a * e.z; return acc;
+}
+static double cv_norm2(cvec3 E) {
+    return creal(E.x * conj(E.x) + E.y * conj(E.y) + E.z * conj(E.z));
+}
+/* Re(E^H dE) */
+static double cv_re_inner(cvec3 E, cvec3 dE) {
+    return creal(conj(E.x) * dE.x + conj(E.y) * dE.y + conj(E.z) * dE.z);
+}
+
+/* ------------------------------------------------------- dual numbers (3) */
+/* value + derivatives w.r.t. (yaw, pitch, roll) */
+typedef struct { double v, d[3]; } dual;
+
+static dual dc(double v) { dual r; r.v = v; r.d[0] = r.d[1] = r.d[2] = 0; return r; }
+static dual dvar(double v, int i) { dual r = dc(v); r.d[i] = 1.0; return r; }
+static dual dadd(dual a, dual b) { dual r; r.v = a.v + b.v; for (int i = 0; i < 3; i++) r.d[i] = a.d[i] + b.d[i]; return r; }
+static dual dsub(dual a, dual b) { dual r; r.v = a.v - b.v; for (int i = 0; i < 3; i++) r.d[i] = a.d[i] - b.d[i]; return r; }
+static dual dmul(dual a, dual b) { dual r; r.v = a.v * b.v; for (int i = 0; i < 3; i++) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
+static dual dneg(dual a) { dual r; r.v = -a.v; for (int i = 0; i < 3; i++) r.d[i] = -a.d[i]; return r; }
+static dual dfun(dual a, double f, double fp) { dual r; r.v = f; for (int i = 0; i < 3; i++) r.d[i] = fp * a.d[i]; return r; }
+static dual dsin(dual a) { return dfun(a, sin(a.v), cos(a.v)); }
+static dual dcos(dual a) { return dfun(a, cos(a.v), -sin(a.v)); }
+static dual dacos(dual a) {
+    double s = sqrt(fmax(0.0, 1.0 - a.v * a.v));
+    return dfun(a, acos(fmax(-1.0, fmin(1.0, a.v))), s > 0 ? -1.0 / s : 0.0);
+}
+static dual datan2(dual y, dual x) {
+    dual r; double q = x.v * x.v + y.v * y.v;
+    r.v = atan2(y.v, x.v);
+    for (int i = 0; i < 3; i++) r.d[i] = q > 0 ? (x.v * y.d[i] - y.v * x.d[i]) / q : 0.0;
+    return r;
+}
+static dual dpow(dual a, double p) {
+    double f = pow(a.v, p);
+    double fp = (a.v > 0) ? p * pow(a.v, p - 1.0) : 0.0;
+    return dfun(a, f, fp);
+}
+static dual dsqrt(dual a) { double s = sqrt(fmax(0.0, a.v)); return dfun(a, s, s > 0 ? 0.5 / s : 0.0); }
+
+/* ----------------------------------------------------------------- inputs */
+typedef struct {
+    double pos[3];
+    double yaw, pitch, roll;
+    int32_t pattern;     /* 0 isotropic, 1 directional (q) */
+    double q;
+    int32_t pol;         /* 0 V, 1 H, 2 dual (V and H) */
+} or_tx;
+
+typedef struct {
+    double z, x0, y0, dx, dy;
+    int32_t W, H;
+} or_plane;
+
+typedef struct {
+    double freq;
+    int64_t n_rays;
+    int32_t max_depth;
+    double t_min;
+} or_params;
+
+typedef struct {
+    /* all outputs optional (NULL) */
+    double* map;          /* [npol][H][W], accumulated into                  */
+    int64_t* counts;      /* [H][W] crossings, accumulated into              */
+    int32_t* hits;        /* [n_rays_run][L+1]                              */
+    uint8_t* flags;       /* [n_rays_run][L+1]                              */
+    int64_t rec_cap;      /* capacity of the crossing-record arrays          */
+    int64_t rec_n;        /* out: number of crossings (may exceed rec_cap)  */
+    int64_t* rec_ray;
+    int32_t* rec_depth;
+    int32_t* rec_cell;
+    double* rec_w;        /* weight of polarisation 0                        */
+    double* rec_border;   /* distance to the nearest decision boundary (m)   */
+    double* rec_len;      /* unfolded length from the source (m)             */
+    const double* grad_map; /* [npol][H][W] upstream gradient, or NULL       */
+    double* grad;         /* [2*n_mat+3] accumulated: eps_r[m], sigma[m], yaw, pitch, roll */
+    const int32_t* replay_hits; /* [n_rays_run][L+1]: force these hits (no search) */
+    int64_t tri_tests;    /* out: number of ray-triangle tests */
+    int64_t segments;     /* out: number of traced segments */
+} or_out;
+
+/* ------------------------------------------------------ lattice and launch */
+/* Spherical Fibonacci lattice (Sec. "Sampling Initial Ray Directions"). */
+void or_fibonacci(int64_t n, int64_t N, double* theta, double* phi)
+{
+    if (N == 1) { *theta = OR_PI / 2; *phi = OR_PI; return; }
+    double u = 1.0 - 2.0 * (double)n / (double)(N - 1);
+    *theta = acos(u);
+    /* frac(n / phi_g) = frac(n (phi_g - 1)), evaluated in extended precision */
+    long double g1 = (sqrtl(5.0L) - 1.0L) / 2.0L;
+    long double x = (long double)n * g1;
+    long double fr = x - floorl(x);
+    *phi = 2.0 * OR_PI * (double)fr;
+}
+
+static vec3 lattice_dir(int64_t n, int64_t N)
+{
+    double th, ph;
+    or_fibonacci(n, N, &th, &ph);
+    double u = (N == 1) ? 0.0 : 1.0 - 2.0 * (double)n / (double)(N - 1);
+    double st = sqrt(fmax(0.0, (1.0 - u) * (1.0 + u)));
+    return mk(st * cos(ph), st * sin(ph), u);
+}
+
+/* R(yaw, pitch, roll) = Rz(yaw) Ry(pitch) Rx(roll), eq. rotation, with duals */
+static void rotation_dual(double yaw, double pitch, double roll, dual R[3][3])
+{
+    dual a = dvar(yaw, 0), b = dvar(pitch, 1), g = dvar(roll, 2);
+    dual ca = dcos(a), sa = dsin(a), cb = dcos(b), sb = dsin(b), cg = dcos(g), sg = dsin(g);
+    dual Rz[3][3] = {{ca, dneg(sa), dc(0)}, {sa, ca, dc(0)}, {dc(0), dc(0), dc(1)}};
+    dual Ry[3][3] = {{cb, dc(0), sb}, {dc(0), dc(1), dc(0)}, {dneg(sb), dc(0), cb}};
+    dual Rx[3][3] = {{dc(1), dc(0), dc(0)}, {dc(0), cg, dneg(sg)}, {dc(0), sg, cg}};
+    dual T[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            dual s = dc(0);
+            for (int k = 0; k < 3; k++) s = dadd(s, dmul(Rz[i][k], Ry[k][j]));
+            T[i][j] = s;
+        }
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            dual s = dc(0);
+            for (int k = 0; k < 3; k++) s = dadd(s, dmul(T[i][k], Rx[k][j]));
+            R[i][j] = s;
+        }
+}
+
+/*
+ * Transmitted field in global coordinates for direction k (a real 3-vector,
+ * with derivatives w.r.t. yaw/pitch/roll).  The local direction is u = R^T k
+ * (eq. theta_phi_prime); the local pattern C' = (C_theta', C_phi') multiplies
+ * the local spherical unit vectors (eq. spherical_vecs) and the vector is
+ * rotated back by R, which is eq. F_prime_2_F written as a 3-vector.
+ * pol_index: 0 -> C' = sqrt(G) theta_hat', 1 -> C' = sqrt(G) phi_hat'.
+ */
+static void launch_field(vec3 k, const or_tx* tx, int pol_index, dual E[3])
+{
+    dual R[3][3];
+    rotation_dual(tx->yaw, tx->pitch, tx->roll, R);
+    double kk[3] = {k.x, k.y, k.z};
+    dual u[3];
+    for (int i = 0; i < 3; i++) {           /* u = R^T k */
+        dual s = dc(0);
+        for (int j = 0; j < 3; j++) s = dadd(s, dmul(R[j][i], dc(kk[j])));
+        u[i] = s;
+    }
+    dual th = dacos(u[2]);
+    dual ph = datan2(u[1], u[0]);
+    dual ct = dcos(th), st = dsin(th), cp = dcos(ph), sp = dsin(ph);
+    dual thv[3] = {dmul(ct, cp), dmul(ct, sp), dneg(st)};
+    dual phv[3] = {dneg(sp), cp, dc(0)};
+    dual amp;
+    if (tx->pattern == 1) {
+        /* G(alpha) = (q+1) ((1 + cos alpha)/2)^q, alpha = angle to local +x */
+        dual half = dmul(dadd(dc(1.0), u[0]), dc(0.5));
+        amp = dsqrt(dmul(dc(tx->q + 1.0), dpow(half, tx->q)));
+    } else {
+        amp = dc(1.0);
+    }
+    dual f[3];
+    for (int i = 0; i < 3; i++) f[i] = dmul(amp, pol_index == 0 ? thv[i] : phv[i]);
+    for (int i = 0; i < 3; i++) {           /* E = R f */
+        dual s = dc(0);
+        for (int j = 0; j < 3; j++) s = dadd(s, dmul(R[i][j], f[j]));
+        E[i] = s;
+    }
+}
+
+/* --------------------------------------------------------- intersection */
+typedef struct {
+    const float* V; const int32_t* F; int64_t n_tri;
+} or_mesh;
+
+static void tri_verts(const or_mesh* m, int64_t t, vec3* a, vec3* b, vec3* c)
+{
+    const int32_t* f = m->F + 3 * t;
+    const float* p0 = m->V + 3 * (int64_t)f[0];
+    const float* p1 = m->V + 3 * (int64_t)f[1];
+    const float* p2 = m->V + 3 * (int64_t)f[2];
+    *a = mk(p0[0], p0[1], p0[2]);
+    *b = mk(p1[0], p1[1], p1[2]);
+    *c = mk(p2[0], p2[1], p2[2]);
+}
+
+/* Moeller-Trumbore in double: returns 1 if the supporting plane is hit at
+ * finite t, with barycentrics (u, v) and t; inside-ness is decided by caller. */
+static int tri_plane_hit(vec3 o, vec3 k, vec3 a, vec3 b, vec3 c, double* t, double* bu, double* bv)
+{
+    vec3 e1 = vsub(b, a), e2 = vsub(c, a);
+    vec3 p = vcross(k, e2);
+    double det = vdot(e1, p);
+    if (det == 0.0 || !isfinite(det)) return 0;
+    double inv = 1.0 / det;
+    vec3 s = vsub(o, a);
+    double u = vdot(s, p) * inv;
+    vec3 q = vcross(s, e1);
+    double v = vdot(k, q) * inv;
+    *t = vdot(e2, q) * inv;
+    *bu = u; *bv = v;
+    return 1;
+}
+
+typedef struct {
+    double t; int64_t prim; double t2; uint8_t flags;
+} hit_info;
+
+static hit_info closest_hit(const or_mesh* m, vec3 o, vec3 k, int64_t last, double t_min, int64_t* tests)
+{
+    hit_info h = {INFINITY, -1, INFINITY, 0};
+    double t_edge = INFINITY;   /* smallest t of a triangle hit/missed within 1e-5 of an edge */
+    double t_any = INFINITY;    /* smallest positive t of any (nearly) inside triangle */
+    for (int64_t i = 0; i < m->n_tri; i++) {
+        if (i == last) continue;
+        vec3 a, b, c;
+        tri_verts(m, i, &a, &b, &c);
+        double t, u, v;
+        (*tests)++;
+        if (!tri_plane_hit(o, k, a, b, c, &t, &u, &v)) continue;
+        double w = 1.0 - u - v;
+        double mb = fmin(u, fmin(v, w));
+        if (t > 0.0 && mb > -1e-5 && t < t_any) t_any = t;
+        if (!(t > t_min)) continue;
+        if (fabs(mb) < 1e-5 && t < t_edge) t_edge = t;
+        if (mb < 0.0) continue;
+        if (t < h.t || (t == h.t && i < h.prim)) {
+            h.t2 = h.t;
+            h.t = t;
+            h.prim = i;
+        } else if (t < h.t2) {
+            h.t2 = t;
+        }
+    }
+    if (t_edge <= h.t * (1.0 + 1e-6)) h.flags |= OR_FLAG_EDGE;
+    if (h.prim >= 0 && h.t2 <= h.t * (1.0 + 1e-5)) h.flags |= OR_FLAG_TIE;
+    if (t_any < 1e-2) h.flags |= OR_FLAG_NEAR;
+    return h;
+}
+
+/* ------------------------------------------------------------- main loop */
+/*
+ * or_radio_map: trace rays [ray_begin, ray_end) of an N_S-ray lattice (or the
+ * explicit list ray_ids[0..n_ids) when ray_ids != NULL) and accumulate the
+ * radio map and the optional parity / gradient outputs.
+ * Returns 0 on success, nonzero on invalid arguments.
+ */
+int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
+                 const int32_t* tri_mat, int32_t n_mat,
+                 const double* eps_r, const double* sigma,
+                 const or_tx* tx, const or_plane* pl, const or_params* prm,
+                 const int64_t* ray_ids, int64_t n_ids, int64_t ray_begin, int64_t ray_end,
+                 or_out* out)
+{
+    if (prm->n_rays < 1 || prm->max_depth < 0 || prm->max_depth >= OR_MAX_DEPTH) return 1;
+    if (pl->W < 1 || pl->H < 1 || !(pl->dx > 0) || !(pl->dy > 0)) return 1;
+    if (n_mat < 1 || 2 * n_mat + 3 > OR_MAX_PARAMS) return 1;
+    for (int64_t i = 0; i < n_tri; i++) {
+        for (int j = 0; j < 3; j++)
+            if (F[3 * i + j] < 0 || F[3 * i + j] >= n_v) return 1;
+        if (tri_mat[i] < 0 || tri_mat[i] >= n_mat) return 1;
+    }
+    const int L = prm->max_depth;
+    const int64_t N = prm->n_rays;
+    const int npol = tx->pol == 2 ? 2 : 1;
+    const int P = 2 * n_mat + 3;
+    const double lam = OR_C0 / prm->freq;
+    const double omega = 2.0 * OR_PI * prm->freq;
+    const double area = pl->dx * pl->dy;
+    const double kappa = lam * lam / (4.0 * OR_PI * (double)N * area);
+    const cplx deta_dsigma = -I / (OR_EPS0 * omega);
+    or_mesh mesh = {V, F, n_tri};
+    const int want_grad = out->grad_map != NULL && out->grad != NULL;
+    int64_t n_run = ray_ids ? n_ids : (ray_end - ray_begin);
+    if (!ray_ids && (ray_begin < 0 || ray_end > N || ray_begin > ray_end)) return 1;
+    out->rec_n = 0;
+    out->tri_tests = 0;
+    out->segments = 0;
+
+    cvec3 E[2];
+    static cvec3 dE[2][OR_MAX_PARAMS];
+
+    for (int64_t r = 0; r < n_run; r++) {
+        int64_t n = ray_ids ? ray_ids[r] : ray_begin + r;
+        if (n < 0 || n >= N) return 1;
+        vec3 k = lattice_dir(n, N);
+        for (int p = 0; p < npol; p++) {
+            dual Ed[3];
+            launch_field(k, tx, tx->pol == 1 ? 1 : p, Ed);
+            E[p].x = Ed[0].v; E[p].y = Ed[1].v; E[p].z = Ed[2].v;
+            for (int q = 0; q < P; q++) dE[p][q] = cv_zero();
+            for (int a = 0; a < 3; a++) {
+                dE[p][2 * n_mat + a].x = Ed[0].d[a];
+                dE[p][2 * n_mat + a].y = Ed[1].d[a];
+                dE[p][2 * n_mat + a].z = Ed[2].d[a];
+            }
+        }
+        vec3 o = mk(tx->pos[0], tx->pos[1], tx->pos[2]);
+        int64_t last = -1;
+        double run_len = 0.0;
+        int32_t* hrow = out->hits ? out->hits + r * (L + 1) : NULL;
+        uint8_t* frow = out->flags ? out->flags + r * (L + 1) : NULL;
+        if (hrow) for (int l = 0; l <= L; l++) hrow[l] = -2;
+        if (frow) for (int l = 0; l <= L; l++) frow[l] = 0;
+
+        for (int l = 0; l <= L; l++) {
+            hit_info h;
+            if (out->replay_hits) {
+                int32_t pr = out->replay_hits[r * (L + 1) + l];
+                if (pr == -2) break;
+                h.prim = pr; h.t = INFINITY; h.t2 = INFINITY; h.flags = 0;
+                if (pr >= 0) {
+                    vec3 a, b, c; double t, u, v;
+                    tri_verts(&mesh, pr, &a, &b, &c);
+                    if (!tri_plane_hit(o, k, a, b, c, &t, &u, &v)) return 2;
+                    h.t = t;
+                }
+            } else {
+                h = closest_hit(&mesh, o, k, last, prm->t_min, &out->tri_tests);
+            }
+            out->segments++;
+            uint8_t fl = h.flags;
+            if (N > 1 && (n == 0 || n == N - 1)) fl |= OR_FLAG_POLAR;
+
+            /* grazing incidence on the hit surface */
+            vec3 nrm = mk(0, 0, 0);
+            if (h.prim >= 0) {
+                vec3 a, b, c;
+                tri_verts(&mesh, h.prim, &a, &b, &c);
+                nrm = vunit(vcross(vsub(b, a), vsub(c, a)));
+                if (vdot(nrm, k) > 0) nrm = vscale(nrm, -1.0);
+                if (fabs(vdot(nrm, k)) < 1e-5) fl |= OR_FLAG_GRAZING;
+                if (h.t < 1e-2) fl |= OR_FLAG_NEAR;
+            }
+            if (hrow) hrow[l] = (int32_t)h.prim;
+            if (frow) frow[l] = fl;
+
+            /* measurement-plane crossing of this segment */
+            if (k.z != 0.0) {
+                double tm = (pl->z - o.z) / k.z;
+                if (tm > 0.0 && tm < h.t) {
+                    double x = o.x + tm * k.x, y = o.y + tm * k.y;
+                    double fx = (x - pl->x0) / pl->dx, fy = (y - pl->y0) / pl->dy;
+                    double fi = floor(fx), fj = floor(fy);
+                    if (fi >= 0 && fi < pl->W && fj >= 0 && fj < pl->H) {
+                        int64_t i = (int64_t)fi, j = (int64_t)fj;
+                        int64_t cell = j * pl->W + i;
+                        double g = kappa / fabs(k.z);
+                        for (int p = 0; p < npol; p++) {
+                            double w = g * cv_norm2(E[p]);
+                            if (out->map) out->map[(int64_t)p * pl->W * pl->H + cell] += w;
+                            if (want_grad) {
+                                double G = out->grad_map[(int64_t)p * pl->W * pl->H + cell];
+                                if (G != 0.0)
+                                    for (int q = 0; q < P; q++)
+                                        out->grad[q] += G * g * 2.0 * cv_re_inner(E[p], dE[p][q]);
+                            }
+                        }
+                        if (out->counts) out->counts[cell] += 1;
+                        int64_t ri = out->rec_n++;
+                        if (ri < out->rec_cap) {
+                            double bx = fmin(x - (pl->x0 + fi * pl->dx), pl->x0 + (fi + 1) * pl->dx - x);
+                            double by = fmin(y - (pl->y0 + fj * pl->dy), pl->y0 + (fj + 1) * pl->dy - y);
+                            double bz = fmin(tm * fabs(k.z), isfinite(h.t) ? (h.t - tm) * fabs(k.z) : INFINITY);
+                            if (out->rec_ray) out->rec_ray[ri] = n;
+                            if (out->rec_depth) out->rec_depth[ri] = l;
+                            if (out->rec_cell) out->rec_cell[ri] = (int32_t)cell;
+                            if (out->rec_w) out->rec_w[ri] = g * cv_norm2(E[0]);
+                            if (out->rec_border) out->rec_border[ri] = fmin(fmin(bx, by), bz);
+                            if (out->rec_len) out->rec_len[ri] = run_len + tm;
+                        }
+                    }
+                }
+            }
+            if (h.prim < 0 || l == L) break;
+
+            /* specular reflection at primitive h.prim */
+            int m = tri_mat[h.prim];
+            cplx eta = eps_r[m] - I * sigma[m] / (OR_EPS0 * omega);
+            double c = -vdot(nrm, k);                 /* cos(theta_1) >= 0 */
+            double s2 = 1.0 - c * c;                  /* sin^2(theta_1) */
+            cplx s = csqrt(eta - s2);
+            cplx den_p = c + s, den_l = eta * c + s;
+            cplx r_perp = (c - s) / den_p;
+            cplx r_par = (eta * c - s) / den_l;
+            /* derivatives w.r.t. eta (quotient rule; ds/deta = 1/(2 s)) */
+            cplx ds = 1.0 / (2.0 * s);
+            cplx dr_perp = ((-ds) * den_p - (c - s) * ds) / (den_p * den_p);
+            cplx dr_par = ((c - ds) * den_l - (eta * c - s) * (c + ds)) / (den_l * den_l);
+
+            vec3 kn = vcross(k, nrm);
+            vec3 e_perp;
+            if (vnorm(kn) > 1e-12) {
+                e_perp = vunit(kn);
+            } else {
+                double ax = fabs(k.x), ay = fabs(k.y), az = fabs(k.z);
+                vec3 a = (ax <= ay && ax <= az) ? mk(1, 0, 0) : (ay <= az ? mk(0, 1, 0) : mk(0, 0, 1));
+                e_perp = vunit(vcross(k, a));
+            }
+            vec3 e_par = vcross(e_perp, k);
+            vec3 kr = vsub(k, vscale(nrm, 2.0 * vdot(k, nrm)));
+            kr = vunit(kr);
+            vec3 er_par = vunit(vcross(e_perp, kr));
+
+            for (int p = 0; p < npol; p++) {
+                cplx a_perp = cv_dot_real(e_perp, E[p]);
+                cplx a_par = cv_dot_real(e_par, E[p]);
+                if (want_grad) {
+                    for (int q = 0; q < P; q++) {
+                        cplx b_perp = cv_dot_real(e_perp, dE[p][q]);
+                        cplx b_par = cv_dot_real(e_par, dE[p][q]);
+                        cvec3 nd = cv_zero();
+                        nd = cv_axpy(nd, r_perp * b_perp, e_perp);
+                        nd = cv_axpy(nd, r_par * b_par, er_par);
+                        cplx deta = 0.0;
+                        if (q == m) deta = 1.0;                   /* d eta / d eps_r[m] */
+                        else if (q == n_mat + m) deta = deta_dsigma; /* d eta / d sigma[m] */
+                        if (deta != 0.0) {
+                            nd = cv_axpy(nd, dr_perp * deta * a_perp, e_perp);
+                            nd = cv_axpy(nd, dr_par * deta * a_par, er_par);
+                        }
+                        dE[p][q] = nd;
+                    }
+                }
+                cvec3 En = cv_zero();
+                En = cv_axpy(En, r_perp * a_perp, e_perp);
+                En = cv_axpy(En, r_par * a_par, er_par);
+                E[p] = En;
+            }
+            o = vadd(o, vscale(k, h.t));
+            run_len += h.t;
+            k = kr;
+            last = h.prim;
+        }
+    }
+    return 0;
+}
+
+/* Fresnel coefficients for tests: eq. fresnel_vac at incidence cos(theta_1) = c. */
+void or_fresnel(double eps_r, double sigma, double freq, double c,
+                double* rperp_re, double* rperp_im, double* rpar_re, double* rpar_im)
+{
+    double omega = 2.0 * OR_PI * freq;
+    cplx eta = eps_r - I * sigma / (OR_EPS0 * omega);
+    cplx s = csqrt(eta - (1.0 - c * c));
+    cplx a = (c - s) / (c + s), b = (eta * c - s) / (eta * c + s);
+    *rperp_re = creal(a); *rperp_im = cimag(a);
+    *rpar_re = creal(b); *rpar_im = cimag(b);
+}
+
+/* Transmitted field (value only) for tests: E[3 complex as re,im pairs]. */
+void or_launch_field(double kx, double ky, double kz, const or_tx* tx, int pol_index, double* E3, double* dE3x3)
+{
+    dual Ed[3];
+    launch_field(mk(kx, ky, kz), tx, pol_index, Ed);
+    for (int i = 0; i < 3; i++) {
+        E3[i] = Ed[i].v;
+        if (dE3x3) for (int a = 0; a < 3; a++) dE3x3[3 * a + i] = Ed[i].d[a];
+    }
+}
+
+void or_lattice_dir(int64_t n, int64_t N, double* k3)
+{
+    vec3 k = lattice_dir(n, N);
+    k3[0] = k.x; k3[1] = k.y; k3[2] = k.z;
+}

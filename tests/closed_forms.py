@@ -1,0 +1,134 @@
+"""Closed-form reference values that pin the oracle (test-only, NumPy).
+
+Nothing here is shared with the oracle or the HIP library.  Where a
+reflection coefficient is needed it is taken from the general two-medium
+Fresnel equations (eq. fresnel) with Snell's law for cos(theta_2), a different
+route from the vacuum-incidence form (eq. fresnel_vac) that the oracle uses.
+
+Radio maps are cell averages (Sec. "Definition of Radio Map", eq. radio-map-
+solver-ci-ell), so point gains are integrated over each cell with 16 x 16
+Gauss-Legendre points.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+C0 = 299_792_458.0                 # m/s (exact)
+EPS0 = 8.8541878128e-12            # F/m (CODATA 2018)
+
+
+def wavelength(freq):
+    return C0 / freq
+
+
+def eta(eps_r, sigma, freq):
+    """Complex relative permittivity, eq. eta."""
+    return eps_r - 1j * sigma / (EPS0 * 2 * math.pi * freq)
+
+
+def fresnel_general(eta2, cos_t1):
+    """(r_perp, r_par) from eq. fresnel with eta1 = 1 and Snell's law."""
+    cos_t1 = np.asarray(cos_t1, dtype=np.complex128)
+    n2 = np.sqrt(eta2 + 0j)
+    sin2 = 1.0 - cos_t1 ** 2
+    cos_t2 = np.sqrt(1.0 - sin2 / eta2)
+    r_perp = (cos_t1 - n2 * cos_t2) / (cos_t1 + n2 * cos_t2)
+    r_par = (n2 * cos_t1 - cos_t2) / (n2 * cos_t1 + cos_t2)
+    return r_perp, r_par
+
+
+def normal_incidence_r(eta2):
+    """Textbook normal-incidence reflection coefficient (1 - n)/(1 + n), n = sqrt(eta)."""
+    n = np.sqrt(eta2 + 0j)
+    return (1 - n) / (1 + n)
+
+
+def brewster_angle(eps_r):
+    return math.atan(math.sqrt(eps_r))
+
+
+def free_space_gain(d, lam):
+    """Friis gain (lambda/(4 pi d))^2 for unit antenna gains (Friis box, App. A)."""
+    return (lam / (4 * math.pi * d)) ** 2
+
+
+def cell_average(fn, plane, n=16):
+    """(1/|M_i|) * integral of fn(x, y) over every cell, 16x16 Gauss-Legendre.
+
+    Returns an array [H][W].
+    """
+    g, w = np.polynomial.legendre.leggauss(n)
+    ux = (g + 1) / 2 * plane.dx           # offsets within a cell
+    uy = (g + 1) / 2 * plane.dy
+    wx = w / 2
+    xs = plane.x0 + np.arange(plane.W)[:, None] * plane.dx + ux[None, :]   # [W][n]
+    ys = plane.y0 + np.arange(plane.H)[:, None] * plane.dy + uy[None, :]   # [H][n]
+    X = xs[None, :, None, :]                                               # [1][W][1][n]
+    Y = ys[:, None, :, None]                                               # [H][1][n][1]
+    F = fn(np.broadcast_to(X, (plane.H, plane.W, n, n)), np.broadcast_to(Y, (plane.H, plane.W, n, n)))
+    return np.einsum("hwij,i,j->hw", F, wx, wx)
+
+
+def friis_map(tx_pos, plane, lam):
+    tx = np.asarray(tx_pos, dtype=np.float64)
+
+    def f(x, y):
+        d2 = (x - tx[0]) ** 2 + (y - tx[1]) ** 2 + (plane.z - tx[2]) ** 2
+        return (lam / (4 * math.pi)) ** 2 / d2
+
+    return cell_average(f, plane)
+
+
+def two_ray_map(tx_pos, plane, lam, eta2, pol="V", ground_z=0.0):
+    """Non-coherent two-ray map over a horizontal ground at z = ground_z.
+
+    LoS term plus the image-source term weighted by |r|^2 at the incidence
+    angle; V polarisation lies in the plane of incidence (r_par), H is
+    perpendicular to it (r_perp).  pol = "sum" gives |r_perp|^2 + |r_par|^2.
+    """
+    tx = np.asarray(tx_pos, dtype=np.float64)
+    ht = tx[2] - ground_z
+    hr = plane.z - ground_z
+
+    def f(x, y):
+        rho2 = (x - tx[0]) ** 2 + (y - tx[1]) ** 2
+        d_los2 = rho2 + (ht - hr) ** 2
+        d_ref2 = rho2 + (ht + hr) ** 2
+        cos_i = (ht + hr) / np.sqrt(d_ref2)
+        rp, rl = fresnel_general(eta2, cos_i)
+        if pol == "V":
+            refl = np.abs(rl) ** 2
+        elif pol == "H":
+            refl = np.abs(rp) ** 2
+        else:
+            refl = np.abs(rp) ** 2 + np.abs(rl) ** 2
+        return (lam / (4 * math.pi)) ** 2 * (1.0 / d_los2 + refl / d_ref2)
+
+    return cell_average(f, plane)
+
+
+def reflected_only_map(tx_pos, plane, lam, eta2, pol="V", ground_z=0.0):
+    tx = np.asarray(tx_pos, dtype=np.float64)
+    ht = tx[2] - ground_z
+    hr = plane.z - ground_z
+
+    def f(x, y):
+        rho2 = (x - tx[0]) ** 2 + (y - tx[1]) ** 2
+        d_ref2 = rho2 + (ht + hr) ** 2
+        cos_i = (ht + hr) / np.sqrt(d_ref2)
+        rp, rl = fresnel_general(eta2, cos_i)
+        refl = np.abs(rl) ** 2 if pol == "V" else np.abs(rp) ** 2
+        return (lam / (4 * math.pi)) ** 2 * refl / d_ref2
+
+    return cell_average(f, plane)
+
+
+def fibonacci_phase_exact(n: int) -> float:
+    """frac(n / phi_g) with 60 significant digits (decimal arithmetic)."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    phi = (Decimal(1) + Decimal(5).sqrt()) / 2
+    x = Decimal(n) / phi
+    return float(x - int(x))
