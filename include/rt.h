@@ -1,0 +1,288 @@
+/*
+ * rt.h -- C ABI of librtmap.so, the MI355X (gfx950) SBR radio-map library.
+ *
+ * What the library computes: the radio map of a point source over a
+ * horizontal measurement plane by shooting and bouncing rays (SBR), for
+ * specular reflection only.  Citations are to "Sionna RT: Technical Report"
+ * (arXiv 2504.21719, v2.1):
+ *   - rays leave the source on a spherical Fibonacci lattice of N_S points
+ *     (Sec. "Sampling Initial Ray Directions");
+ *   - each ray finds its closest hit in a triangle scene (Sec. "Scene Objects
+ *     and Meshes"; Sec. "Generating Candidates by SBR");
+ *   - at every hit it is specularly reflected (eq. path-solver-scatter-dir) and
+ *     its 2x2 complex field transfer matrix is multiplied by the Fresnel
+ *     reflection matrix of the hit material (eq. fresnel_in_vectors,
+ *     eq. fresnel_out_vectors, eq. fresnel_vac, with eta from eq. eta);
+ *   - every traced segment l = 0..L that crosses the plane adds
+ *         lambda^2 ||T C_T||^2 / (4 pi N_S |M_i| |k_z|)
+ *     to its cell i: this is the estimator eq. radio-map-solver-ci-all-2-
+ *     estimator with no diffuse reflection (interaction probability 1), where
+ *     the squared ray-tube length of the change of variables dA = r^2/|n^T k|
+ *     d(omega) cancels the spherical spreading of the path gain eq. radio-map-
+ *     solver-path-gain (Sec. "Definition of Radio Map").
+ *   - C_T is the transmit antenna pattern C = sqrt(G) F (eq. C) of a rotated
+ *     antenna (eq. rotation, eq. theta_phi_prime, eq. F_prime_2_F).
+ *
+ * Conventions shared by every call:
+ *   - SI units (metres, hertz, siemens per metre, radians).
+ *   - "device" pointers point to memory of the current HIP device (for
+ *     example torch CUDA tensors); "host" pointers point to CPU memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on `stream` unless stated otherwise; outputs are
+ *     valid after the stream is synchronised.
+ *   - Every call returns an rt_status; on failure rt_last_error() returns a
+ *     thread-local message.  No exception crosses the ABI.  Argument checks
+ *     happen on the host before any device work is queued, so a rejected call
+ *     writes no output.
+ *   - The library never takes ownership of caller memory.  Objects it creates
+ *     (rt_scene, rt_tape) are released only by their destroy calls.
+ */
+#ifndef RTMAP_RT_H
+#define RTMAP_RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RT_OK = 0,
+    RT_EINVAL = 1,        /* invalid argument (message says which)             */
+    RT_ENOMEM = 2,        /* device allocation failed                          */
+    RT_EDEVICE = 3,       /* HIP runtime error                                 */
+    RT_EOVERFLOW = 4,     /* traversal stack overflow (map not written)        */
+    RT_EUNSUPPORTED = 5   /* feature not supported by this build/device        */
+} rt_status;
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* rt_last_error(void);
+
+/* ------------------------------------------------------------------ scene */
+typedef struct rt_scene rt_scene;
+
+typedef struct {
+    int64_t n_triangles;
+    int32_t n_materials;
+    int32_t bvh_depth;        /* deepest leaf of the LBVH (root = depth 0)    */
+    int64_t n_nodes;          /* internal nodes (n_triangles - 1)             */
+    int64_t device_bytes;     /* device memory held by the scene              */
+    double build_ms;          /* device time of the last build                 */
+    float lo[3], hi[3];       /* scene bounds                                  */
+} rt_scene_info;
+
+/*
+ * rt_build_scene -- build the device-resident scene and its LBVH
+ * (Sec. "Scene Objects and Meshes": triangles with one radio material each).
+ *   vertices     device float32 [n_vertices][3]
+ *   triangles    device int32   [n_triangles][3]  vertex indices
+ *   tri_material device int32   [n_triangles]     material index in [0, n_materials)
+ * Hit ids reported by the library are indices into `triangles`.
+ * The library copies what it needs; the inputs may be freed after return.
+ * This call synchronises `stream` (it reads back validation flags).
+ * Errors: RT_EINVAL for negative sizes, NULL pointers with n > 0, vertex
+ * indices or material ids out of range, or non-finite vertex coordinates;
+ * RT_ENOMEM; RT_EDEVICE.  Zero triangles is a valid (empty) scene.
+ * Zero-area triangles are accepted and can never be hit.
+ */
+rt_status rt_build_scene(const float* vertices, int64_t n_vertices,
+                         const int32_t* triangles, int64_t n_triangles,
+                         const int32_t* tri_material, int32_t n_materials,
+                         void* stream, rt_scene** out);
+
+/* Release a scene (NULL is accepted).  Synchronises the device. */
+rt_status rt_scene_destroy(rt_scene* scene);
+
+/* Host-side description of a built scene. */
+rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
+
+/* ------------------------------------------------------- call parameters */
+/*
+ * Radio materials, device float32 arrays.  eps_r and sigma are the real
+ * relative permittivity and the conductivity of eq. eta, indexed by material
+ * (and, for batched calls, [n_samples][n_materials]).
+ */
+typedef struct {
+    const float* eps_r;
+    const float* sigma;
+} rt_materials;
+
+enum { RT_PATTERN_ISO = 0, RT_PATTERN_DIRECTIONAL = 1 };
+enum { RT_POL_V = 0, RT_POL_H = 1, RT_POL_DUAL = 2 };
+
+/*
+ * Transmitter (host struct).  Orientation R = Rz(yaw) Ry(pitch) Rx(roll)
+ * (eq. rotation).  Patterns, in local antenna coordinates:
+ *   RT_PATTERN_ISO          G = 1
+ *   RT_PATTERN_DIRECTIONAL  G(alpha) = (q+1) ((1 + cos alpha)/2)^q, alpha the
+ *                           angle to the local +x axis (integrates to 4 pi).
+ * pol: V puts C' = sqrt(G) theta_hat', H puts C' = sqrt(G) phi_hat'; DUAL
+ * computes both, into two maps.
+ */
+typedef struct {
+    double pos[3];
+    double yaw, pitch, roll;
+    int32_t pattern;
+    float pattern_q;
+    int32_t pol;
+} rt_tx;
+
+/*
+ * Horizontal measurement plane z = z, W x H cells of dx x dy starting at
+ * (x0, y0); cell (i, j) covers [x0 + i dx, x0 + (i+1) dx) x [y0 + j dy, ...)
+ * and is stored at map[j * W + i] (row-major, j along +y).  The plane does
+ * not interact with rays and is two-sided (Sec. "Radio Map Solver").
+ */
+typedef struct {
+    double z, x0, y0, dx, dy;
+    int32_t W, H;
+} rt_plane;
+
+enum { RT_ACCEL_BVH = 0, RT_ACCEL_BRUTE = 1 };
+enum { RT_DEPOSIT_AUTO = 0, RT_DEPOSIT_ATOMIC = 1, RT_DEPOSIT_WAVE = 2 };
+
+/*
+ * SBR parameters (host struct).
+ *   freq_hz     carrier frequency f (lambda = c0/f, omega = 2 pi f)
+ *   n_rays      N_S: size of the Fibonacci lattice and normaliser of the estimator
+ *   ray_begin, ray_end
+ *               lattice indices traced by this call, [ray_begin, ray_end);
+ *               ray_end <= 0 means N_S.  Disjoint sub-ranges of one lattice
+ *               add up (with accumulate = 1) to the full map.
+ *   max_depth   L: segments l = 0..L are traced (L reflections at most)
+ *   accumulate  0: the map is overwritten; 1: contributions are added to it
+ *   t_min       spawned rays accept hits at t > t_min (metres); the triangle
+ *               just hit is always excluded
+ *   accel       RT_ACCEL_BVH, or RT_ACCEL_BRUTE (every triangle is tested;
+ *               same intersection test, for validation)
+ *   deposit     plane deposit strategy: AUTO (tuned), ATOMIC (one FP32 atomic
+ *               per crossing) or WAVE (same-cell crossings of a wavefront are
+ *               summed before one atomic)
+ */
+typedef struct {
+    double freq_hz;
+    int64_t n_rays;
+    int64_t ray_begin, ray_end;
+    int32_t max_depth;
+    int32_t accumulate;
+    float t_min;
+    int32_t accel;
+    int32_t deposit;
+    int32_t block_size;   /* 0 = tuned default; else 64, 128, 256 or 512 */
+} rt_sbr_params;
+
+/*
+ * Optional per-segment records (device pointers, each may be NULL), indexed
+ * [ray - ray_begin][l] with l = 0..L:
+ *   hits     int32: id of the triangle that ends segment l, -1 if the
+ *            segment escapes, -2 if it was not traced
+ *   cells    int32: plane cell crossed by segment l (j*W + i), or -1
+ *   weights  float: weight deposited by segment l (polarisation 0), or 0
+ *   stats    uint64[5], accumulated (not reset): traced segments, plane
+ *            crossings, BVH node visits, ray-triangle tests, traversal stack
+ *            overflows (always 0: the spill area is sized from the tree depth)
+ */
+typedef struct {
+    int32_t* hits;
+    int32_t* cells;
+    float* weights;
+    unsigned long long* stats;
+} rt_records;
+
+/* --------------------------------------------------------------- forward */
+typedef struct rt_tape rt_tape;
+
+/*
+ * rt_radio_map -- the SBR radio map (estimator eq. radio-map-solver-ci-all-2-
+ * estimator, specular chains only).
+ *   out_map   device float32 [H][W] (pol V or H) or [2][H][W] (RT_POL_DUAL)
+ *   tape      NULL, or a tape from rt_tape_create for the same ray range and
+ *             depth: records what rt_radio_map_backward needs
+ *   records   NULL, or optional per-segment records (see rt_records)
+ * Errors: RT_EINVAL (bad sizes, ranges, NULL map, tape of another shape),
+ * RT_EOVERFLOW (a traversal stack overflowed; the map content is undefined),
+ * RT_EDEVICE.
+ */
+rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
+                       const rt_tx* tx, const rt_plane* plane,
+                       const rt_sbr_params* params, float* out_map,
+                       rt_tape* tape, const rt_records* records, void* stream);
+
+/* ------------------------------------------------------------------ tape */
+/*
+ * A tape holds, per traced segment, the hit index, the crossed cell, the
+ * direction and polarisation basis of the segment and the field transfer
+ * matrix T (the per-bounce checkpoint).  Library-owned device memory.
+ * rt_tape_bytes: bytes a tape for these params needs.
+ */
+size_t rt_tape_bytes(const rt_sbr_params* params);
+rt_status rt_tape_create(const rt_sbr_params* params, rt_tape** out);
+rt_status rt_tape_destroy(rt_tape* tape);
+
+/*
+ * rt_radio_map_backward -- vector-Jacobian product of the radio map.
+ * Given grad_map = dLoss/dMap (device float32, same shape as out_map), writes
+ *   grad_eps_r  device float32 [n_materials]  dLoss/d eps_r
+ *   grad_sigma  device float32 [n_materials]  dLoss/d sigma
+ *   grad_orient device float32 [3]            dLoss/d (yaw, pitch, roll)
+ * (each may be NULL; non-NULL outputs are overwritten).  It replays the tape
+ * filled by the rt_radio_map call with the same scene, materials, tx, plane
+ * and params; it traces nothing.  Derivatives follow eq. fresnel_vac,
+ * eq. eta (d eta/d eps_r = 1, d eta/d sigma = -j/(eps0 omega)) and
+ * eq. rotation.  Partial sums are reduced in a fixed order, so results are
+ * run-to-run deterministic.
+ * Errors: RT_EINVAL if the tape was not filled by a matching forward call.
+ */
+rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials materials,
+                                const rt_tx* tx, const rt_plane* plane,
+                                const rt_sbr_params* params, const rt_tape* tape,
+                                const float* grad_map, float* grad_eps_r,
+                                float* grad_sigma, float* grad_orient, void* stream);
+
+/* --------------------------------------------------------------- batched */
+/*
+ * rt_radio_map_batched -- many transmitters and/or many material samples in
+ * one call ("radio maps for multiple sources in parallel", Sec. "Radio Map
+ * Solver").
+ *   materials   device float32 [n_samples][n_materials]
+ *   txs         host [n_tx] transmitters (pol V or H; DUAL is rejected)
+ *   rays_per_tx host int64 [n_tx]: N_S of each transmitter's lattice
+ *   params      n_rays, ray_begin and ray_end are ignored
+ *   out_maps    device float32 [n_tx][n_samples][H][W]
+ *   grad_maps   NULL (forward only) or device float32 [n_tx][n_samples][H][W]
+ *               upstream gradients: the call then also returns the
+ *               vector-Jacobian products
+ *   grads       device float32 [n_tx][n_samples][2*n_materials + 3]
+ *               (eps_r[m]..., sigma[m]..., yaw, pitch, roll), overwritten,
+ *               required iff grad_maps != NULL
+ * Every ray is traced once and serves all material samples.  Work over
+ * (transmitter, ray) is scheduled from a device work counter by a persistent
+ * kernel.
+ */
+rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials materials,
+                               int32_t n_samples, const rt_tx* txs,
+                               const int64_t* rays_per_tx, int32_t n_tx,
+                               const rt_plane* plane, const rt_sbr_params* params,
+                               float* out_maps, const float* grad_maps,
+                               float* grads, void* stream);
+
+/* ------------------------------------------------------------- autotuner */
+/*
+ * rt_tune -- time the forward kernel variants (block size, deposit strategy)
+ * on this scene/tx/plane/params with `n_probe_rays` rays and remember the
+ * fastest for later calls with RT_DEPOSIT_AUTO / block_size 0 on this scene.
+ * Writes the chosen block size and deposit strategy (host ints, may be NULL).
+ * Synchronises `stream`; `scratch_map` is device float32 of the map's size
+ * and is overwritten.
+ */
+rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_tx* tx,
+                  const rt_plane* plane, const rt_sbr_params* params,
+                  int64_t n_probe_rays, float* scratch_map, void* stream,
+                  int32_t* chosen_block, int32_t* chosen_deposit);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTMAP_RT_H */

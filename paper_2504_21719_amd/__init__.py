@@ -1,0 +1,274 @@
+"""Python binding of librtmap.so, the MI355X SBR radio-map library.
+
+Argument marshalling only: every step of the SBR path runs in the HIP
+kernels behind the C ABI declared in ``include/rt.h``.  PyTorch supplies
+device memory and the current HIP stream.  The functions keep the C names
+(``rt_build_scene``, ``rt_radio_map``, ``rt_radio_map_backward``,
+``rt_radio_map_batched``, ...).
+
+There is no fallback: importing this package without the built library, or
+calling it without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtmap.so")
+
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EOVERFLOW, RT_EUNSUPPORTED = range(6)
+RT_ACCEL_BVH, RT_ACCEL_BRUTE = 0, 1
+RT_DEPOSIT_AUTO, RT_DEPOSIT_ATOMIC, RT_DEPOSIT_WAVE = 0, 1, 2
+RT_POL_V, RT_POL_H, RT_POL_DUAL = 0, 1, 2
+
+EXPORTED = ["rt_last_error", "rt_build_scene", "rt_scene_destroy", "rt_scene_info_get", "rt_radio_map",
+            "rt_tape_bytes", "rt_tape_create", "rt_tape_destroy", "rt_radio_map_backward",
+            "rt_radio_map_batched", "rt_tune"]
+
+
+class RtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("rt status %d: %s" % (status, msg))
+        self.status = status
+
+
+class rt_scene_info(C.Structure):
+    _fields_ = [("n_triangles", C.c_int64), ("n_materials", C.c_int32), ("bvh_depth", C.c_int32),
+                ("n_nodes", C.c_int64), ("device_bytes", C.c_int64), ("build_ms", C.c_double),
+                ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+
+
+class rt_materials(C.Structure):
+    _fields_ = [("eps_r", C.c_void_p), ("sigma", C.c_void_p)]
+
+
+class rt_tx(C.Structure):
+    _fields_ = [("pos", C.c_double * 3), ("yaw", C.c_double), ("pitch", C.c_double), ("roll", C.c_double),
+                ("pattern", C.c_int32), ("pattern_q", C.c_float), ("pol", C.c_int32)]
+
+
+class rt_plane(C.Structure):
+    _fields_ = [("z", C.c_double), ("x0", C.c_double), ("y0", C.c_double), ("dx", C.c_double),
+                ("dy", C.c_double), ("W", C.c_int32), ("H", C.c_int32)]
+
+
+class rt_sbr_params(C.Structure):
+    _fields_ = [("freq_hz", C.c_double), ("n_rays", C.c_int64), ("ray_begin", C.c_int64),
+                ("ray_end", C.c_int64), ("max_depth", C.c_int32), ("accumulate", C.c_int32),
+                ("t_min", C.c_float), ("accel", C.c_int32), ("deposit", C.c_int32), ("block_size", C.c_int32)]
+
+
+class rt_records(C.Structure):
+    _fields_ = [("hits", C.c_void_p), ("cells", C.c_void_p), ("weights", C.c_void_p), ("stats", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librtmap.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("librtmap.so is not built; run paper_2504_21719_amd/build.py (hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.rt_last_error.restype = C.c_char_p
+    L.rt_last_error.argtypes = []
+    L.rt_build_scene.restype = C.c_int
+    L.rt_build_scene.argtypes = [vp, i64, vp, i64, vp, i32, vp, C.POINTER(vp)]
+    L.rt_scene_destroy.restype = C.c_int
+    L.rt_scene_destroy.argtypes = [vp]
+    L.rt_scene_info_get.restype = C.c_int
+    L.rt_scene_info_get.argtypes = [vp, C.POINTER(rt_scene_info)]
+    L.rt_radio_map.restype = C.c_int
+    L.rt_radio_map.argtypes = [vp, rt_materials, C.POINTER(rt_tx), C.POINTER(rt_plane),
+                               C.POINTER(rt_sbr_params), vp, vp, C.POINTER(rt_records), vp]
+    L.rt_tape_bytes.restype = C.c_size_t
+    L.rt_tape_bytes.argtypes = [C.POINTER(rt_sbr_params)]
+    L.rt_tape_create.restype = C.c_int
+    L.rt_tape_create.argtypes = [C.POINTER(rt_sbr_params), C.POINTER(vp)]
+    L.rt_tape_destroy.restype = C.c_int
+    L.rt_tape_destroy.argtypes = [vp]
+    L.rt_radio_map_backward.restype = C.c_int
+    L.rt_radio_map_backward.argtypes = [vp, rt_materials, C.POINTER(rt_tx), C.POINTER(rt_plane),
+                                        C.POINTER(rt_sbr_params), vp, vp, vp, vp, vp, vp]
+    L.rt_radio_map_batched.restype = C.c_int
+    L.rt_radio_map_batched.argtypes = [vp, rt_materials, i32, C.POINTER(rt_tx), vp, i32,
+                                       C.POINTER(rt_plane), C.POINTER(rt_sbr_params), vp, vp, vp, vp]
+    L.rt_tune.restype = C.c_int
+    L.rt_tune.argtypes = [vp, rt_materials, C.POINTER(rt_tx), C.POINTER(rt_plane), C.POINTER(rt_sbr_params),
+                          i64, vp, vp, C.POINTER(i32), C.POINTER(i32)]
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != RT_OK:
+        raise RtError(status, lib().rt_last_error().decode(errors="replace"))
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------- structs
+def make_tx(tx) -> rt_tx:
+    t = rt_tx()
+    t.pos[:] = [float(v) for v in tx.pos]
+    t.yaw, t.pitch, t.roll = float(tx.yaw), float(tx.pitch), float(tx.roll)
+    t.pattern, t.pattern_q, t.pol = int(tx.pattern), float(tx.pattern_q), int(tx.pol)
+    return t
+
+
+def make_plane(p) -> rt_plane:
+    return rt_plane(float(p.z), float(p.x0), float(p.y0), float(p.dx), float(p.dy), int(p.W), int(p.H))
+
+
+def make_params(p, *, ray_begin=None, ray_end=None, accumulate=0, accel=RT_ACCEL_BVH,
+                deposit=RT_DEPOSIT_AUTO, block_size=0) -> rt_sbr_params:
+    rb = int(p.ray_begin if ray_begin is None else ray_begin)
+    re_ = ray_end if ray_end is not None else getattr(p, "ray_end", None)
+    re_ = 0 if re_ is None else int(re_)
+    return rt_sbr_params(float(p.freq_hz), int(p.n_rays), rb, re_, int(p.max_depth), int(accumulate),
+                         float(p.t_min), int(accel), int(deposit), int(block_size))
+
+
+# ------------------------------------------------------------------ scene
+class RtScene:
+    """Owner of an rt_scene* (device-resident triangles + LBVH)."""
+
+    def __init__(self, handle, n_materials):
+        self.handle = handle
+        self.n_materials = n_materials
+
+    def info(self) -> rt_scene_info:
+        out = rt_scene_info()
+        _check(lib().rt_scene_info_get(self.handle, C.byref(out)))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().rt_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rt_build_scene(vertices, triangles, tri_material, n_materials, stream=None) -> RtScene:
+    """vertices f32 [n_v,3], triangles i32 [n_t,3], tri_material i32 [n_t] (device tensors)."""
+    h = C.c_void_p()
+    _check(lib().rt_build_scene(_ptr(vertices), int(vertices.shape[0]), _ptr(triangles), int(triangles.shape[0]),
+                                _ptr(tri_material), int(n_materials), _stream(stream), C.byref(h)))
+    return RtScene(h, int(n_materials))
+
+
+def scene_from_mesh(scene, device="cuda") -> RtScene:
+    """Upload a mesh object (vertices, triangles, tri_material, eps_r) and build it."""
+    import torch
+    V = torch.as_tensor(scene.vertices, dtype=torch.float32).contiguous().to(device)
+    F = torch.as_tensor(scene.triangles, dtype=torch.int32).contiguous().to(device)
+    M = torch.as_tensor(scene.tri_material, dtype=torch.int32).contiguous().to(device)
+    if F.shape[0] == 0:
+        V = torch.zeros((1, 3), dtype=torch.float32, device=device)
+    return rt_build_scene(V, F, M, len(scene.eps_r))
+
+
+def materials(eps_r, sigma) -> rt_materials:
+    return rt_materials(_ptr(eps_r), _ptr(sigma))
+
+
+# ----------------------------------------------------------------- forward
+def rt_radio_map(scene: RtScene, eps_r, sigma, tx, plane, params, out_map, *, tape=None, hits=None,
+                 cells=None, weights=None, stats=None, stream=None, **pkw):
+    """Queue the SBR radio map into ``out_map`` (device f32 [H][W] or [2][H][W])."""
+    rec = rt_records(_ptr(hits), _ptr(cells), _ptr(weights), _ptr(stats))
+    p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
+    t = tx if isinstance(tx, rt_tx) else make_tx(tx)
+    pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
+    _check(lib().rt_radio_map(scene.handle, materials(eps_r, sigma), C.byref(t), C.byref(pl), C.byref(p),
+                              _ptr(out_map), tape.handle if tape is not None else None, C.byref(rec),
+                              _stream(stream)))
+    return out_map
+
+
+class RtTape:
+    def __init__(self, handle, nbytes):
+        self.handle = handle
+        self.nbytes = nbytes
+
+    def close(self):
+        if self.handle:
+            lib().rt_tape_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rt_tape_create(params, **pkw) -> RtTape:
+    p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
+    h = C.c_void_p()
+    _check(lib().rt_tape_create(C.byref(p), C.byref(h)))
+    return RtTape(h, int(lib().rt_tape_bytes(C.byref(p))))
+
+
+def rt_radio_map_backward(scene: RtScene, eps_r, sigma, tx, plane, params, tape: RtTape, grad_map,
+                          grad_eps_r=None, grad_sigma=None, grad_orient=None, stream=None, **pkw):
+    p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
+    t = tx if isinstance(tx, rt_tx) else make_tx(tx)
+    pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
+    _check(lib().rt_radio_map_backward(scene.handle, materials(eps_r, sigma), C.byref(t), C.byref(pl), C.byref(p),
+                                       tape.handle, _ptr(grad_map), _ptr(grad_eps_r), _ptr(grad_sigma),
+                                       _ptr(grad_orient), _stream(stream)))
+
+
+def rt_radio_map_batched(scene: RtScene, eps_r, sigma, txs: Sequence, rays_per_tx: Sequence[int], plane, params,
+                         out_maps, grad_maps=None, grads=None, stream=None, **pkw):
+    """eps_r/sigma: device f32 [S][n_mat]; out_maps [T][S][H][W]; grads [T][S][2 n_mat + 3]."""
+    n_tx = len(txs)
+    arr = (rt_tx * n_tx)(*[tx if isinstance(tx, rt_tx) else make_tx(tx) for tx in txs])
+    budgets = (C.c_int64 * n_tx)(*[int(b) for b in rays_per_tx])
+    p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
+    pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
+    S = int(eps_r.shape[0]) if eps_r.dim() == 2 else 1
+    _check(lib().rt_radio_map_batched(scene.handle, materials(eps_r, sigma), S, arr, C.cast(budgets, C.c_void_p),
+                                      n_tx, C.byref(pl), C.byref(p), _ptr(out_maps), _ptr(grad_maps), _ptr(grads),
+                                      _stream(stream)))
+    return out_maps
+
+
+def rt_tune(scene: RtScene, eps_r, sigma, tx, plane, params, n_probe_rays, scratch_map, stream=None, **pkw):
+    p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
+    t = tx if isinstance(tx, rt_tx) else make_tx(tx)
+    pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
+    b, d = C.c_int32(), C.c_int32()
+    _check(lib().rt_tune(scene.handle, materials(eps_r, sigma), C.byref(t), C.byref(pl), C.byref(p),
+                         int(n_probe_rays), _ptr(scratch_map), _stream(stream), C.byref(b), C.byref(d)))
+    return b.value, d.value

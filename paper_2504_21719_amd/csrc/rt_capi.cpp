@@ -1,0 +1,489 @@
+// rt_capi.cpp -- the extern "C" entry points of librtmap.so: argument
+// validation (all on the host, before any device work is queued), object
+// ownership, launch descriptors and the thread-local error channel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+void rt_set_error(const std::string& m) { g_err = m; }
+rt_status rt_fail(rt_status st, const std::string& m) {
+    g_err = m;
+    return st;
+}
+rt_status rt_hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? RT_ENOMEM : RT_EDEVICE;
+}
+
+extern "C" const char* rt_last_error(void) { return g_err.c_str(); }
+
+#define CHECK_ARG(cond, msg)                      \
+    do {                                          \
+        if (!(cond)) return rt_fail(RT_EINVAL, msg); \
+    } while (0)
+
+static bool finite_d(double v) { return std::isfinite(v); }
+
+// ------------------------------------------------------------------- scene
+extern "C" rt_status rt_build_scene(const float* vertices, int64_t n_vertices, const int32_t* triangles,
+                                    int64_t n_triangles, const int32_t* tri_material, int32_t n_materials,
+                                    void* stream, rt_scene** out) {
+    CHECK_ARG(out != nullptr, "rt_build_scene: out is NULL");
+    *out = nullptr;
+    CHECK_ARG(n_vertices >= 0 && n_triangles >= 0, "rt_build_scene: negative size");
+    CHECK_ARG(n_triangles < (int64_t)1 << 30, "rt_build_scene: more than 2^30 triangles");
+    CHECK_ARG(n_materials >= 1 && n_materials <= 65536, "rt_build_scene: n_materials must be in [1, 65536]");
+    if (n_triangles > 0) {
+        CHECK_ARG(vertices && triangles && tri_material, "rt_build_scene: NULL input pointer");
+        CHECK_ARG(n_vertices > 0, "rt_build_scene: triangles given but no vertices");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    rt_scene* s = new rt_scene();
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return rt_hip_fail(e, "hipGetDevice");
+    }
+    s->n_tri = n_triangles;
+    s->n_mat = n_materials;
+    e = hipMalloc(&s->counters, sizeof(unsigned long long) * 8);
+    if (e != hipSuccess) {
+        delete s;
+        return rt_hip_fail(e, "hipMalloc(counters)");
+    }
+    rt_status r = rt_build_lbvh(s, vertices, n_vertices, triangles, tri_material, st);
+    if (r != RT_OK) {
+        std::string m = g_err;
+        rt_scene_destroy(s);
+        return rt_fail(r, m);
+    }
+    // traversal spill: (depth + 1 - RT_STACK_LDS) entries for every lane of
+    // the largest persistent grid (a fixed number of lanes per CU)
+    int64_t need_depth = std::max<int64_t>(0, (int64_t)s->depth + 1 - RT_STACK_LDS);
+    int64_t lanes = (int64_t)rt_persistent_blocks(64, s->device) * 64;
+    s->spill_entries = (size_t)(need_depth * lanes);
+    if (s->spill_entries) {
+        e = hipMalloc(&s->spill, sizeof(int) * s->spill_entries);
+        if (e != hipSuccess) {
+            rt_scene_destroy(s);
+            return rt_hip_fail(e, "hipMalloc(spill)");
+        }
+    }
+    s->bytes += sizeof(int) * s->spill_entries + sizeof(unsigned long long) * 8;
+    *out = s;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_scene_destroy(rt_scene* s) {
+    if (!s) return RT_OK;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(s->nodes);
+    (void)hipFree(s->tris);
+    (void)hipFree(s->normals);
+    (void)hipFree(s->counters);
+    (void)hipFree(s->spill);
+    (void)hipFree(s->tx_desc);
+    if (s->tx_desc_host) (void)hipHostFree(s->tx_desc_host);
+    delete s;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_scene_info_get(const rt_scene* s, rt_scene_info* out) {
+    CHECK_ARG(s && out, "rt_scene_info_get: NULL argument");
+    out->n_triangles = s->n_tri;
+    out->n_materials = s->n_mat;
+    out->bvh_depth = s->depth;
+    out->n_nodes = std::max<int64_t>(0, s->n_tri - 1);
+    out->device_bytes = (int64_t)s->bytes;
+    out->build_ms = s->build_ms;
+    for (int a = 0; a < 3; a++) {
+        out->lo[a] = s->lo[a];
+        out->hi[a] = s->hi[a];
+    }
+    return RT_OK;
+}
+
+// ------------------------------------------------------------ descriptors
+static rt_status check_tx(const rt_tx* tx, bool allow_dual) {
+    CHECK_ARG(tx != nullptr, "tx is NULL");
+    for (int a = 0; a < 3; a++) CHECK_ARG(finite_d(tx->pos[a]), "tx position is not finite");
+    CHECK_ARG(finite_d(tx->yaw) && finite_d(tx->pitch) && finite_d(tx->roll), "tx orientation is not finite");
+    CHECK_ARG(tx->pattern == RT_PATTERN_ISO || tx->pattern == RT_PATTERN_DIRECTIONAL, "tx pattern must be 0 or 1");
+    CHECK_ARG(std::isfinite(tx->pattern_q) && tx->pattern_q >= 0.0f, "tx pattern_q must be finite and >= 0");
+    CHECK_ARG(tx->pol == RT_POL_V || tx->pol == RT_POL_H || (allow_dual && tx->pol == RT_POL_DUAL),
+              allow_dual ? "tx pol must be 0 (V), 1 (H) or 2 (dual)" : "tx pol must be 0 (V) or 1 (H) here");
+    return RT_OK;
+}
+
+static rt_status check_plane(const rt_plane* p) {
+    CHECK_ARG(p != nullptr, "plane is NULL");
+    CHECK_ARG(finite_d(p->z) && finite_d(p->x0) && finite_d(p->y0), "plane origin is not finite");
+    CHECK_ARG(finite_d(p->dx) && finite_d(p->dy) && p->dx > 0 && p->dy > 0, "plane cell size must be > 0");
+    CHECK_ARG(p->W >= 1 && p->H >= 1, "plane must have W >= 1 and H >= 1 cells");
+    CHECK_ARG((int64_t)p->W * p->H <= ((int64_t)1 << 30), "plane has more than 2^30 cells");
+    return RT_OK;
+}
+
+static rt_status check_params(const rt_sbr_params* p, int64_t* b, int64_t* e) {
+    CHECK_ARG(p != nullptr, "params is NULL");
+    CHECK_ARG(finite_d(p->freq_hz) && p->freq_hz > 0, "freq_hz must be > 0");
+    CHECK_ARG(p->n_rays >= 1 && p->n_rays <= ((int64_t)1 << 40), "n_rays must be in [1, 2^40]");
+    CHECK_ARG(p->max_depth >= 0 && p->max_depth <= 64, "max_depth must be in [0, 64]");
+    CHECK_ARG(std::isfinite(p->t_min) && p->t_min >= 0.0f, "t_min must be finite and >= 0");
+    CHECK_ARG(p->accel == RT_ACCEL_BVH || p->accel == RT_ACCEL_BRUTE, "accel must be 0 or 1");
+    CHECK_ARG(p->deposit >= RT_DEPOSIT_AUTO && p->deposit <= RT_DEPOSIT_WAVE, "deposit must be 0, 1 or 2");
+    CHECK_ARG(p->block_size == 0 || p->block_size == 64 || p->block_size == 128 || p->block_size == 256 ||
+                  p->block_size == 512,
+              "block_size must be 0, 64, 128, 256 or 512");
+    CHECK_ARG(p->accumulate == 0 || p->accumulate == 1, "accumulate must be 0 or 1");
+    int64_t begin = p->ray_begin, end = p->ray_end <= 0 ? p->n_rays : p->ray_end;
+    CHECK_ARG(begin >= 0 && begin <= end && end <= p->n_rays, "ray range must satisfy 0 <= begin <= end <= n_rays");
+    *b = begin;
+    *e = end;
+    return RT_OK;
+}
+
+static void fill_plane(const rt_plane* p, double freq, PlaneDesc* d) {
+    d->z = (float)p->z;
+    d->x0 = (float)p->x0;
+    d->y0 = (float)p->y0;
+    d->inv_dx = (float)(1.0 / p->dx);
+    d->inv_dy = (float)(1.0 / p->dy);
+    d->W = p->W;
+    d->H = p->H;
+    d->inv_eps0_omega = (float)(1.0 / (RT_EPS0 * 2.0 * RT_PI * freq));
+}
+
+static void fill_tx(const rt_tx* t, int64_t n_rays, const rt_plane* p, double freq, TxDesc* d) {
+    for (int a = 0; a < 3; a++) d->pos[a] = (float)t->pos[a];
+    d->pattern = t->pattern;
+    d->q = t->pattern_q;
+    d->pol = t->pol;
+    d->yaw = t->yaw;
+    d->pitch = t->pitch;
+    d->roll = t->roll;
+    double ca = cos(t->yaw), sa = sin(t->yaw), cb = cos(t->pitch), sb = sin(t->pitch), cg = cos(t->roll),
+           sg = sin(t->roll);
+    double R[9] = {ca * cb, ca * sb * sg - sa * cg, ca * sb * cg + sa * sg,
+                   sa * cb, sa * sb * sg + ca * cg, sa * sb * cg - ca * sg,
+                   -sb,     cb * sg,                cb * cg};
+    for (int i = 0; i < 9; i++) d->R[i] = R[i];
+    d->n_rays = n_rays;
+    double lam = RT_C0 / freq;
+    d->kappa = (float)(lam * lam / (4.0 * RT_PI * (double)n_rays * p->dx * p->dy));
+    d->pad = 0;
+}
+
+static uint64_t mix(uint64_t h, const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; i++) h = (h ^ c[i]) * 1099511628211ull;   // FNV-1a
+    return h;
+}
+
+static uint64_t call_key(const rt_scene* s, rt_materials m, const rt_tx* tx, const rt_plane* pl,
+                         const rt_sbr_params* p, int64_t b, int64_t e) {
+    uint64_t h = 1469598103934665603ull;
+    h = mix(h, &s, sizeof(s));
+    h = mix(h, &m.eps_r, sizeof(m.eps_r));
+    h = mix(h, &m.sigma, sizeof(m.sigma));
+    h = mix(h, tx, sizeof(rt_tx));
+    h = mix(h, pl, sizeof(rt_plane));
+    h = mix(h, &p->freq_hz, sizeof(double));
+    h = mix(h, &p->n_rays, sizeof(int64_t));
+    h = mix(h, &b, sizeof(b));
+    h = mix(h, &e, sizeof(e));
+    h = mix(h, &p->max_depth, sizeof(int32_t));
+    h = mix(h, &p->t_min, sizeof(float));
+    return h;
+}
+
+static int pick_block(const rt_scene* s, const rt_sbr_params* p) {
+    if (p->block_size) return p->block_size;
+    if (s->tuned_block) return s->tuned_block;
+    return 256;
+}
+
+static int pick_deposit(const rt_scene* s, const rt_sbr_params* p) {
+    if (p->deposit) return p->deposit;
+    if (s->tuned_deposit) return s->tuned_deposit;
+    return RT_DEPOSIT_ATOMIC;
+}
+
+static rt_status check_device(const rt_scene* s) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return rt_hip_fail(e, "hipGetDevice");
+    CHECK_ARG(dev == s->device, "the current device is not the scene's device");
+    return RT_OK;
+}
+
+// ----------------------------------------------------------------- forward
+extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials, const rt_tx* tx,
+                                  const rt_plane* plane, const rt_sbr_params* params, float* out_map,
+                                  rt_tape* tape, const rt_records* records, void* stream) {
+    CHECK_ARG(scene != nullptr, "rt_radio_map: scene is NULL");
+    CHECK_ARG(out_map != nullptr, "rt_radio_map: out_map is NULL");
+    CHECK_ARG(materials.eps_r && materials.sigma, "rt_radio_map: material pointers are NULL");
+    rt_status r;
+    if ((r = check_tx(tx, true)) != RT_OK) return r;
+    if ((r = check_plane(plane)) != RT_OK) return r;
+    int64_t b, e;
+    if ((r = check_params(params, &b, &e)) != RT_OK) return r;
+    if (tape) {
+        CHECK_ARG(tape->n_rays == e - b && tape->max_depth == params->max_depth,
+                  "rt_radio_map: tape was created for another ray range or depth");
+    }
+    if ((r = check_device(scene)) != RT_OK) return r;
+    FwdLaunch f{};
+    f.scene = scene;
+    f.eps_r = materials.eps_r;
+    f.sigma = materials.sigma;
+    fill_tx(tx, params->n_rays, plane, params->freq_hz, &f.tx);
+    fill_plane(plane, params->freq_hz, &f.pl);
+    f.ray_begin = b;
+    f.ray_end = e;
+    f.L = params->max_depth;
+    f.t_min = params->t_min;
+    f.accel = params->accel;
+    f.deposit = pick_deposit(scene, params);
+    f.block = pick_block(scene, params);
+    f.zero_map = params->accumulate == 0;
+    f.map = out_map;
+    f.tape = tape;
+    if (records) {
+        f.hits = records->hits;
+        f.cells = records->cells;
+        f.weights = records->weights;
+        f.stats = records->stats;
+    }
+    r = rt_launch_forward(f, (hipStream_t)stream);
+    if (r != RT_OK) return r;
+    if (tape) {
+        tape->key = call_key(scene, materials, tx, plane, params, b, e);
+        tape->filled = true;
+    }
+    return RT_OK;
+}
+
+// -------------------------------------------------------------------- tape
+extern "C" size_t rt_tape_bytes(const rt_sbr_params* p) {
+    if (!p) return 0;
+    int64_t b, e;
+    if (check_params(p, &b, &e) != RT_OK) return 0;
+    size_t n = (size_t)(e - b);
+    return n * (size_t)(p->max_depth + 1) * 4 * sizeof(float4) + n * sizeof(int);
+}
+
+extern "C" rt_status rt_tape_create(const rt_sbr_params* p, rt_tape** out) {
+    CHECK_ARG(out != nullptr, "rt_tape_create: out is NULL");
+    *out = nullptr;
+    int64_t b, e;
+    rt_status r = check_params(p, &b, &e);
+    if (r != RT_OK) return r;
+    rt_tape* t = new rt_tape();
+    t->n_rays = e - b;
+    t->max_depth = p->max_depth;
+    size_t segb = (size_t)t->n_rays * (size_t)(p->max_depth + 1) * 4 * sizeof(float4);
+    hipError_t he = hipMalloc(&t->seg, std::max<size_t>(16, segb));
+    if (he == hipSuccess) he = hipMalloc(&t->nseg, std::max<size_t>(4, sizeof(int) * (size_t)t->n_rays));
+    if (he != hipSuccess) {
+        rt_tape_destroy(t);
+        return rt_hip_fail(he, "rt_tape_create: hipMalloc");
+    }
+    t->bytes = segb + sizeof(int) * (size_t)t->n_rays;
+    *out = t;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_tape_destroy(rt_tape* t) {
+    if (!t) return RT_OK;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(t->seg);
+    (void)hipFree(t->nseg);
+    delete t;
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------- backward
+extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials materials, const rt_tx* tx,
+                                           const rt_plane* plane, const rt_sbr_params* params,
+                                           const rt_tape* tape, const float* grad_map, float* grad_eps_r,
+                                           float* grad_sigma, float* grad_orient, void* stream) {
+    CHECK_ARG(scene != nullptr, "rt_radio_map_backward: scene is NULL");
+    CHECK_ARG(tape != nullptr, "rt_radio_map_backward: tape is NULL");
+    CHECK_ARG(grad_map != nullptr, "rt_radio_map_backward: grad_map is NULL");
+    CHECK_ARG(materials.eps_r && materials.sigma, "rt_radio_map_backward: material pointers are NULL");
+    rt_status r;
+    if ((r = check_tx(tx, true)) != RT_OK) return r;
+    if ((r = check_plane(plane)) != RT_OK) return r;
+    int64_t b, e;
+    if ((r = check_params(params, &b, &e)) != RT_OK) return r;
+    CHECK_ARG(tape->filled && tape->key == call_key(scene, materials, tx, plane, params, b, e),
+              "rt_radio_map_backward: the tape was not filled by a forward call with these arguments");
+    if ((r = check_device(scene)) != RT_OK) return r;
+    BwdLaunch bl{};
+    bl.scene = scene;
+    bl.eps_r = materials.eps_r;
+    bl.sigma = materials.sigma;
+    fill_tx(tx, params->n_rays, plane, params->freq_hz, &bl.tx);
+    fill_plane(plane, params->freq_hz, &bl.pl);
+    bl.ray_begin = b;
+    bl.ray_end = e;
+    bl.L = params->max_depth;
+    bl.tape = tape;
+    bl.grad_map = grad_map;
+    bl.grad_eps = grad_eps_r;
+    bl.grad_sigma = grad_sigma;
+    bl.grad_orient = grad_orient;
+    return rt_launch_backward(bl, (hipStream_t)stream);
+}
+
+// ----------------------------------------------------------------- batched
+extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials materials, int32_t n_samples,
+                                          const rt_tx* txs, const int64_t* rays_per_tx, int32_t n_tx,
+                                          const rt_plane* plane, const rt_sbr_params* params, float* out_maps,
+                                          const float* grad_maps, float* grads, void* stream) {
+    CHECK_ARG(scene != nullptr, "rt_radio_map_batched: scene is NULL");
+    CHECK_ARG(out_maps != nullptr, "rt_radio_map_batched: out_maps is NULL");
+    CHECK_ARG(materials.eps_r && materials.sigma, "rt_radio_map_batched: material pointers are NULL");
+    CHECK_ARG(n_samples >= 1 && n_samples <= 64, "rt_radio_map_batched: n_samples must be in [1, 64]");
+    CHECK_ARG(n_tx >= 1 && n_tx <= 4096, "rt_radio_map_batched: n_tx must be in [1, 4096]");
+    CHECK_ARG(txs && rays_per_tx, "rt_radio_map_batched: txs / rays_per_tx are NULL");
+    CHECK_ARG((grad_maps == nullptr) == (grads == nullptr),
+              "rt_radio_map_batched: grad_maps and grads must both be given or both be NULL");
+    rt_status r;
+    for (int i = 0; i < n_tx; i++) {
+        if ((r = check_tx(&txs[i], false)) != RT_OK) return r;
+        CHECK_ARG(rays_per_tx[i] >= 1 && rays_per_tx[i] <= ((int64_t)1 << 40),
+                  "rt_radio_map_batched: rays_per_tx must be in [1, 2^40]");
+    }
+    if ((r = check_plane(plane)) != RT_OK) return r;
+    int64_t b, e;
+    rt_sbr_params p = *params;
+    p.n_rays = 1;
+    p.ray_begin = 0;
+    p.ray_end = 0;
+    if ((r = check_params(&p, &b, &e)) != RT_OK) return r;
+    if ((r = check_device(scene)) != RT_OK) return r;
+    rt_scene* s = const_cast<rt_scene*>(scene);
+    // order transmitters largest budget first so that the long lattices start early
+    std::vector<int> order(n_tx);
+    for (int i = 0; i < n_tx; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rays_per_tx[x] > rays_per_tx[y]; });
+    size_t need = sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1) + sizeof(int32_t) * n_tx + 256;
+    if (s->tx_desc_bytes < need) {
+        hipStream_t hs = (hipStream_t)stream;
+        (void)hipStreamSynchronize(hs);
+        (void)hipFree(s->tx_desc);
+        if (s->tx_desc_host) (void)hipHostFree(s->tx_desc_host);
+        s->tx_desc = nullptr;
+        s->tx_desc_host = nullptr;
+        s->tx_desc_bytes = 0;
+        hipError_t he = hipMalloc(&s->tx_desc, need);
+        if (he == hipSuccess) he = hipHostMalloc(&s->tx_desc_host, need, hipHostMallocDefault);
+        if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: staging allocation");
+        s->tx_desc_bytes = need;
+    } else {
+        // the pinned staging buffer may still be read by a previous call's copy
+        (void)hipStreamSynchronize((hipStream_t)stream);
+    }
+    char* hb = (char*)s->tx_desc_host;
+    TxDesc* hd = (TxDesc*)hb;
+    int64_t* hp = (int64_t*)(hb + sizeof(TxDesc) * n_tx);
+    int32_t* hslot = (int32_t*)(hb + sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1));
+    int64_t total = 0;
+    for (int i = 0; i < n_tx; i++) {
+        int t = order[i];
+        fill_tx(&txs[t], rays_per_tx[t], plane, params->freq_hz, &hd[i]);
+        hp[i] = total;
+        hslot[i] = t;
+        total += rays_per_tx[t];
+    }
+    hp[n_tx] = total;
+    hipError_t he = hipMemcpyAsync(s->tx_desc, hb, need, hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: descriptor upload");
+    char* db = (char*)s->tx_desc;
+    BatchLaunch bl{};
+    bl.scene = scene;
+    bl.eps_r = materials.eps_r;
+    bl.sigma = materials.sigma;
+    bl.n_samples = n_samples;
+    bl.n_tx = n_tx;
+    bl.tx_dev = (const TxDesc*)db;
+    bl.prefix_dev = (const int64_t*)(db + sizeof(TxDesc) * n_tx);
+    bl.tx_slot_dev = (const int32_t*)(db + sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1));
+    bl.total_rays = total;
+    fill_plane(plane, params->freq_hz, &bl.pl);
+    bl.L = params->max_depth;
+    bl.t_min = params->t_min;
+    bl.block = pick_block(scene, params);
+    bl.maps = out_maps;
+    bl.grad_maps = grad_maps;
+    bl.grads = grads;
+    return rt_launch_batched(bl, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------- autotune
+extern "C" rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_tx* tx, const rt_plane* plane,
+                             const rt_sbr_params* params, int64_t n_probe_rays, float* scratch_map,
+                             void* stream, int32_t* chosen_block, int32_t* chosen_deposit) {
+    CHECK_ARG(scene != nullptr && scratch_map != nullptr, "rt_tune: NULL argument");
+    CHECK_ARG(n_probe_rays >= 1, "rt_tune: n_probe_rays must be >= 1");
+    rt_sbr_params p = *params;
+    p.ray_begin = 0;
+    p.ray_end = std::min<int64_t>(n_probe_rays, params->n_rays);
+    p.accumulate = 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) return rt_hip_fail(he, "rt_tune: hipEventCreate");
+    const int blocks[] = {64, 128, 256, 512};
+    const int deps[] = {RT_DEPOSIT_ATOMIC, RT_DEPOSIT_WAVE};
+    float best = 1e30f;
+    int bb = 256, bd = RT_DEPOSIT_ATOMIC;
+    rt_status r = RT_OK;
+    for (int bi : blocks) {
+        for (int di : deps) {
+            p.block_size = bi;
+            p.deposit = di;
+            // one warm-up, then the median of three timed runs
+            r = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
+            if (r != RT_OK) break;
+            float ts[3];
+            for (int rep = 0; rep < 3 && r == RT_OK; rep++) {
+                (void)hipEventRecord(e0, st);
+                r = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
+                (void)hipEventRecord(e1, st);
+                (void)hipEventSynchronize(e1);
+                (void)hipEventElapsedTime(&ts[rep], e0, e1);
+            }
+            if (r != RT_OK) break;
+            std::sort(ts, ts + 3);
+            if (ts[1] < best) {
+                best = ts[1];
+                bb = bi;
+                bd = di;
+            }
+        }
+        if (r != RT_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != RT_OK) return r;
+    scene->tuned_block = bb;
+    scene->tuned_deposit = bd;
+    if (chosen_block) *chosen_block = bb;
+    if (chosen_deposit) *chosen_deposit = bd;
+    return RT_OK;
+}

@@ -1,0 +1,163 @@
+// rt_internal.h -- library-internal types shared by the host ABI layer and the
+// kernel launchers.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/rt.h"
+
+// Physical constants (SI).  The paper prints none of them; these are the
+// exact speed of light and the CODATA 2018 vacuum permittivity.
+#define RT_C0 299792458.0
+#define RT_EPS0 8.8541878128e-12
+#define RT_PI 3.14159265358979323846
+
+// Traversal stack: RT_STACK_LDS entries per lane live in LDS; deeper entries
+// spill to a per-lane global buffer sized from the BVH depth.
+#define RT_STACK_LDS 16
+
+// LBVH layout.  Internal node = 4 x float4 (64 B, one cache line):
+//   q0 = (L.lo.x, L.hi.x, L.lo.y, L.hi.y)
+//   q1 = (R.lo.x, R.hi.x, R.lo.y, R.hi.y)
+//   q2 = (L.lo.z, L.hi.z, R.lo.z, R.hi.z)
+//   q3 = (left ref, right ref, -, -)   (int bits)
+// A child reference r >= 0 is an internal node; r < 0 is the leaf holding
+// triangle slot ~r.  Triangles are stored in Morton order ("slots"):
+//   tris[3 s + 0] = (v0.xyz, original id bits)
+//   tris[3 s + 1] = (v1.xyz, material bits)
+//   tris[3 s + 2] = (v2.xyz, 0)
+//   normals[s]    = (unit geometric normal, material bits)
+struct rt_scene {
+    int device = 0;
+    int64_t n_tri = 0;
+    int32_t n_mat = 0;
+    int32_t depth = 0;        // deepest leaf depth (root = 0)
+    int32_t root = -1;        // child reference of the root (unused if n_tri == 0)
+    float4* nodes = nullptr;
+    float4* tris = nullptr;
+    float4* normals = nullptr;
+    size_t bytes = 0;
+    double build_ms = 0.0;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    // per-scene workspace: [0] work counter, [1] overflow flag, [2..] spare
+    unsigned long long* counters = nullptr;
+    int* spill = nullptr;     // traversal stack spill
+    size_t spill_entries = 0; // ints available in `spill`
+    // autotuned launch configuration (0 = not tuned)
+    int tuned_block = 0;
+    int tuned_deposit = 0;
+    // batched-call staging (device copies of per-transmitter descriptors)
+    void* tx_desc = nullptr;
+    size_t tx_desc_bytes = 0;
+    void* tx_desc_host = nullptr;  // pinned host staging
+};
+
+// Tape: per segment (l, ray) four float4 records, stored [l][g][ray] for
+// coalesced access:
+//   g = 0: (k.xyz, hit slot bits or -1)
+//   g = 1: (e_s.xyz, crossed cell bits or -1)
+//   g = 2: (T.a, T.b)   complex re/im
+//   g = 3: (T.c, T.d)
+// plus one int per ray: number of traced segments.
+struct rt_tape {
+    int64_t n_rays = 0;       // rays in the range the tape was created for
+    int32_t max_depth = 0;
+    float4* seg = nullptr;
+    int* nseg = nullptr;
+    size_t bytes = 0;
+    // identity of the forward call that filled it
+    uint64_t key = 0;
+    bool filled = false;
+};
+
+// Per-transmitter launch descriptor (host-computed constants).
+struct TxDesc {
+    float pos[3];
+    int32_t pattern;         // 0 iso, 1 directional
+    double R[9];             // rotation matrix, row-major
+    double yaw, pitch, roll;
+    float q;
+    int32_t pol;             // 0 V, 1 H, 2 dual
+    int64_t n_rays;          // N_S of this transmitter's lattice
+    float kappa;             // lambda^2 / (4 pi N_S dx dy)
+    int32_t pad;
+};
+
+// Plane + physics constants for one call.
+struct PlaneDesc {
+    float z, x0, y0, inv_dx, inv_dy;
+    int32_t W, H;
+    float inv_eps0_omega;    // 1 / (eps0 omega): sigma -> Im(eta) scale
+};
+
+// Error channel (thread-local message).
+void rt_set_error(const std::string& msg);
+rt_status rt_fail(rt_status st, const std::string& msg);
+rt_status rt_hip_fail(hipError_t e, const char* what);
+
+// Builders and launchers (device code lives in the .hip files).
+rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t* F,
+                        const int32_t* M, hipStream_t st);
+
+struct FwdLaunch {
+    const rt_scene* scene;
+    const float* eps_r;
+    const float* sigma;
+    TxDesc tx;
+    PlaneDesc pl;
+    int64_t ray_begin, ray_end;
+    int32_t L;
+    float t_min;
+    int accel;               // 0 BVH, 1 brute force
+    int deposit;             // 1 atomic, 2 wave
+    int block;
+    bool zero_map;
+    float* map;
+    rt_tape* tape;
+    int32_t* hits;
+    int32_t* cells;
+    float* weights;
+    unsigned long long* stats;
+};
+rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st);
+
+struct BwdLaunch {
+    const rt_scene* scene;
+    const float* eps_r;
+    const float* sigma;
+    TxDesc tx;
+    PlaneDesc pl;
+    int64_t ray_begin, ray_end;
+    int32_t L;
+    const rt_tape* tape;
+    const float* grad_map;
+    float* grad_eps;
+    float* grad_sigma;
+    float* grad_orient;
+};
+rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st);
+
+struct BatchLaunch {
+    const rt_scene* scene;
+    const float* eps_r;      // [S][n_mat]
+    const float* sigma;
+    int32_t n_samples;
+    int32_t n_tx;
+    const TxDesc* tx_dev;    // device [n_tx], ordered largest budget first
+    const int64_t* prefix_dev;  // device [n_tx + 1] exclusive prefix of budgets
+    const int32_t* tx_slot_dev; // device [n_tx]: output slot of ordered tx
+    int64_t total_rays;
+    PlaneDesc pl;
+    int32_t L;
+    float t_min;
+    int block;
+    float* maps;             // [n_tx][S][H][W]
+    const float* grad_maps;  // [n_tx][S][H][W] or null
+    float* grads;            // [n_tx][S][2 n_mat + 3] or null
+};
+rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st);
+
+int rt_persistent_blocks(int block, int device);

@@ -1,0 +1,315 @@
+// sbr_common.h -- device building blocks of the SBR path (gfx950).
+//
+//   * Fibonacci ray generation with an exact 64-bit fixed-point phase
+//     (Sec. "Sampling Initial Ray Directions")
+//   * transmit field C_T in the launch basis (theta_hat, phi_hat) of a rotated
+//     antenna (eq. rotation, eq. theta_phi_prime, eq. F_prime_2_F, eq. C),
+//     templated on the scalar so that the adjoint can run it on dual numbers
+//   * watertight ray/triangle test (Woop, Benthin and Wald, JCGT 2013)
+//   * two-child slab test with a conservative upper bound
+//   * vacuum Fresnel coefficients (eq. fresnel_vac) and their eta-derivatives
+//   * the basis change W of eq. fresnel_in_vectors / eq. fresnel_out_vectors
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "rt_device.h"
+#include "rt_internal.h"
+
+namespace rtd {
+
+// round(2^64 (phi_g - 1)): frac(n / phi_g) = frac(n (phi_g - 1)) = (n * C mod 2^64) / 2^64
+constexpr uint64_t kPhiFrac = 0x9e3779b97f4a7c16ull;
+
+// ---------------------------------------------------------------- duals
+// Forward-mode scalar carrying d/d(yaw, pitch, roll).
+struct dual3 {
+    double v, d0, d1, d2;
+};
+__device__ __forceinline__ dual3 mkd(double v) { return dual3{v, 0.0, 0.0, 0.0}; }
+__device__ __forceinline__ dual3 operator+(dual3 a, dual3 b) { return dual3{a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2}; }
+__device__ __forceinline__ dual3 operator-(dual3 a, dual3 b) { return dual3{a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2}; }
+__device__ __forceinline__ dual3 operator-(dual3 a) { return dual3{-a.v, -a.d0, -a.d1, -a.d2}; }
+__device__ __forceinline__ dual3 operator*(dual3 a, dual3 b) {
+    return dual3{a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1, a.d2 * b.v + a.v * b.d2};
+}
+__device__ __forceinline__ dual3 chain(dual3 a, double f, double fp) { return dual3{f, fp * a.d0, fp * a.d1, fp * a.d2}; }
+__device__ __forceinline__ dual3 dsin(dual3 a) { return chain(a, sin(a.v), cos(a.v)); }
+__device__ __forceinline__ dual3 dcos(dual3 a) { return chain(a, cos(a.v), -sin(a.v)); }
+__device__ __forceinline__ dual3 dsqrt(dual3 a) {
+    double s = sqrt(fmax(a.v, 0.0));
+    return chain(a, s, s > 0.0 ? 0.5 / s : 0.0);
+}
+__device__ __forceinline__ dual3 dpow(dual3 a, double p) {
+    double f = pow(a.v, p);
+    return chain(a, f, a.v > 0.0 ? p * pow(a.v, p - 1.0) : 0.0);
+}
+__device__ __forceinline__ dual3 datan2(dual3 y, dual3 x) {
+    double q = x.v * x.v + y.v * y.v;
+    double s = q > 0.0 ? 1.0 / q : 0.0;
+    return dual3{atan2(y.v, x.v), (x.v * y.d0 - y.v * x.d0) * s, (x.v * y.d1 - y.v * x.d1) * s,
+                 (x.v * y.d2 - y.v * x.d2) * s};
+}
+__device__ __forceinline__ dual3 dacos(dual3 a) {
+    double c = fmin(1.0, fmax(-1.0, a.v));
+    double s = sqrt(fmax(0.0, 1.0 - c * c));
+    return chain(a, acos(c), s > 0.0 ? -1.0 / s : 0.0);
+}
+// plain-double overloads with the same names
+__device__ __forceinline__ double mkd_d(double v) { return v; }
+__device__ __forceinline__ double dsin(double a) { return sin(a); }
+__device__ __forceinline__ double dcos(double a) { return cos(a); }
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(fmax(a, 0.0)); }
+__device__ __forceinline__ double dpow(double a, double p) { return pow(a, p); }
+__device__ __forceinline__ double datan2(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ double dacos(double a) { return acos(fmin(1.0, fmax(-1.0, a))); }
+
+template <typename S>
+__device__ __forceinline__ S scal(double v);
+template <>
+__device__ __forceinline__ double scal<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ dual3 scal<dual3>(double v) { return mkd(v); }
+
+// ------------------------------------------------------------ ray launch
+struct Launch {
+    double kx, ky, kz;      // direction
+    double tx, ty, tz;      // theta_hat (launch polarisation basis, e_s)
+    double px, py;          // phi_hat = (px, py, 0)
+};
+
+// Lattice point n of an N-point spherical Fibonacci lattice, in FP64.
+__device__ __forceinline__ Launch fib_launch(int64_t n, int64_t N) {
+    double z, ph;
+    if (N == 1) {
+        z = 0.0;
+        ph = RT_PI;
+    } else {
+        z = 1.0 - 2.0 * (double)n / (double)(N - 1);
+        uint64_t f = (uint64_t)n * kPhiFrac;                 // wraps mod 2^64
+        ph = 2.0 * RT_PI * ((double)(f >> 11) * 0x1.0p-53);
+    }
+    double st = sqrt(fmax(0.0, (1.0 - z) * (1.0 + z)));
+    double sp, cp;
+    sincos(ph, &sp, &cp);
+    Launch L;
+    L.kx = st * cp;
+    L.ky = st * sp;
+    L.kz = z;
+    L.tx = z * cp;
+    L.ty = z * sp;
+    L.tz = -st;
+    L.px = -sp;
+    L.py = cp;
+    return L;
+}
+
+// Transmit pattern components (C_theta, C_phi) in the launch basis for one
+// polarisation (pol_index 0: C' = sqrt(G) theta_hat', 1: sqrt(G) phi_hat').
+// The local direction is u = R^T k; the local field is rotated back by R and
+// projected on (theta_hat, phi_hat) of k, which is eq. F_prime_2_F.
+template <typename S>
+__device__ __forceinline__ void tx_pattern(const Launch& L, S yaw, S pitch, S roll, int pattern, double q,
+                                           int pol_index, S& c_theta, S& c_phi) {
+    S ca = dcos(yaw), sa = dsin(yaw), cb = dcos(pitch), sb = dsin(pitch), cg = dcos(roll), sg = dsin(roll);
+    // R = Rz(yaw) Ry(pitch) Rx(roll), eq. rotation, multiplied out
+    S R00 = ca * cb, R01 = ca * sb * sg - sa * cg, R02 = ca * sb * cg + sa * sg;
+    S R10 = sa * cb, R11 = sa * sb * sg + ca * cg, R12 = sa * sb * cg - ca * sg;
+    S R20 = -sb, R21 = cb * sg, R22 = cb * cg;
+    S kx = scal<S>(L.kx), ky = scal<S>(L.ky), kz = scal<S>(L.kz);
+    S ux = R00 * kx + R10 * ky + R20 * kz;
+    S uy = R01 * kx + R11 * ky + R21 * kz;
+    S uz = R02 * kx + R12 * ky + R22 * kz;
+    S th = dacos(uz), ph = datan2(uy, ux);
+    S ct = dcos(th), st = dsin(th), cp = dcos(ph), sp = dsin(ph);
+    S amp = scal<S>(1.0);
+    if (pattern == 1) amp = dsqrt(scal<S>(q + 1.0) * dpow((scal<S>(1.0) + ux) * scal<S>(0.5), q));
+    S fx, fy, fz;
+    if (pol_index == 0) {
+        fx = amp * ct * cp;
+        fy = amp * ct * sp;
+        fz = -(amp * st);
+    } else {
+        fx = -(amp * sp);
+        fy = amp * cp;
+        fz = scal<S>(0.0);
+    }
+    S gx = R00 * fx + R01 * fy + R02 * fz;
+    S gy = R10 * fx + R11 * fy + R12 * fz;
+    S gz = R20 * fx + R21 * fy + R22 * fz;
+    c_theta = scal<S>(L.tx) * gx + scal<S>(L.ty) * gy + scal<S>(L.tz) * gz;
+    c_phi = scal<S>(L.px) * gx + scal<S>(L.py) * gy;
+}
+
+// ------------------------------------------------------------ geometry
+struct Ray {
+    float ox, oy, oz;
+    float dx, dy, dz;
+    float ix, iy, iz;          // guarded reciprocal direction (slab test)
+    float sx, sy, sz;          // watertight shear constants
+    int kx, ky, kz;            // watertight axis permutation
+};
+
+__device__ __forceinline__ float pick(float a, float b, float c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
+
+__device__ __forceinline__ float safe_inv(float d) {
+    float a = fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d;
+    return 1.0f / a;
+}
+
+__device__ __forceinline__ void ray_setup(Ray& r) {
+    float ax = fabsf(r.dx), ay = fabsf(r.dy), az = fabsf(r.dz);
+    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    float dkz = pick(r.dx, r.dy, r.dz, kz);
+    if (dkz < 0.0f) {
+        int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.sx = pick(r.dx, r.dy, r.dz, kx) / dkz;
+    r.sy = pick(r.dx, r.dy, r.dz, ky) / dkz;
+    r.sz = 1.0f / dkz;
+    r.ix = safe_inv(r.dx);
+    r.iy = safe_inv(r.dy);
+    r.iz = safe_inv(r.dz);
+}
+
+// Watertight ray/triangle test.  Returns t (> t_min) or a negative value.
+// Edge cases where a scaled barycentric is exactly zero are recomputed in
+// FP64, which is what makes shared edges watertight.
+__device__ __forceinline__ float tri_hit(const Ray& r, float4 a, float4 b, float4 c, float t_min) {
+#pragma clang fp contract(off)
+    float Ax0 = a.x - r.ox, Ay0 = a.y - r.oy, Az0 = a.z - r.oz;
+    float Bx0 = b.x - r.ox, By0 = b.y - r.oy, Bz0 = b.z - r.oz;
+    float Cx0 = c.x - r.ox, Cy0 = c.y - r.oy, Cz0 = c.z - r.oz;
+    float Ak = pick(Ax0, Ay0, Az0, r.kz), Bk = pick(Bx0, By0, Bz0, r.kz), Ck = pick(Cx0, Cy0, Cz0, r.kz);
+    float Ax = pick(Ax0, Ay0, Az0, r.kx) - r.sx * Ak;
+    float Ay = pick(Ax0, Ay0, Az0, r.ky) - r.sy * Ak;
+    float Bx = pick(Bx0, By0, Bz0, r.kx) - r.sx * Bk;
+    float By = pick(Bx0, By0, Bz0, r.ky) - r.sy * Bk;
+    float Cx = pick(Cx0, Cy0, Cz0, r.kx) - r.sx * Ck;
+    float Cy = pick(Cx0, Cy0, Cz0, r.ky) - r.sy * Ck;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return -1.0f;
+    float det = U + V + W;
+    if (det == 0.0f) return -1.0f;
+    float Az = r.sz * Ak, Bz = r.sz * Bk, Cz = r.sz * Ck;
+    float T = U * Az + V * Bz + W * Cz;
+    float t = T / det;
+    return t > t_min ? t : -1.0f;
+}
+
+// Relative slack of the slab test, above the rounding of the slab distances
+// and of the triangle distance, so that a box is never culled while a
+// triangle inside it can still win.
+constexpr float kBoxSlack = 1.0f + 1e-5f;
+
+// Slab test of the two children of a node.  lo/hi layout as in rt_internal.h.
+__device__ __forceinline__ void box2(const Ray& r, float4 q0, float4 q1, float4 q2, float tmin, float tmax,
+                                     bool& hitL, bool& hitR, float& tL, float& tR) {
+    float lx0 = (q0.x - r.ox) * r.ix, lx1 = (q0.y - r.ox) * r.ix;
+    float ly0 = (q0.z - r.oy) * r.iy, ly1 = (q0.w - r.oy) * r.iy;
+    float lz0 = (q2.x - r.oz) * r.iz, lz1 = (q2.y - r.oz) * r.iz;
+    float rx0 = (q1.x - r.ox) * r.ix, rx1 = (q1.y - r.ox) * r.ix;
+    float ry0 = (q1.z - r.oy) * r.iy, ry1 = (q1.w - r.oy) * r.iy;
+    float rz0 = (q2.z - r.oz) * r.iz, rz1 = (q2.w - r.oz) * r.iz;
+    float aL = fmaxf(fmaxf(fminf(lx0, lx1), fminf(ly0, ly1)), fmaxf(fminf(lz0, lz1), tmin));
+    float bL = fminf(fminf(fmaxf(lx0, lx1), fmaxf(ly0, ly1)), fmaxf(lz0, lz1)) * kBoxSlack;
+    float aR = fmaxf(fmaxf(fminf(rx0, rx1), fminf(ry0, ry1)), fmaxf(fminf(rz0, rz1), tmin));
+    float bR = fminf(fminf(fmaxf(rx0, rx1), fmaxf(ry0, ry1)), fmaxf(rz0, rz1)) * kBoxSlack;
+    hitL = aL <= fminf(bL, tmax);
+    hitR = aR <= fminf(bR, tmax);
+    tL = aL;
+    tR = aR;
+}
+
+// ------------------------------------------------------------ Fresnel
+struct Fresnel {
+    cf rperp, rpar;       // eq. fresnel_vac
+    cf drperp, drpar;     // d/d eta
+};
+
+// c = cos(theta_1) >= 0, eta = eps_r - j sigma/(eps0 omega)  (eq. eta)
+template <bool DERIV>
+__device__ __forceinline__ Fresnel fresnel(float c, cf eta) {
+    Fresnel F;
+    cf s = csqrt_principal(cf{eta.re - (1.0f - c * c), eta.im});
+    cf cp = cf{c + s.re, s.im};
+    cf cm = cf{c - s.re, -s.im};
+    cf ec = cscale(eta, c);
+    cf lp = cadd(ec, s), lm = csub(ec, s);
+    F.rperp = cdiv(cm, cp);
+    F.rpar = cdiv(lm, lp);
+    if (DERIV) {
+        // r_perp = (c - s)/(c + s), s = sqrt(eta - sin^2): d r_perp/d eta = -c / (s (c + s)^2)
+        // r_par = (eta c - s)/(eta c + s): d r_par/d eta = c (eta - 2 sin^2) / (s (eta c + s)^2)
+        cf scp2 = cmul(s, cmul(cp, cp));
+        F.drperp = cdiv(cf{-c, 0.0f}, scp2);
+        cf num = cscale(cf{eta.re - 2.0f * (1.0f - c * c), eta.im}, c);
+        F.drpar = cdiv(num, cmul(s, cmul(lp, lp)));
+    } else {
+        F.drperp = cf{0, 0};
+        F.drpar = cf{0, 0};
+    }
+    return F;
+}
+
+// Orthonormal TE direction e_perp = (k x n)/|k x n|; at normal incidence any
+// direction transverse to k: k x a with a the axis least aligned with k.
+__device__ __forceinline__ float3 te_direction(float3 k, float3 n) {
+    float3 e = cross3(k, n);
+    float l2 = dot3(e, e);
+    if (l2 < 1e-14f) {
+        float ax = fabsf(k.x), ay = fabsf(k.y), az = fabsf(k.z);
+        float3 a = (ax <= ay && ax <= az) ? f3(1, 0, 0) : (ay <= az ? f3(0, 1, 0) : f3(0, 0, 1));
+        e = cross3(k, a);
+        l2 = dot3(e, e);
+    }
+    return e * (1.0f / sqrtf(l2));
+}
+
+// Reflection geometry at a hit.  The field of a segment is stored as complex
+// components on (e_s, e_p = k x e_s).  After reflection the basis is
+// (e_perp, k_r x e_perp); since the reflected TM direction of
+// eq. fresnel_out_vectors is e_perp x k_r = -(k_r x e_perp), the TM
+// coefficient enters with a minus sign: T <- diag(r_perp, -r_par) W T.
+struct Bounce {
+    float w00, w01, w10, w11;   // W(e_perp, e_par_i ; e_s, e_p)
+    float c;                    // cos(theta_1)
+    float3 kr;                  // reflected direction
+    float3 es_new;              // e_perp
+};
+
+__device__ __forceinline__ Bounce bounce_geometry(float3 k, float3 es, float3 nrm) {
+    Bounce b;
+    float kn = dot3(k, nrm);
+    if (kn > 0.0f) {          // orient the normal toward the incident side
+        nrm = nrm * -1.0f;
+        kn = -kn;
+    }
+    b.c = fminf(1.0f, -kn);
+    float3 ep = cross3(k, es);
+    float3 eperp = te_direction(k, nrm);
+    float3 epar = cross3(eperp, k);
+    b.w00 = dot3(eperp, es);
+    b.w01 = dot3(eperp, ep);
+    b.w10 = dot3(epar, es);
+    b.w11 = dot3(epar, ep);
+    float3 kr = k - nrm * (2.0f * kn);
+    b.kr = unit3(kr);
+    b.es_new = eperp;
+    return b;
+}
+
+}  // namespace rtd

@@ -1,0 +1,429 @@
+// sbr_forward.hip -- persistent SBR radio-map kernel for gfx950.
+//
+// One lane carries one ray at a time.  A lane whose ray has ended takes the
+// next lattice index from a device work counter (one atomic per wavefront,
+// shared out with ballot/mbcnt), so wavefronts stay full while ray lengths
+// differ.  Per traced segment l the lane
+//   1. finds the closest hit through the LBVH (short LDS stack, spill to a
+//      per-lane global area sized from the tree depth), or by testing every
+//      triangle when accel = brute force (validation);
+//   2. deposits ||T C_T||^2 * lambda^2 / (4 pi N_S |M_i| |k_z|) into the plane
+//      cell it crosses, if any (estimator eq. radio-map-solver-ci-all-2-
+//      estimator for specular chains), either with one FP32 atomic or after
+//      summing same-cell crossings across the wavefront;
+//   3. unless the segment escaped or l = L, reflects specularly and updates
+//      the 2x2 field transfer matrix T (eq. fresnel_vac and the bases of
+//      eq. fresnel_in_vectors / eq. fresnel_out_vectors).
+// Ray state (origin, direction, basis, T) stays in VGPRs for the whole ray.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sbr_common.h"
+
+using namespace rtd;
+
+namespace {
+
+struct FwdArgs {
+    const float4* nodes;
+    const float4* tris;
+    const float4* normals;
+    int root;
+    int n_tri;
+    const float* eps_r;
+    const float* sigma;
+    TxDesc tx;
+    PlaneDesc pl;
+    int64_t ray_begin;
+    int64_t n_work;
+    int L;
+    float t_min;
+    int deposit;       // 1 atomic, 2 wave
+    int npol;
+    float* map;
+    int64_t map_stride;
+    float4* tape_seg;
+    int* tape_nseg;
+    int64_t tape_n;
+    int32_t* hits;
+    int32_t* cells;
+    float* weights;
+    unsigned long long* stats;
+    unsigned long long* counter;
+    int* spill;
+    int64_t spill_stride;
+    int spill_depth;
+};
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src) {
+    unsigned lo = __shfl((unsigned)(v & 0xffffffffu), src);
+    unsigned hi = __shfl((unsigned)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Closest hit of ray r among all triangles but `last` (a slot).  Ties in t go
+// to the smallest original triangle id.  Returns the slot or -1.
+template <bool BRUTE>
+__device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int last, float& t_best, int& id_best,
+                                           int* __restrict__ lstack, int lstride, int64_t gtid,
+                                           unsigned& n_nodes, unsigned& n_tris, unsigned& overflow) {
+    t_best = INFINITY;
+    id_best = 0x7fffffff;
+    int slot_best = -1;
+    const float tmin = a.t_min;
+    if (a.n_tri == 0) return -1;
+    auto test = [&](int s) {
+        if (s == last) return;
+        float4 v0 = a.tris[3 * (int64_t)s], v1 = a.tris[3 * (int64_t)s + 1], v2 = a.tris[3 * (int64_t)s + 2];
+        n_tris++;
+        float t = tri_hit(r, v0, v1, v2, tmin);
+        if (t > 0.0f) {
+            int id = __float_as_int(v0.w);
+            if (t < t_best || (t == t_best && id < id_best)) {
+                t_best = t;
+                id_best = id;
+                slot_best = s;
+            }
+        }
+    };
+    if (BRUTE) {
+        for (int s = 0; s < a.n_tri; s++) test(s);
+        return slot_best;
+    }
+    if (a.root < 0) {
+        test(~a.root);
+        return slot_best;
+    }
+    int sp = 0;
+    int node = a.root;
+    // every internal node is visited at most once per query; the bound only
+    // guards against a malformed tree
+    for (int guard = 0; guard < a.n_tri; guard++) {
+        n_nodes++;
+        const float4* q = a.nodes + 4 * (int64_t)node;
+        float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+        bool hL, hR;
+        float tL, tR;
+        box2(r, q0, q1, q2, tmin, t_best * kBoxSlack, hL, hR, tL, tR);
+        int cl = __float_as_int(q3.x), cr = __float_as_int(q3.y);
+        if (hL && cl < 0) {
+            test(~cl);
+            hL = false;
+        }
+        if (hR && cr < 0) {
+            test(~cr);
+            hR = false;
+        }
+        if (hL && hR) {
+            int nearc = tL <= tR ? cl : cr;
+            int farc = tL <= tR ? cr : cl;
+            if (sp < RT_STACK_LDS) {
+                lstack[sp * lstride] = farc;
+                sp++;
+            } else if (sp - RT_STACK_LDS < a.spill_depth) {
+                a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid] = farc;
+                sp++;
+            } else {
+                overflow++;   // cannot happen when the spill is sized from the tree depth
+            }
+            node = nearc;
+        } else if (hL) {
+            node = cl;
+        } else if (hR) {
+            node = cr;
+        } else {
+            // pop until a node whose box may still hold a closer hit
+            if (sp == 0) break;
+            sp--;
+            node = (sp < RT_STACK_LDS) ? lstack[sp * lstride] : a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid];
+        }
+    }
+    return slot_best;
+}
+
+template <bool BRUTE>
+__global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
+    extern __shared__ int s_stack[];
+    const int lstride = blockDim.x;
+    int* lstack = s_stack + threadIdx.x;
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int L = a.L;
+    const int stride = L + 1;
+    const int W = a.pl.W, H = a.pl.H;
+
+    unsigned st_seg = 0, st_cross = 0, st_nodes = 0, st_tris = 0, st_over = 0;
+
+    bool active = false;
+    bool exhausted = false;
+    int64_t rid = 0;          // ray index relative to ray_begin
+    int l = 0;
+    int last = -1;
+    float3 o = f3(0, 0, 0), k = f3(0, 0, 0), es = f3(0, 0, 0);
+    cf Ta = {1, 0}, Tb = {0, 0}, Tc = {0, 0}, Td = {1, 0};
+    float c0t = 0.f, c0p = 0.f, c1t = 0.f, c1p = 0.f;   // C_T per polarisation
+
+    while (true) {
+        // ---- refill lanes without a ray from the work counter
+        if (!exhausted) {
+            unsigned long long need = __ballot(!active);
+            if (need) {
+                int leader = __ffsll((long long)need) - 1;
+                unsigned cnt = (unsigned)__popcll(need);
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)cnt);
+                base = shfl_u64(base, leader);
+                if (base + cnt >= (unsigned long long)a.n_work) exhausted = true;
+                if (!active) {
+                    unsigned long long my = base + (unsigned long long)__popcll(need & lt);
+                    if (my < (unsigned long long)a.n_work) {
+                        rid = (int64_t)my;
+                        const int64_t n = a.ray_begin + rid;
+                        Launch Lr = fib_launch(n, a.tx.n_rays);
+                        double ct0, cp0;
+                        tx_pattern<double>(Lr, a.tx.yaw, a.tx.pitch, a.tx.roll, a.tx.pattern, a.tx.q,
+                                           a.tx.pol == 1 ? 1 : 0, ct0, cp0);
+                        c0t = (float)ct0;
+                        c0p = (float)cp0;
+                        if (a.npol == 2) {
+                            double ct1, cp1;
+                            tx_pattern<double>(Lr, a.tx.yaw, a.tx.pitch, a.tx.roll, a.tx.pattern, a.tx.q, 1,
+                                               ct1, cp1);
+                            c1t = (float)ct1;
+                            c1p = (float)cp1;
+                        }
+                        k = f3((float)Lr.kx, (float)Lr.ky, (float)Lr.kz);
+                        es = f3((float)Lr.tx, (float)Lr.ty, (float)Lr.tz);
+                        o = f3(a.tx.pos[0], a.tx.pos[1], a.tx.pos[2]);
+                        Ta = cf{1, 0};
+                        Tb = cf{0, 0};
+                        Tc = cf{0, 0};
+                        Td = cf{1, 0};
+                        l = 0;
+                        last = -1;
+                        active = true;
+                        if (a.hits) {
+                            for (int j = 0; j < stride; j++) a.hits[rid * stride + j] = -2;
+                        }
+                        if (a.cells) {
+                            for (int j = 0; j < stride; j++) a.cells[rid * stride + j] = -1;
+                        }
+                        if (a.weights) {
+                            for (int j = 0; j < stride; j++) a.weights[rid * stride + j] = 0.0f;
+                        }
+                    }
+                }
+            }
+        }
+        if (__ballot(active) == 0ull) break;
+
+        // ---- closest hit of the current segment
+        int slot = -1, hit_id = -1, cell = -1;
+        float t_hit = INFINITY;
+        float w0 = 0.f, w1 = 0.f;
+        if (active) {
+            Ray r;
+            r.ox = o.x;
+            r.oy = o.y;
+            r.oz = o.z;
+            r.dx = k.x;
+            r.dy = k.y;
+            r.dz = k.z;
+            ray_setup(r);
+            int idb;
+            slot = closest_hit<BRUTE>(a, r, last, t_hit, idb, lstack, lstride, gtid, st_nodes, st_tris, st_over);
+            hit_id = slot >= 0 ? idb : -1;
+            st_seg++;
+            // ---- plane crossing of this segment
+            if (k.z != 0.0f) {
+                float tm = (a.pl.z - o.z) / k.z;
+                if (tm > 0.0f && tm < t_hit) {
+                    float x = o.x + tm * k.x, y = o.y + tm * k.y;
+                    float fx = (x - a.pl.x0) * a.pl.inv_dx, fy = (y - a.pl.y0) * a.pl.inv_dy;
+                    if (fx >= 0.0f && fy >= 0.0f && fx < (float)W && fy < (float)H) {
+                        int i = min((int)fx, W - 1), j = min((int)fy, H - 1);
+                        cell = j * W + i;
+                        float g = a.tx.kappa / fabsf(k.z);
+                        cf e0 = cadd(cscale(Ta, c0t), cscale(Tb, c0p));
+                        cf e1 = cadd(cscale(Tc, c0t), cscale(Td, c0p));
+                        w0 = g * (cabs2(e0) + cabs2(e1));
+                        if (a.npol == 2) {
+                            cf f0 = cadd(cscale(Ta, c1t), cscale(Tb, c1p));
+                            cf f1 = cadd(cscale(Tc, c1t), cscale(Td, c1p));
+                            w1 = g * (cabs2(f0) + cabs2(f1));
+                        }
+                        st_cross++;
+                    }
+                }
+            }
+            if (a.hits) a.hits[rid * stride + l] = hit_id;
+            if (a.cells) a.cells[rid * stride + l] = cell;
+            if (a.weights) a.weights[rid * stride + l] = w0;
+            if (a.tape_seg) {
+                const int64_t tn = a.tape_n;
+                float4* ts = a.tape_seg + (int64_t)l * 4 * tn + rid;
+                ts[0] = make_float4(k.x, k.y, k.z, __int_as_float(slot));
+                ts[tn] = make_float4(es.x, es.y, es.z, __int_as_float(cell));
+                ts[2 * tn] = make_float4(Ta.re, Ta.im, Tb.re, Tb.im);
+                ts[3 * tn] = make_float4(Tc.re, Tc.im, Td.re, Td.im);
+            }
+        }
+
+        // ---- deposit (all lanes reconverged here)
+        if (a.deposit == 2) {
+            unsigned long long pend = __ballot(cell >= 0);
+            bool done = cell < 0;
+            while (pend) {
+                int leader = __ffsll((long long)pend) - 1;
+                int lc = __shfl(cell, leader);
+                bool mine = !done && cell == lc;
+                unsigned long long grp = __ballot(mine);
+                float v0 = wave_sum(mine ? w0 : 0.0f);
+                float v1 = 0.0f;
+                if (a.npol == 2) v1 = wave_sum(mine ? w1 : 0.0f);
+                if (lane == leader) {
+                    unsafeAtomicAdd(a.map + lc, v0);
+                    if (a.npol == 2) unsafeAtomicAdd(a.map + a.map_stride + lc, v1);
+                }
+                if (mine) done = true;
+                pend &= ~grp;
+            }
+        } else if (cell >= 0) {
+            unsafeAtomicAdd(a.map + cell, w0);
+            if (a.npol == 2) unsafeAtomicAdd(a.map + a.map_stride + cell, w1);
+        }
+
+        // ---- reflect, or end the ray
+        if (active) {
+            if (slot < 0 || l == L) {
+                if (a.tape_nseg) a.tape_nseg[rid] = l + 1;
+                active = false;
+            } else {
+                float4 nm = a.normals[slot];
+                int mat = __float_as_int(nm.w);
+                Bounce b = bounce_geometry(k, es, f3(nm.x, nm.y, nm.z));
+                cf eta = cf{a.eps_r[mat], -a.sigma[mat] * a.pl.inv_eps0_omega};
+                Fresnel F = fresnel<false>(b.c, eta);
+                // T <- diag(r_perp, -r_par) W T
+                cf na = cadd(cscale(Ta, b.w00), cscale(Tc, b.w01));
+                cf nb = cadd(cscale(Tb, b.w00), cscale(Td, b.w01));
+                cf nc = cadd(cscale(Ta, b.w10), cscale(Tc, b.w11));
+                cf nd = cadd(cscale(Tb, b.w10), cscale(Td, b.w11));
+                Ta = cmul(F.rperp, na);
+                Tb = cmul(F.rperp, nb);
+                cf mr = cf{-F.rpar.re, -F.rpar.im};
+                Tc = cmul(mr, nc);
+                Td = cmul(mr, nd);
+                o = o + k * t_hit;
+                k = b.kr;
+                es = b.es_new;
+                last = slot;
+                l++;
+            }
+        }
+    }
+
+    if (a.stats) {
+        unsigned long long v[5] = {st_seg, st_cross, st_nodes, st_tris, st_over};
+        for (int i = 0; i < 5; i++) {
+            unsigned long long s = v[i];
+            for (int off = 32; off >= 1; off >>= 1) {
+                unsigned lo = __shfl_xor((unsigned)(s & 0xffffffffu), off);
+                unsigned hi = __shfl_xor((unsigned)(s >> 32), off);
+                s += ((unsigned long long)hi << 32) | lo;
+            }
+            if (lane == 0 && s) atomicAdd(a.stats + i, s);
+        }
+    }
+}
+
+// Zero the map (unless accumulating) and reset the work counter.  A kernel,
+// not a memset, so that the whole call can be captured in a HIP graph.
+__global__ void k_prepare(float* __restrict__ map, int64_t n, unsigned long long* __restrict__ counter) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *counter = 0ull;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) map[i] = 0.0f;
+}
+
+}  // namespace
+
+int rt_persistent_blocks(int block, int device) {
+    static int cu[64] = {0};
+    int dev = device < 64 ? device : 0;
+    if (!cu[dev]) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c <= 0) c = 256;
+        cu[dev] = c;
+    }
+    // enough resident waves per CU to hide traversal latency
+    int waves_per_cu = 32;
+    int blocks_per_cu = std::max(1, waves_per_cu * 64 / block);
+    return cu[dev] * blocks_per_cu;
+}
+
+rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
+    const rt_scene* s = f.scene;
+    FwdArgs a;
+    a.nodes = s->nodes;
+    a.tris = s->tris;
+    a.normals = s->normals;
+    a.root = s->root;
+    a.n_tri = (int)s->n_tri;
+    a.eps_r = f.eps_r;
+    a.sigma = f.sigma;
+    a.tx = f.tx;
+    a.pl = f.pl;
+    a.ray_begin = f.ray_begin;
+    a.n_work = f.ray_end - f.ray_begin;
+    a.L = f.L;
+    a.t_min = f.t_min;
+    a.deposit = f.deposit;
+    a.npol = f.tx.pol == RT_POL_DUAL ? 2 : 1;
+    a.map = f.map;
+    a.map_stride = (int64_t)f.pl.W * f.pl.H;
+    a.tape_seg = f.tape ? f.tape->seg : nullptr;
+    a.tape_nseg = f.tape ? f.tape->nseg : nullptr;
+    a.tape_n = f.tape ? f.tape->n_rays : 0;
+    a.hits = f.hits;
+    a.cells = f.cells;
+    a.weights = f.weights;
+    a.stats = f.stats;
+    a.counter = s->counters;
+    const int block = f.block;
+    int blocks = rt_persistent_blocks(block, s->device);
+    int64_t threads = (int64_t)blocks * block;
+    int64_t need_depth = std::max<int64_t>(0, (int64_t)s->depth + 1 - RT_STACK_LDS);
+    if ((int64_t)s->spill_entries < need_depth * threads) {
+        // the spill area is owned by the scene and sized at build time for
+        // the largest supported block count; this cannot normally happen
+        return rt_fail(RT_EOVERFLOW, "traversal spill area too small for this launch");
+    }
+    a.spill = s->spill;
+    a.spill_stride = threads;
+    a.spill_depth = (int)need_depth;
+    int64_t map_n = a.map_stride * a.npol;
+    {
+        int64_t zn = f.zero_map ? map_n : 0;
+        int g = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (zn + 255) / 256));
+        hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, f.map, zn, s->counters);
+    }
+    if (a.n_work > 0) {
+        size_t lds = sizeof(int) * RT_STACK_LDS * block;
+        if (f.accel == RT_ACCEL_BRUTE)
+            hipLaunchKernelGGL(k_forward<true>, dim3(blocks), dim3(block), lds, st, a);
+        else
+            hipLaunchKernelGGL(k_forward<false>, dim3(blocks), dim3(block), lds, st, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rt_hip_fail(e, "forward launch");
+    return RT_OK;
+}

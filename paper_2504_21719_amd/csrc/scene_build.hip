@@ -1,0 +1,472 @@
+// scene_build.hip -- on-device LBVH construction for gfx950.
+//
+// Pipeline (all device work on the caller's stream):
+//   ingest      validate indices / materials / finiteness, per-triangle AABB,
+//               centroid bounds (block-reduced, then ordered-int atomics)
+//   morton      63-bit Morton code (21 bits per axis) of every AABB centre
+//   radix sort  stable LSD sort of (code, triangle) pairs, 8 passes of 8 bits;
+//               equal codes keep input order, and the Karras split below breaks
+//               ties by index, so every key is effectively unique
+//   karras      one thread per internal node finds its key range and split
+//               from longest-common-prefix lengths (Karras, HPG 2012)
+//   depth       each internal node walks to the root to learn its depth
+//   refit       one launch per depth level, deepest first: a node's two child
+//               boxes are written only after every deeper level finished, so
+//               no inter-block flags or fences are needed
+//   gather      triangles, unit normals (computed in FP64) and materials in
+//               Morton order, so that traversal touches nearby memory
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rt_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kBlock * kRsItems;
+
+__device__ __forceinline__ unsigned f2ord(float f) {
+    unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+float ord2f_host(unsigned u) {
+    unsigned v = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    float f;
+    std::memcpy(&f, &v, 4);
+    return f;
+}
+
+// Validation + AABB + centroid bounds.
+__global__ void k_ingest(const float* __restrict__ V, int64_t n_v, const int32_t* __restrict__ F,
+                         const int32_t* __restrict__ M, int32_t n_mat, int64_t n_tri,
+                         float4* __restrict__ raw, float4* __restrict__ cen,
+                         unsigned* __restrict__ bounds, unsigned* __restrict__ err) {
+    __shared__ unsigned sb[6];
+    if (threadIdx.x < 6) sb[threadIdx.x] = (threadIdx.x < 3) ? 0xffffffffu : 0u;
+    __syncthreads();
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_tri) {
+        int32_t i0 = F[3 * t], i1 = F[3 * t + 1], i2 = F[3 * t + 2];
+        int32_t m = M[t];
+        bool ok = true;
+        if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= n_v || i1 >= n_v || i2 >= n_v) {
+            atomicOr(err, 1u);
+            ok = false;
+        }
+        if (m < 0 || m >= n_mat) {
+            atomicOr(err, 2u);
+            ok = false;
+        }
+        if (ok) {
+            float p[9];
+            const int32_t idx[3] = {i0, i1, i2};
+            bool fin = true;
+            for (int a = 0; a < 3; a++)
+                for (int c = 0; c < 3; c++) {
+                    p[3 * a + c] = V[3 * (int64_t)idx[a] + c];
+                    fin = fin && isfinite(p[3 * a + c]);
+                }
+            if (!fin) {
+                atomicOr(err, 4u);
+            } else {
+                raw[3 * t + 0] = make_float4(p[0], p[1], p[2], 0.0f);
+                raw[3 * t + 1] = make_float4(p[3], p[4], p[5], 0.0f);
+                raw[3 * t + 2] = make_float4(p[6], p[7], p[8], 0.0f);
+                float c[3];
+                for (int a = 0; a < 3; a++) {
+                    float lo = fminf(fminf(p[a], p[3 + a]), p[6 + a]);
+                    float hi = fmaxf(fmaxf(p[a], p[3 + a]), p[6 + a]);
+                    c[a] = 0.5f * (lo + hi);
+                    atomicMin(&sb[a], f2ord(c[a]));
+                    atomicMax(&sb[3 + a], f2ord(c[a]));
+                }
+                cen[t] = make_float4(c[0], c[1], c[2], 0.0f);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) atomicMin(&bounds[threadIdx.x], sb[threadIdx.x]);
+    else if (threadIdx.x < 6) atomicMax(&bounds[threadIdx.x], sb[threadIdx.x]);
+}
+
+__device__ __forceinline__ uint64_t spread21(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x001f00000000ffffull;
+    x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ void k_morton(const float4* __restrict__ cen, int64_t n, float lx, float ly, float lz,
+                         float sx, float sy, float sz, uint64_t* __restrict__ keys,
+                         uint32_t* __restrict__ vals) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float4 c = cen[t];
+    const float qmax = 2097151.0f;
+    uint32_t qx = (uint32_t)fminf(fmaxf((c.x - lx) * sx, 0.0f), qmax);
+    uint32_t qy = (uint32_t)fminf(fmaxf((c.y - ly) * sy, 0.0f), qmax);
+    uint32_t qz = (uint32_t)fminf(fmaxf((c.z - lz) * sz, 0.0f), qmax);
+    keys[t] = (spread21(qx) << 2) | (spread21(qy) << 1) | spread21(qz);
+    vals[t] = (uint32_t)t;
+}
+
+// ---- radix sort -----------------------------------------------------------
+__global__ void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                          unsigned* __restrict__ hist, int nblocks) {
+    __shared__ unsigned h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int i = 0; i < kRsItems; i++) {
+        int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `count` unsigned values in place, one block of 1024.
+__global__ void k_scan1(unsigned* __restrict__ data, int64_t count) {
+    __shared__ unsigned part[1024];
+    const int T = 1024;
+    int64_t per = (count + T - 1) / T;
+    int64_t b = threadIdx.x * per, e = min(count, b + per);
+    unsigned s = 0;
+    for (int64_t i = b; i < e; i++) s += data[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < T; off <<= 1) {
+        unsigned v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned run = part[threadIdx.x] - s;   // exclusive prefix of this chunk
+    for (int64_t i = b; i < e; i++) {
+        unsigned v = data[i];
+        data[i] = run;
+        run += v;
+    }
+}
+
+__global__ void k_rs_scatter(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                             uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
+                             int shift, const unsigned* __restrict__ offs, int nblocks) {
+    __shared__ unsigned running[256];
+    __shared__ unsigned wcnt[kBlock / 64][256];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    running[tid] = offs[(int64_t)tid * nblocks + blockIdx.x];
+    int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int c = 0; c < kRsItems; c++) {
+        int64_t idx = base + (int64_t)c * kBlock + tid;
+        bool valid = idx < n;
+        uint64_t key = valid ? kin[idx] : 0ull;
+        unsigned digit = valid ? (unsigned)((key >> shift) & 255u) : 0u;
+        uint64_t m = __ballot(valid);
+        for (int b = 0; b < 8; b++) {
+            bool bit = (digit >> b) & 1u;
+            uint64_t bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
+        for (int w = 0; w < kBlock / 64; w++) wcnt[w][tid] = 0u;
+        __syncthreads();
+        unsigned rank = (unsigned)__popcll(m & lt);
+        bool last = valid && ((m >> lane) == 1ull);
+        if (last) wcnt[wave][digit] = rank + 1;
+        __syncthreads();
+        if (valid) {
+            unsigned off = running[digit];
+            for (int w = 0; w < wave; w++) off += wcnt[w][digit];
+            kout[off + rank] = key;
+            vout[off + rank] = vin[idx];
+        }
+        __syncthreads();
+        unsigned add = 0;
+        for (int w = 0; w < kBlock / 64; w++) add += wcnt[w][tid];
+        running[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---- hierarchy ------------------------------------------------------------
+__device__ __forceinline__ int lcp(const uint64_t* __restrict__ k, int64_t n, int64_t i, int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    uint64_t a = k[i], b = k[j];
+    if (a == b) return 64 + __clz((unsigned)(i ^ j));
+    return __clzll(a ^ b);
+}
+
+__global__ void k_karras(const uint64_t* __restrict__ keys, int64_t n, int4* __restrict__ child,
+                         int* __restrict__ parent) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int d = (lcp(keys, n, i, i + 1) - lcp(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = lcp(keys, n, i, i - d);
+    int64_t lmax = 2;
+    while (lcp(keys, n, i, i + lmax * d) > dmin) lmax *= 2;
+    int64_t l = 0;
+    for (int64_t t = lmax / 2; t >= 1; t /= 2)
+        if (lcp(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    int64_t j = i + l * d;
+    int dnode = lcp(keys, n, i, j);
+    int64_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (lcp(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    int64_t g = i + s * d + min(d, 0);
+    int left = (min(i, j) == g) ? ~(int)g : (int)g;
+    int right = (max(i, j) == g + 1) ? ~(int)(g + 1) : (int)(g + 1);
+    child[i] = make_int4(left, right, 0, 0);
+    if (left >= 0) parent[left] = (int)i;
+    if (right >= 0) parent[right] = (int)i;
+}
+
+__global__ void k_depth(const int* __restrict__ parent, const int4* __restrict__ child, int64_t n_int,
+                        int* __restrict__ depth, int* __restrict__ maxdepth) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_int) return;
+    // walk to the root; the bound and the range check turn a malformed
+    // hierarchy into an error flag instead of a runaway loop
+    int d = 0;
+    int p = (int)i;
+    while (p != 0) {
+        p = parent[p];
+        d++;
+        if (p < 0 || p >= n_int || d > 4096) {
+            atomicMax(maxdepth, 1 << 30);
+            depth[i] = -1;
+            return;
+        }
+    }
+    depth[i] = d;
+    int4 c = child[i];
+    if (c.x < 0 || c.y < 0) atomicMax(maxdepth, d + 1);
+    else atomicMax(maxdepth, d);
+}
+
+__device__ __forceinline__ void tri_box(const float4* __restrict__ raw, const uint32_t* __restrict__ order,
+                                        int slot, float lo[3], float hi[3]) {
+    int64_t t = order[slot];
+    float4 a = raw[3 * t], b = raw[3 * t + 1], c = raw[3 * t + 2];
+    lo[0] = fminf(fminf(a.x, b.x), c.x);
+    lo[1] = fminf(fminf(a.y, b.y), c.y);
+    lo[2] = fminf(fminf(a.z, b.z), c.z);
+    hi[0] = fmaxf(fmaxf(a.x, b.x), c.x);
+    hi[1] = fmaxf(fmaxf(a.y, b.y), c.y);
+    hi[2] = fmaxf(fmaxf(a.z, b.z), c.z);
+}
+
+__device__ __forceinline__ void node_box(const float4* __restrict__ nodes, int c, float lo[3], float hi[3]) {
+    float4 q0 = nodes[4 * (int64_t)c], q1 = nodes[4 * (int64_t)c + 1], q2 = nodes[4 * (int64_t)c + 2];
+    lo[0] = fminf(q0.x, q1.x);
+    hi[0] = fmaxf(q0.y, q1.y);
+    lo[1] = fminf(q0.z, q1.z);
+    hi[1] = fmaxf(q0.w, q1.w);
+    lo[2] = fminf(q2.x, q2.z);
+    hi[2] = fmaxf(q2.y, q2.w);
+}
+
+__global__ void k_refit_level(const int4* __restrict__ child, const int* __restrict__ depth, int level,
+                              int64_t n_int, const float4* __restrict__ raw,
+                              const uint32_t* __restrict__ order, float4* __restrict__ nodes) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_int || depth[i] != level) return;
+    int4 c = child[i];
+    float llo[3], lhi[3], rlo[3], rhi[3];
+    if (c.x < 0) tri_box(raw, order, ~c.x, llo, lhi);
+    else node_box(nodes, c.x, llo, lhi);
+    if (c.y < 0) tri_box(raw, order, ~c.y, rlo, rhi);
+    else node_box(nodes, c.y, rlo, rhi);
+    nodes[4 * i + 0] = make_float4(llo[0], lhi[0], llo[1], lhi[1]);
+    nodes[4 * i + 1] = make_float4(rlo[0], rhi[0], rlo[1], rhi[1]);
+    nodes[4 * i + 2] = make_float4(llo[2], lhi[2], rlo[2], rhi[2]);
+    nodes[4 * i + 3] = make_float4(__int_as_float(c.x), __int_as_float(c.y), 0.0f, 0.0f);
+}
+
+__global__ void k_gather(const float4* __restrict__ raw, const uint32_t* __restrict__ order,
+                         const int32_t* __restrict__ M, int64_t n, float4* __restrict__ tris,
+                         float4* __restrict__ normals) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int64_t t = order[s];
+    float4 a = raw[3 * t], b = raw[3 * t + 1], c = raw[3 * t + 2];
+    int32_t m = M[t];
+    tris[3 * s + 0] = make_float4(a.x, a.y, a.z, __int_as_float((int)t));
+    tris[3 * s + 1] = make_float4(b.x, b.y, b.z, __int_as_float(m));
+    tris[3 * s + 2] = make_float4(c.x, c.y, c.z, 0.0f);
+    double e1x = (double)b.x - a.x, e1y = (double)b.y - a.y, e1z = (double)b.z - a.z;
+    double e2x = (double)c.x - a.x, e2y = (double)c.y - a.y, e2z = (double)c.z - a.z;
+    double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+    double len = sqrt(nx * nx + ny * ny + nz * nz);
+    if (len > 0.0) {
+        nx /= len;
+        ny /= len;
+        nz /= len;
+    } else {
+        nx = 0.0;
+        ny = 0.0;
+        nz = 1.0;
+    }
+    normals[s] = make_float4((float)nx, (float)ny, (float)nz, __int_as_float(m));
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)std::max<int64_t>(1, (n + block - 1) / block); }
+
+}  // namespace
+
+#define HIPCHK(x)                                            \
+    do {                                                     \
+        hipError_t _e = (x);                                 \
+        if (_e != hipSuccess) {                              \
+            cleanup();                                       \
+            return rt_hip_fail(_e, #x);                      \
+        }                                                    \
+    } while (0)
+
+rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t* F, const int32_t* M,
+                        hipStream_t st) {
+    const int64_t n = s->n_tri;
+    if (n == 0) {
+        s->root = -1;
+        s->depth = 0;
+        return RT_OK;
+    }
+    // temporaries
+    float4 *raw = nullptr, *cen = nullptr;
+    uint64_t *k0 = nullptr, *k1 = nullptr;
+    uint32_t *v0 = nullptr, *v1 = nullptr;
+    unsigned *hist = nullptr, *bounds = nullptr;
+    int4* child = nullptr;
+    int *parent = nullptr, *depth = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(raw);
+        (void)hipFree(cen);
+        (void)hipFree(k0);
+        (void)hipFree(k1);
+        (void)hipFree(v0);
+        (void)hipFree(v1);
+        (void)hipFree(hist);
+        (void)hipFree(bounds);
+        (void)hipFree(child);
+        (void)hipFree(parent);
+        (void)hipFree(depth);
+    };
+    const int64_t n_int = std::max<int64_t>(0, n - 1);
+    const int rs_blocks = (int)((n + kRsTile - 1) / kRsTile);
+    HIPCHK(hipMalloc(&raw, sizeof(float4) * 3 * n));
+    HIPCHK(hipMalloc(&cen, sizeof(float4) * n));
+    HIPCHK(hipMalloc(&k0, sizeof(uint64_t) * n));
+    HIPCHK(hipMalloc(&k1, sizeof(uint64_t) * n));
+    HIPCHK(hipMalloc(&v0, sizeof(uint32_t) * n));
+    HIPCHK(hipMalloc(&v1, sizeof(uint32_t) * n));
+    HIPCHK(hipMalloc(&hist, sizeof(unsigned) * 256 * (size_t)rs_blocks));
+    HIPCHK(hipMalloc(&bounds, sizeof(unsigned) * 8));
+    HIPCHK(hipMalloc(&child, sizeof(int4) * std::max<int64_t>(1, n_int)));
+    HIPCHK(hipMalloc(&parent, sizeof(int) * std::max<int64_t>(1, n_int)));
+    HIPCHK(hipMalloc(&depth, sizeof(int) * (std::max<int64_t>(1, n_int) + 1)));
+
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+
+    unsigned hb[8] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u, 0u};
+    HIPCHK(hipMemcpyAsync(bounds, hb, sizeof(hb), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_ingest, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, V, n_v, F, M, s->n_mat, n,
+                       raw, cen, bounds, bounds + 6);
+    HIPCHK(hipGetLastError());
+    unsigned hres[8];
+    HIPCHK(hipMemcpyAsync(hres, bounds, sizeof(hres), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hres[6] != 0) {
+        cleanup();
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        std::string why;
+        if (hres[6] & 1u) why += " vertex index out of range;";
+        if (hres[6] & 2u) why += " material id out of range;";
+        if (hres[6] & 4u) why += " non-finite vertex coordinate;";
+        return rt_fail(RT_EINVAL, "rt_build_scene: invalid mesh:" + why);
+    }
+    float lo[3], hi[3], sc[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = ord2f_host(hres[a]);
+        hi[a] = ord2f_host(hres[3 + a]);
+        float ext = hi[a] - lo[a];
+        sc[a] = ext > 0.0f ? 2097151.0f / ext : 0.0f;
+    }
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, cen, n, lo[0], lo[1], lo[2],
+                       sc[0], sc[1], sc[2], k0, v0);
+    HIPCHK(hipGetLastError());
+    uint64_t *ka = k0, *kb = k1;
+    uint32_t *va = v0, *vb = v1;
+    for (int shift = 0; shift < 64; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(rs_blocks), dim3(kBlock), 0, st, ka, n, shift, hist, rs_blocks);
+        hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * rs_blocks);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(rs_blocks), dim3(kBlock), 0, st, ka, va, kb, vb, n, shift, hist,
+                           rs_blocks);
+        HIPCHK(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    // after 8 passes the sorted data is back in (k0, v0)
+    size_t node_bytes = sizeof(float4) * 4 * (size_t)std::max<int64_t>(1, n_int);
+    HIPCHK(hipMalloc(&s->nodes, node_bytes));
+    HIPCHK(hipMalloc(&s->tris, sizeof(float4) * 3 * n));
+    HIPCHK(hipMalloc(&s->normals, sizeof(float4) * n));
+    s->bytes += node_bytes + sizeof(float4) * 4 * n;
+    int maxdepth = 0;
+    if (n_int > 0) {
+        HIPCHK(hipMemsetAsync(parent, 0xff, sizeof(int) * n_int, st));
+        hipLaunchKernelGGL(k_karras, dim3(grid_for(n_int, kBlock)), dim3(kBlock), 0, st, ka, n, child, parent);
+        HIPCHK(hipMemsetAsync(depth + n_int, 0, sizeof(int), st));
+        hipLaunchKernelGGL(k_depth, dim3(grid_for(n_int, kBlock)), dim3(kBlock), 0, st, parent, child, n_int,
+                           depth, depth + n_int);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&maxdepth, depth + n_int, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (maxdepth > 4096) {
+            cleanup();
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rt_fail(RT_EDEVICE, "rt_build_scene: LBVH hierarchy is malformed");
+        }
+        for (int lvl = maxdepth - 1; lvl >= 0; lvl--) {
+            hipLaunchKernelGGL(k_refit_level, dim3(grid_for(n_int, kBlock)), dim3(kBlock), 0, st, child, depth,
+                               lvl, n_int, raw, va, s->nodes);
+        }
+        HIPCHK(hipGetLastError());
+        s->root = 0;
+    } else {
+        s->root = ~0;   // single triangle: the root is a leaf
+        maxdepth = 0;
+    }
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, raw, va, M, n, s->tris,
+                       s->normals);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->build_ms = ms;
+    s->depth = maxdepth;
+    for (int a = 0; a < 3; a++) {
+        s->lo[a] = lo[a];
+        s->hi[a] = hi[a];
+    }
+    cleanup();
+    return RT_OK;
+}
