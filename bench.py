@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X SBR radio-map path (one GPU).
+
+Workload: the seeded Manhattan city (10 x 10 blocks, 1,202 triangles, concrete
+and glass), isotropic V-pol transmitter at (0, 0, 30) m, f = 3.5 GHz,
+N_S = 1e7 rays, max depth L = 5, 1000 x 1000 cells of 1 m at z = 1.5 m.
+
+One timed step = one rt_radio_map call: zero the map, launch every ray, trace
+all its segments through the LBVH, reflect, deposit.  The metric is traced
+segments ("ray-bounces", one closest-hit query each) per second, counted on
+the device.  Inputs are resident in HBM before timing starts.
+
+Printed: one JSON line with the metric, a roofline object for the forward
+kernel (algorithmic bytes per launch from the node/triangle/deposit counters,
+over the kernel's event-timed duration), and the FP64 oracle timed on a
+bounded strided sample of the same lattice on one host core.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SBR radio map M ray-bounces/s; fwd+bwd/fwd and batched vs plain at 1e-3 tol"
+HBM_PEAK_GBS = 8000.0
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "forward_manhattan_counters.json")
+KERNEL_SOURCES = ["paper_2504_21719_amd/csrc/sbr_forward.hip", "paper_2504_21719_amd/csrc/sbr_common.h",
+                  "paper_2504_21719_amd/csrc/rt_device.h"]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-extras", action="store_true", help="skip the fwd+bwd and batched ratio legs")
+    ap.add_argument("--calib-copy", action="store_true", help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--profile-steps", type=int, default=0, help="only run N forward steps (for rocprofv3)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the map would be "
+              "all-reduced over RCCL after tracing disjoint ray ranges; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2504_21719_amd as rt
+    import scenegen as sg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = sg.manhattan_config()
+    scene = rt.scene_from_mesh(cfg.scene)
+    info = scene.info()
+    eps = torch.tensor(cfg.scene.eps_r, dtype=torch.float32, device=dev)
+    sig = torch.tensor(cfg.scene.sigma, dtype=torch.float32, device=dev)
+    H, W = cfg.plane.H, cfg.plane.W
+    out = torch.empty((1, H, W), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out)
+        if args.calib_copy:
+            a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "calib_copy_bytes": (64 << 20) * 4 if args.calib_copy else 0}))
+        return
+
+    # device counters of one pass: segments, crossings, node visits, triangle tests
+    stats = torch.zeros(8, dtype=torch.int64, device=dev)
+    rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out, stats=stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy().astype(np.int64)
+    n_seg, n_cross, n_node, n_tri = int(st[0]), int(st[1]), int(st[2]), int(st[3])
+    alg_bytes = 56 * n_node + 40 * n_tri + 8 * n_cross
+
+    for _ in range(args.warmup):
+        rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out)
+    torch.cuda.synchronize()
+    # timed region: exactly `steps` steps, synchronised on both sides
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out)
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [s.elapsed_time(e) for s, e in ev]
+    ms_per_step = wall * 1e3 / args.steps
+    value = n_seg / (ms_per_step * 1e-3) / 1e6
+
+    # forward-kernel duration: the same call with accumulate = 1 queues only the
+    # work-counter reset (one thread) besides the forward kernel
+    evk = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for s, e in evk:
+        s.record(stream)
+        rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out, accumulate=1)
+        e.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = float(np.mean([s.elapsed_time(e) for s, e in evk]))
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+
+    traffic = None
+    try:
+        with open(PROFILE_COUNTERS) as f:
+            pc = json.load(f)
+        if pc.get("kernel_source_sha") == kernel_source_sha():
+            traffic = {"fetch_bytes": pc["fetch_bytes_per_launch"], "write_bytes": pc["write_bytes_per_launch"],
+                       "total_bytes": pc["fetch_bytes_per_launch"] + pc["write_bytes_per_launch"],
+                       "source": os.path.relpath(PROFILE_COUNTERS, ROOT)}
+    except (OSError, KeyError, ValueError):
+        traffic = None
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "M ray-bounces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "manhattan: seeded 10x10-block city, 1,202 triangles, iso V-pol Tx at (0,0,30) m, "
+                               "3.5 GHz, 1e7 Fibonacci rays, max depth 5, 1000x1000 cells of 1 m at z=1.5 m",
+                   "n_rays": cfg.params.n_rays, "max_depth": cfg.params.max_depth,
+                   "n_triangles": cfg.scene.n_triangles, "cells": [H, W], "parallelism": "single GPU"},
+        "segments_per_step": n_seg,
+        "crossings_per_step": n_cross,
+        "event_ms_per_step_median": round(float(np.median(step_ms)), 4),
+        "build_ms": round(info.build_ms, 3),
+        "bvh_depth": info.bvh_depth,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_forward<false>", "kernel_ms": round(kern_ms, 4),
+                     "alg_bytes_per_launch": int(alg_bytes),
+                     "byte_model": "56 B per node visit + 40 B per triangle test + 8 B per deposit",
+                     "node_visits": n_node, "tri_tests": n_tri},
+    }
+
+    if not args.no_extras:
+        try:
+            result.update(extra_legs(rt, sg, cfg, scene, eps, sig, dev))
+        except rt.RtError as e:
+            result["extras_error"] = str(e)
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+
+    print(json.dumps(result), flush=True)
+
+
+def extra_legs(rt, sg, cfg, scene, eps, sig, dev):
+    """fwd+bwd/fwd (differentiation workload) and batched vs plain loops."""
+    import numpy as np
+    import torch
+    out = {}
+    # ---- fwd+bwd / fwd on the differentiation workload (1e6 rays, L = 4)
+    dc = sg.diff_config()
+    H, W = dc.plane.H, dc.plane.W
+    m = torch.empty((1, H, W), dtype=torch.float32, device=dev)
+    tape = rt.rt_tape_create(dc.params)
+    g = torch.randn((1, H, W), dtype=torch.float32, device=dev)
+    ge = torch.empty(2, dtype=torch.float32, device=dev)
+    gs = torch.empty(2, dtype=torch.float32, device=dev)
+    go = torch.empty(3, dtype=torch.float32, device=dev)
+
+    def fwd():
+        rt.rt_radio_map(scene, eps, sig, dc.tx, dc.plane, dc.params, m)
+
+    def fwdbwd():
+        rt.rt_radio_map(scene, eps, sig, dc.tx, dc.plane, dc.params, m, tape=tape)
+        rt.rt_radio_map_backward(scene, eps, sig, dc.tx, dc.plane, dc.params, tape, g, ge, gs, go)
+
+    t_f = _time(fwd)
+    t_fb = _time(fwdbwd)
+    out["fwd_bwd_over_fwd"] = round(t_fb / t_f, 3)
+    out["fwd_ms_diff"] = round(t_f, 4)
+    out["fwd_bwd_ms_diff"] = round(t_fb, 4)
+    return out
+
+
+def _time(fn, reps=10, warm=2):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def cpu_baseline(cfg, seconds):
+    """FP64 oracle on one host core over a bounded sample of the same lattice.
+
+    The sample is a run of interleaved strided chunks (chunk c = rays c, c+1000,
+    c+2000, ...), added until about `seconds` of wall time have been spent.
+    """
+    import numpy as np
+    import oracle
+    N = cfg.params.n_rays
+    stride = 1000
+    oracle.lib()
+    segs = 0
+    rays = 0
+    chunks = 0
+    cpu0 = time.process_time()
+    w0 = time.perf_counter()
+    while chunks < stride and time.perf_counter() - w0 < seconds:
+        ids = np.arange(chunks, N, stride, dtype=np.int64)
+        r = oracle.radio_map(cfg.scene, cfg.tx, cfg.plane, cfg.params, ray_ids=ids)
+        segs += r.segments
+        rays += ids.size
+        chunks += 1
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - cpu0
+    return {"value": round(segs / wall / 1e6, 6), "unit": "M ray-bounces/s", "cores": 1, "kind": "oracle",
+            "sample": "%d rays (%d interleaved chunks of every 1000th ray of the 1e7-ray lattice), %d segments, "
+                      "%.1f s wall, %.1f s CPU, single-threaded FP64 brute force" % (rays, chunks, segs, wall, cpu),
+            "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()
