@@ -221,14 +221,15 @@ def fibonacci_angles(n, N):
 # ---------------------------------------------------------------- parallel
 def _worker(args):
     scene, tx, plane, params, b, e, kw = args
-    r = radio_map(scene, tx, plane, params, ray_begin=b, ray_end=e, **kw)
-    return r.map, r.counts, r.grad, r.segments, r.tri_tests
+    return radio_map(scene, tx, plane, params, ray_begin=b, ray_end=e, **kw)
 
 
-def radio_map_parallel(scene, tx, plane, params, workers=None, chunks_per_worker=4, **kw):
-    """Split [ray_begin, ray_end) over a process pool and sum the per-chunk maps.
+def radio_map_parallel(scene, tx, plane, params, workers=None, chunks_per_worker=1, replay_hits=None, **kw):
+    """Split [ray_begin, ray_end) over a process pool and combine the chunks.
 
-    Supported keyword options are the accumulating ones (eps_r, sigma, grad_map).
+    Maps, counts and gradients are summed; hits, flags and crossing records
+    are concatenated in ray order.  ``replay_hits`` ([n_rays_run][L+1]) is
+    split along with the rays.
     """
     import multiprocessing as mp
     workers = int(workers or min(16, os.cpu_count() or 1))
@@ -236,14 +237,25 @@ def radio_map_parallel(scene, tx, plane, params, workers=None, chunks_per_worker
     n = e0 - b0
     nchunk = max(1, min(n, workers * chunks_per_worker))
     edges = [b0 + (n * i) // nchunk for i in range(nchunk + 1)]
-    jobs = [(scene, tx, plane, params, edges[i], edges[i + 1], kw) for i in range(nchunk) if edges[i + 1] > edges[i]]
+    jobs = []
+    for i in range(nchunk):
+        if edges[i + 1] <= edges[i]:
+            continue
+        kwi = dict(kw)
+        if replay_hits is not None:
+            kwi["replay_hits"] = replay_hits[edges[i] - b0: edges[i + 1] - b0]
+        jobs.append((scene, tx, plane, params, edges[i], edges[i + 1], kwi))
     lib()  # build before forking
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
         parts = pool.map(_worker, jobs)
-    mp_ = sum(p[0] for p in parts)
-    cnt = sum(p[1] for p in parts)
-    grad = None
-    if parts and parts[0][2] is not None:
-        grad = sum(p[2] for p in parts)
-    return OracleResult(mp_, cnt, None, None, None, grad, sum(p[3] for p in parts), sum(p[4] for p in parts))
+    mp_ = sum(p.map for p in parts)
+    cnt = sum(p.counts for p in parts)
+    grad = sum(p.grad for p in parts) if parts[0].grad is not None else None
+    hits = np.concatenate([p.hits for p in parts]) if parts[0].hits is not None else None
+    flags = np.concatenate([p.flags for p in parts]) if parts[0].flags is not None else None
+    recs = None
+    if parts[0].records is not None:
+        recs = {k: np.concatenate([p.records[k] for p in parts]) for k in parts[0].records}
+    return OracleResult(mp_, cnt, hits, flags, recs, grad, sum(p.segments for p in parts),
+                        sum(p.tri_tests for p in parts))

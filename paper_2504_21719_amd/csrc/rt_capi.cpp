@@ -93,6 +93,7 @@ extern "C" rt_status rt_scene_destroy(rt_scene* s) {
     (void)hipFree(s->counters);
     (void)hipFree(s->spill);
     (void)hipFree(s->tx_desc);
+    (void)hipFree(s->grad_ws);
     if (s->tx_desc_host) (void)hipHostFree(s->tx_desc_host);
     delete s;
     return RT_OK;
@@ -385,6 +386,7 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
         hipStream_t hs = (hipStream_t)stream;
         (void)hipStreamSynchronize(hs);
         (void)hipFree(s->tx_desc);
+    (void)hipFree(s->grad_ws);
         if (s->tx_desc_host) (void)hipHostFree(s->tx_desc_host);
         s->tx_desc = nullptr;
         s->tx_desc_host = nullptr;

@@ -49,6 +49,9 @@ struct rt_scene {
     // autotuned launch configuration (0 = not tuned)
     int tuned_block = 0;
     int tuned_deposit = 0;
+    // backward workspace: per-block FP64 partial sums
+    void* grad_ws = nullptr;
+    size_t grad_ws_bytes = 0;
     // batched-call staging (device copies of per-transmitter descriptors)
     void* tx_desc = nullptr;
     size_t tx_desc_bytes = 0;

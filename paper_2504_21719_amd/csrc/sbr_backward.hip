@@ -1,7 +1,235 @@
-// sbr_backward.hip -- adjoint of the SBR radio map (placeholder until the
-// reverse sweep lands).
-#include "rt_internal.h"
+// sbr_backward.hip -- adjoint (vector-Jacobian product) of the SBR radio map.
+//
+// The forward pass with a tape recorded, per traced segment l of every ray,
+// its direction k_l, basis vector e_s,l, the slot of the triangle that ends
+// it, the plane cell it crossed, and the field transfer matrix T_l (the
+// per-bounce checkpoint).  For one ray and polarisation with launch pattern C
+// the loss contribution is
+//     J = sum_l a_l ||E_l||^2,   E_l = T_l C,   a_l = G[cell_l] kappa / |k_l,z|
+// (G = dLoss/dMap; a_l = 0 when segment l crosses no cell), and
+//     E_l = R_l E_{l-1},   R_l = diag(r_perp, -r_par) W_l
+// with W_l the basis change at the hit that ends segment l-1 and r the
+// vacuum Fresnel coefficients (eq. fresnel_vac) of the hit material's
+// eta = eps_r - j sigma/(eps0 omega) (eq. eta).
+//
+// Reverse sweep (Wirtinger calculus for the real J): with
+//     lambda_l = a_l E_l + R_{l+1}^H lambda_{l+1}
+// the derivative with respect to a real parameter p of R_l is
+//     dJ/dp = 2 Re( lambda_l^H (dR_l/dp) E_{l-1} ),
+// where dR/d eta = diag(dr_perp/d eta, -dr_par/d eta) W, d eta/d eps_r = 1,
+// d eta/d sigma = -j/(eps0 omega), and for the launch pattern
+//     dJ/dp = 2 Re( lambda_0^H dC/dp ),  p in {yaw, pitch, roll},
+// with dC/dp from forward-mode dual numbers through eq. rotation and
+// eq. theta_phi_prime.  Nothing is re-traced: geometry and fields come from
+// the tape; only the normal (from the hit slot) and the Fresnel terms are
+// recomputed.
+//
+// Reduction: every thread owns a fixed set of rays (grid-stride order) and
+// registers for up to kMatChunk materials; sums go thread -> wave (butterfly)
+// -> block (waves in order) -> per-block partials in FP64 -> one final kernel
+// that adds the blocks in order.  The result does not depend on scheduling.
+#include <hip/hip_runtime.h>
 
-rt_status rt_launch_backward(const BwdLaunch&, hipStream_t) {
-    return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_backward: not built yet");
+#include <algorithm>
+
+#include "sbr_common.h"
+
+using namespace rtd;
+
+namespace {
+
+constexpr int kMatChunk = 8;
+constexpr int kBwdBlock = 256;
+constexpr int kBwdBlocks = 1024;
+
+struct BwdArgs {
+    const float4* seg;
+    const int* nseg;
+    int64_t n;            // rays on the tape
+    int64_t ray_begin;
+    const float4* normals;
+    const float* eps_r;
+    const float* sigma;
+    TxDesc tx;
+    PlaneDesc pl;
+    int npol;
+    const float* grad_map;
+    int64_t map_stride;
+    int n_mat;
+    int mat0;             // first material of this chunk
+    int P;                // parameters written by this launch into partials
+    double* partials;     // [gridDim.x][P]
+    int write_orient;     // 1: this chunk also produces the orientation terms
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
+    float ge[kMatChunk], gs[kMatChunk];
+#pragma unroll
+    for (int j = 0; j < kMatChunk; j++) {
+        ge[j] = 0.0f;
+        gs[j] = 0.0f;
+    }
+    float go0 = 0.f, go1 = 0.f, go2 = 0.f;
+    const int64_t T = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n = a.n;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += T) {
+        const int ns = a.nseg[r];
+        const int64_t ray = a.ray_begin + r;
+        Launch Lr = fib_launch(ray, a.tx.n_rays);
+        for (int p = 0; p < a.npol; p++) {
+            int pol_index = (a.npol == 2) ? p : (a.tx.pol == 1 ? 1 : 0);
+            dual3 cth, cph;
+            tx_pattern<dual3>(Lr, dual3{a.tx.yaw, 1.0, 0.0, 0.0}, dual3{a.tx.pitch, 0.0, 1.0, 0.0},
+                              dual3{a.tx.roll, 0.0, 0.0, 1.0}, a.tx.pattern, a.tx.q, pol_index, cth, cph);
+            const float ct = (float)cth.v, cp = (float)cph.v;
+            const float* G = a.grad_map + (int64_t)p * a.map_stride;
+            cf lam0 = {0, 0}, lam1 = {0, 0};
+            for (int l = ns - 1; l >= 0; l--) {
+                const float4* s = a.seg + (int64_t)l * 4 * n + r;
+                float4 s0 = s[0], s1 = s[n], s2 = s[2 * n], s3 = s[3 * n];
+                int cell = __float_as_int(s1.w);
+                if (cell >= 0) {
+                    float g = G[cell];
+                    if (g != 0.0f) {
+                        float al = g * a.tx.kappa / fabsf(s0.z);
+                        // E_l = T_l C
+                        cf e0 = cadd(cscale(cf{s2.x, s2.y}, ct), cscale(cf{s2.z, s2.w}, cp));
+                        cf e1 = cadd(cscale(cf{s3.x, s3.y}, ct), cscale(cf{s3.z, s3.w}, cp));
+                        lam0 = cadd(lam0, cscale(e0, al));
+                        lam1 = cadd(lam1, cscale(e1, al));
+                    }
+                }
+                if (l == 0) break;
+                // bounce at the end of segment l-1
+                const float4* q = a.seg + (int64_t)(l - 1) * 4 * n + r;
+                float4 p0 = q[0], p1 = q[n], p2 = q[2 * n], p3 = q[3 * n];
+                int slot = __float_as_int(p0.w);
+                float4 nm = a.normals[slot];
+                int mat = __float_as_int(nm.w);
+                Bounce b = bounce_geometry(f3(p0.x, p0.y, p0.z), f3(p1.x, p1.y, p1.z), f3(nm.x, nm.y, nm.z));
+                cf eta = cf{a.eps_r[mat], -a.sigma[mat] * a.pl.inv_eps0_omega};
+                Fresnel F = fresnel<true>(b.c, eta);
+                // u = W E_{l-1}
+                cf f0 = cadd(cscale(cf{p2.x, p2.y}, ct), cscale(cf{p2.z, p2.w}, cp));
+                cf f1 = cadd(cscale(cf{p3.x, p3.y}, ct), cscale(cf{p3.z, p3.w}, cp));
+                cf u0 = cadd(cscale(f0, b.w00), cscale(f1, b.w01));
+                cf u1 = cadd(cscale(f0, b.w10), cscale(f1, b.w11));
+                int j = mat - a.mat0;
+                if (j >= 0 && j < kMatChunk) {
+                    // z = lambda^H dD/deta u, dD/deta = diag(dr_perp, -dr_par)
+                    cf z = csub(cmulc(lam0, cmul(F.drperp, u0)), cmulc(lam1, cmul(F.drpar, u1)));
+#pragma unroll
+                    for (int jj = 0; jj < kMatChunk; jj++) {
+                        if (jj == j) {
+                            ge[jj] += 2.0f * z.re;
+                            gs[jj] += 2.0f * z.im * a.pl.inv_eps0_omega;
+                        }
+                    }
+                }
+                // lambda <- R^H lambda = W^T diag(conj r_perp, -conj r_par) lambda
+                cf v0 = cmulc(F.rperp, lam0);
+                cf v1 = cmulc(F.rpar, lam1);
+                v1 = cf{-v1.re, -v1.im};
+                lam0 = cadd(cscale(v0, b.w00), cscale(v1, b.w10));
+                lam1 = cadd(cscale(v0, b.w01), cscale(v1, b.w11));
+            }
+            if (a.write_orient) {
+                // 2 Re(lambda_0^H dC), with C real
+                go0 += 2.0f * (lam0.re * (float)cth.d0 + lam1.re * (float)cph.d0);
+                go1 += 2.0f * (lam0.re * (float)cth.d1 + lam1.re * (float)cph.d1);
+                go2 += 2.0f * (lam0.re * (float)cth.d2 + lam1.re * (float)cph.d2);
+            }
+        }
+    }
+    // ---- deterministic reduction: wave butterfly, then waves in order
+    __shared__ double red[kBwdBlock / 64][2 * kMatChunk + 3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v[2 * kMatChunk + 3];
+#pragma unroll
+    for (int j = 0; j < kMatChunk; j++) {
+        v[j] = (double)ge[j];
+        v[kMatChunk + j] = (double)gs[j];
+    }
+    v[2 * kMatChunk] = go0;
+    v[2 * kMatChunk + 1] = go1;
+    v[2 * kMatChunk + 2] = go2;
+#pragma unroll
+    for (int j = 0; j < 2 * kMatChunk + 3; j++) {
+        double s = wave_sum_d(v[j]);
+        if (lane == 0) red[wave][j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kMatChunk + 3) {
+        double s = 0.0;
+        for (int w = 0; w < kBwdBlock / 64; w++) s += red[w][threadIdx.x];
+        a.partials[(int64_t)blockIdx.x * (2 * kMatChunk + 3) + threadIdx.x] = s;
+    }
+}
+
+// Sum the per-block partials in block order and scatter them to the outputs.
+__global__ void k_backward_final(const double* __restrict__ partials, int nblocks, int n_mat, int mat0,
+                                 int write_orient, float* __restrict__ g_eps, float* __restrict__ g_sig,
+                                 float* __restrict__ g_orient) {
+    const int P = 2 * kMatChunk + 3;
+    int j = threadIdx.x;
+    if (j >= P) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; b++) s += partials[(int64_t)b * P + j];
+    if (j < kMatChunk) {
+        int m = mat0 + j;
+        if (m < n_mat && g_eps) g_eps[m] = (float)s;
+    } else if (j < 2 * kMatChunk) {
+        int m = mat0 + j - kMatChunk;
+        if (m < n_mat && g_sig) g_sig[m] = (float)s;
+    } else if (write_orient && g_orient) {
+        g_orient[j - 2 * kMatChunk] = (float)s;
+    }
+}
+
+}  // namespace
+
+rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
+    rt_scene* s = const_cast<rt_scene*>(b.scene);
+    const int P = 2 * kMatChunk + 3;
+    size_t need = sizeof(double) * (size_t)kBwdBlocks * P;
+    if (s->grad_ws_bytes < need) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(s->grad_ws);
+        s->grad_ws = nullptr;
+        s->grad_ws_bytes = 0;
+        hipError_t e = hipMalloc(&s->grad_ws, need);
+        if (e != hipSuccess) return rt_hip_fail(e, "rt_radio_map_backward: workspace");
+        s->grad_ws_bytes = need;
+    }
+    BwdArgs a;
+    a.seg = b.tape->seg;
+    a.nseg = b.tape->nseg;
+    a.n = b.tape->n_rays;
+    a.ray_begin = b.ray_begin;
+    a.normals = s->normals;
+    a.eps_r = b.eps_r;
+    a.sigma = b.sigma;
+    a.tx = b.tx;
+    a.pl = b.pl;
+    a.npol = b.tx.pol == RT_POL_DUAL ? 2 : 1;
+    a.grad_map = b.grad_map;
+    a.map_stride = (int64_t)b.pl.W * b.pl.H;
+    a.n_mat = s->n_mat;
+    a.P = P;
+    a.partials = (double*)s->grad_ws;
+    for (int m0 = 0; m0 < std::max(1, s->n_mat); m0 += kMatChunk) {
+        a.mat0 = m0;
+        a.write_orient = (m0 == 0) ? 1 : 0;
+        hipLaunchKernelGGL(k_backward, dim3(kBwdBlocks), dim3(kBwdBlock), 0, st, a);
+        hipLaunchKernelGGL(k_backward_final, dim3(1), dim3(64), 0, st, (const double*)s->grad_ws, kBwdBlocks,
+                           s->n_mat, m0, a.write_orient, b.grad_eps, b.grad_sigma, b.grad_orient);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rt_hip_fail(e, "backward launch");
+    return RT_OK;
 }
