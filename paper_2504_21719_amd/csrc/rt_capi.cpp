@@ -94,7 +94,11 @@ extern "C" rt_status rt_scene_destroy(rt_scene* s) {
     (void)hipFree(s->spill);
     (void)hipFree(s->tx_desc);
     (void)hipFree(s->grad_ws);
+    (void)hipFree(s->geom_ws);
+    (void)hipFree(s->bgrad_ws);
     if (s->tx_desc_host) (void)hipHostFree(s->tx_desc_host);
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     delete s;
     return RT_OK;
 }
@@ -377,32 +381,16 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     if ((r = check_params(&p, &b, &e)) != RT_OK) return r;
     if ((r = check_device(scene)) != RT_OK) return r;
     rt_scene* s = const_cast<rt_scene*>(scene);
+    hipStream_t hs = (hipStream_t)stream;
     // order transmitters largest budget first so that the long lattices start early
     std::vector<int> order(n_tx);
     for (int i = 0; i < n_tx; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rays_per_tx[x] > rays_per_tx[y]; });
-    size_t need = sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1) + sizeof(int32_t) * n_tx + 256;
-    if (s->tx_desc_bytes < need) {
-        hipStream_t hs = (hipStream_t)stream;
-        (void)hipStreamSynchronize(hs);
-        (void)hipFree(s->tx_desc);
-    (void)hipFree(s->grad_ws);
-        if (s->tx_desc_host) (void)hipHostFree(s->tx_desc_host);
-        s->tx_desc = nullptr;
-        s->tx_desc_host = nullptr;
-        s->tx_desc_bytes = 0;
-        hipError_t he = hipMalloc(&s->tx_desc, need);
-        if (he == hipSuccess) he = hipHostMalloc(&s->tx_desc_host, need, hipHostMallocDefault);
-        if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: staging allocation");
-        s->tx_desc_bytes = need;
-    } else {
-        // the pinned staging buffer may still be read by a previous call's copy
-        (void)hipStreamSynchronize((hipStream_t)stream);
-    }
-    char* hb = (char*)s->tx_desc_host;
-    TxDesc* hd = (TxDesc*)hb;
-    int64_t* hp = (int64_t*)(hb + sizeof(TxDesc) * n_tx);
-    int32_t* hslot = (int32_t*)(hb + sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1));
+    size_t need = sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1) + sizeof(int32_t) * n_tx;
+    std::vector<char> hb(need, 0);
+    TxDesc* hd = (TxDesc*)hb.data();
+    int64_t* hp = (int64_t*)(hb.data() + sizeof(TxDesc) * n_tx);
+    int32_t* hslot = (int32_t*)(hb.data() + sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1));
     int64_t total = 0;
     for (int i = 0; i < n_tx; i++) {
         int t = order[i];
@@ -412,18 +400,12 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
         total += rays_per_tx[t];
     }
     hp[n_tx] = total;
-    hipError_t he = hipMemcpyAsync(s->tx_desc, hb, need, hipMemcpyHostToDevice, (hipStream_t)stream);
-    if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: descriptor upload");
-    char* db = (char*)s->tx_desc;
     BatchLaunch bl{};
     bl.scene = scene;
     bl.eps_r = materials.eps_r;
     bl.sigma = materials.sigma;
     bl.n_samples = n_samples;
     bl.n_tx = n_tx;
-    bl.tx_dev = (const TxDesc*)db;
-    bl.prefix_dev = (const int64_t*)(db + sizeof(TxDesc) * n_tx);
-    bl.tx_slot_dev = (const int32_t*)(db + sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1));
     bl.total_rays = total;
     fill_plane(plane, params->freq_hz, &bl.pl);
     bl.L = params->max_depth;
@@ -432,7 +414,80 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     bl.maps = out_maps;
     bl.grad_maps = grad_maps;
     bl.grads = grads;
-    return rt_launch_batched(bl, (hipStream_t)stream);
+    // identity of the whole step: descriptors, pointers and sizes
+    uint64_t key = 1469598103934665603ull;
+    key = mix(key, hb.data(), hb.size());
+    const void* ptrs[5] = {materials.eps_r, materials.sigma, out_maps, grad_maps, grads};
+    key = mix(key, ptrs, sizeof(ptrs));
+    key = mix(key, plane, sizeof(rt_plane));
+    key = mix(key, &bl.L, sizeof(bl.L));
+    key = mix(key, &bl.t_min, sizeof(bl.t_min));
+    key = mix(key, &bl.block, sizeof(bl.block));
+    key = mix(key, &n_samples, sizeof(n_samples));
+    key = mix(key, &params->freq_hz, sizeof(double));
+    key = mix(key, &s->tuned_deposit, sizeof(int));
+    const bool use_graph = getenv("RTMAP_NO_GRAPH") == nullptr;
+    if (use_graph && s->graph_exec && s->graph_key == key) {
+        hipError_t he = hipGraphLaunch(s->graph_exec, hs);
+        if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: graph launch");
+        return RT_OK;
+    }
+    // descriptors: pinned staging, then one upload on the caller's stream
+    if (s->tx_desc_bytes < need) {
+        (void)hipStreamSynchronize(hs);
+        (void)hipFree(s->tx_desc);
+        if (s->tx_desc_host) (void)hipHostFree(s->tx_desc_host);
+        s->tx_desc = nullptr;
+        s->tx_desc_host = nullptr;
+        s->tx_desc_bytes = 0;
+        hipError_t he = hipMalloc(&s->tx_desc, need);
+        if (he == hipSuccess) he = hipHostMalloc(&s->tx_desc_host, need, hipHostMallocDefault);
+        if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: staging allocation");
+        s->tx_desc_bytes = need;
+    } else {
+        // the staging buffer may still be read by the previous call's upload
+        (void)hipStreamSynchronize(hs);
+    }
+    memcpy(s->tx_desc_host, hb.data(), need);
+    hipError_t he = hipMemcpyAsync(s->tx_desc, s->tx_desc_host, need, hipMemcpyHostToDevice, hs);
+    if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: descriptor upload");
+    char* db = (char*)s->tx_desc;
+    bl.tx_dev = (const TxDesc*)db;
+    bl.prefix_dev = (const int64_t*)(db + sizeof(TxDesc) * n_tx);
+    bl.tx_slot_dev = (const int32_t*)(db + sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1));
+    r = rt_batched_workspace(bl, hs);
+    if (r != RT_OK) return r;
+    if (!use_graph) return rt_launch_batched(bl, hs);
+    // capture the step once on a library stream, then replay it on the caller's
+    if (!s->capture_stream) {
+        he = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
+        if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: capture stream");
+    }
+    if (s->graph_exec) {
+        (void)hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+        s->graph_key = 0;
+    }
+    hipGraph_t graph = nullptr;
+    he = hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: begin capture");
+    r = rt_launch_batched(bl, s->capture_stream);
+    hipError_t he2 = hipStreamEndCapture(s->capture_stream, &graph);
+    if (r != RT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (he2 != hipSuccess) return rt_hip_fail(he2, "rt_radio_map_batched: end capture");
+    he = hipGraphInstantiate(&s->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (he != hipSuccess) {
+        s->graph_exec = nullptr;
+        return rt_hip_fail(he, "rt_radio_map_batched: instantiate");
+    }
+    s->graph_key = key;
+    he = hipGraphLaunch(s->graph_exec, hs);
+    if (he != hipSuccess) return rt_hip_fail(he, "rt_radio_map_batched: graph launch");
+    return RT_OK;
 }
 
 // ---------------------------------------------------------------- autotune

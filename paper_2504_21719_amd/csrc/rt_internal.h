@@ -52,10 +52,19 @@ struct rt_scene {
     // backward workspace: per-block FP64 partial sums
     void* grad_ws = nullptr;
     size_t grad_ws_bytes = 0;
+    // batched workspaces: geometry tape of every ray, FP64 gradient sums
+    void* geom_ws = nullptr;
+    size_t geom_ws_bytes = 0;
+    void* bgrad_ws = nullptr;
+    size_t bgrad_ws_bytes = 0;
     // batched-call staging (device copies of per-transmitter descriptors)
     void* tx_desc = nullptr;
     size_t tx_desc_bytes = 0;
     void* tx_desc_host = nullptr;  // pinned host staging
+    // captured batched step, replayed while the call key repeats
+    uint64_t graph_key = 0;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
 };
 
 // Tape: per segment (l, ray) four float4 records, stored [l][g][ray] for
@@ -161,6 +170,13 @@ struct BatchLaunch {
     const float* grad_maps;  // [n_tx][S][H][W] or null
     float* grads;            // [n_tx][S][2 n_mat + 3] or null
 };
+rt_status rt_batched_workspace(const BatchLaunch& b, hipStream_t st);
 rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st);
+
+rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const float* sigma, const PlaneDesc& pl,
+                                  int L, float t_min, int block, int deposit, const TxDesc* txs,
+                                  const int64_t* prefix, const int32_t* slots, int n_tx, int64_t total_rays,
+                                  bool geom_only, float* maps, int64_t slot_stride, int64_t zero_floats,
+                                  float4* geom_seg, int* geom_nseg, hipStream_t st);
 
 int rt_persistent_blocks(int block, int device);

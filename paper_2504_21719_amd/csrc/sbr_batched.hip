@@ -1,6 +1,314 @@
-// sbr_batched.hip -- batched transmitters / material samples (placeholder).
-#include "rt_internal.h"
+// sbr_batched.hip -- many transmitters and many material samples per call.
+//
+// Work over all transmitters is one index space: transmitter t owns the
+// global ray indices [prefix[t], prefix[t+1]) (ordered largest budget first,
+// so long lattices start early), and lanes of the persistent kernel pull
+// indices from one device counter, whatever transmitter they belong to.
+//
+//  * one material set, forward only: a single persistent launch traces,
+//    reflects and deposits into the map of each ray's transmitter;
+//  * several material samples and/or gradients: the persistent launch traces
+//    every ray once and records its geometry (hit slot, crossed cell,
+//    direction and basis per segment).  The hit sequence does not depend on
+//    the materials or the antenna, so one traversal serves every sample.  A
+//    second kernel runs one thread per (ray, sample): it propagates the field
+//    through the recorded bounces with that sample's permittivities
+//    (eq. fresnel_vac, eq. eta), deposits into the sample's map, and, given
+//    upstream gradients, runs the same reverse sweep as the plain adjoint
+//    (dJ/dp = 2 Re(lambda^H dR/dp E)) with the fields of the forward pass
+//    kept in registers.
+#include <hip/hip_runtime.h>
 
-rt_status rt_launch_batched(const BatchLaunch&, hipStream_t) {
-    return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: not built yet");
+#include <algorithm>
+
+#include "sbr_common.h"
+
+using namespace rtd;
+
+namespace {
+
+constexpr int kMaxSeg = 9;      // register-resident fields for L <= 8 in gradient mode
+constexpr int kMaxMat = 8;      // materials with gradients in batched mode
+constexpr int kSampBlock = 256;
+
+struct SampArgs {
+    const float4* geom;     // [l][2][total]
+    const int* nseg;        // [total]
+    int64_t total;
+    const TxDesc* txs;
+    const int64_t* prefix;
+    const int32_t* slots;
+    int n_tx;
+    int S;
+    const float4* normals;
+    const float* eps_r;     // [S][n_mat]
+    const float* sigma;
+    int n_mat;
+    PlaneDesc pl;
+    float* maps;            // [n_tx][S][H][W]
+    const float* grad_maps; // [n_tx][S][H][W] or null
+    double* gws;            // [n_tx][S][P] FP64 accumulators (gradient mode)
+    int P;                  // 2 n_mat + 3
+};
+
+__device__ __forceinline__ int find_tx_s(const int64_t* __restrict__ prefix, int n_tx, int64_t g) {
+    int lo = 0, hi = n_tx;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double wsum(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+template <bool GRAD>
+__global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
+    const int s = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t HW = (int64_t)a.pl.W * a.pl.H;
+    const int64_t T = a.total;
+    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < T; g0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = g0 + threadIdx.x;
+        const bool valid = g < T;
+        int slot_out = -1;
+        float ge[kMaxMat], gs[kMaxMat], go[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < kMaxMat; j++) {
+            ge[j] = 0.f;
+            gs[j] = 0.f;
+        }
+        if (valid) {
+            const int t = find_tx_s(a.prefix, a.n_tx, g);
+            const TxDesc td = a.txs[t];
+            slot_out = a.slots[t];
+            const int64_t n = g - a.prefix[t];
+            const int ns = a.nseg[g];
+            const float* eps = a.eps_r + (int64_t)s * a.n_mat;
+            const float* sig = a.sigma + (int64_t)s * a.n_mat;
+            float* map = a.maps + ((int64_t)slot_out * a.S + s) * HW;
+            Launch Lr = fib_launch(n, td.n_rays);
+            dual3 cth, cph;
+            if (GRAD) {
+                tx_pattern<dual3>(Lr, dual3{td.yaw, 1.0, 0.0, 0.0}, dual3{td.pitch, 0.0, 1.0, 0.0},
+                                  dual3{td.roll, 0.0, 0.0, 1.0}, td.pattern, td.q, td.pol == 1 ? 1 : 0, cth, cph);
+            } else {
+                double a0, a1;
+                tx_pattern<double>(Lr, td.yaw, td.pitch, td.roll, td.pattern, td.q, td.pol == 1 ? 1 : 0, a0, a1);
+                cth = mkd(a0);
+                cph = mkd(a1);
+            }
+            cf e0 = {(float)cth.v, 0.f}, e1 = {(float)cph.v, 0.f};
+            cf E0[kMaxSeg], E1[kMaxSeg];
+            // forward: deposit every crossing, propagate E through the bounce
+            auto step = [&](int l) {
+                const float4* sp = a.geom + (int64_t)l * 2 * T + g;
+                float4 s0 = sp[0], s1 = sp[T];
+                int cell = __float_as_int(s1.w);
+                if (cell >= 0) {
+                    float w = td.kappa / fabsf(s0.z) * (cabs2(e0) + cabs2(e1));
+                    unsafeAtomicAdd(map + cell, w);
+                }
+                if (l + 1 < ns) {
+                    int hs = __float_as_int(s0.w);
+                    float4 nm = a.normals[hs];
+                    int mat = __float_as_int(nm.w);
+                    Bounce b = bounce_geometry(f3(s0.x, s0.y, s0.z), f3(s1.x, s1.y, s1.z), f3(nm.x, nm.y, nm.z));
+                    Fresnel F = fresnel<false>(b.c, cf{eps[mat], -sig[mat] * a.pl.inv_eps0_omega});
+                    cf u0 = cadd(cscale(e0, b.w00), cscale(e1, b.w01));
+                    cf u1 = cadd(cscale(e0, b.w10), cscale(e1, b.w11));
+                    e0 = cmul(F.rperp, u0);
+                    e1 = cmul(cf{-F.rpar.re, -F.rpar.im}, u1);
+                }
+            };
+            if constexpr (GRAD) {
+                // the fields of every segment stay in registers for the reverse sweep
+#pragma unroll
+                for (int l = 0; l < kMaxSeg; l++) {
+                    if (l >= ns) break;
+                    E0[l] = e0;
+                    E1[l] = e1;
+                    step(l);
+                }
+            } else {
+                for (int l = 0; l < ns; l++) step(l);
+            }
+            if (GRAD) {
+                const float* G = a.grad_maps + ((int64_t)slot_out * a.S + s) * HW;
+                cf lam0 = {0, 0}, lam1 = {0, 0};
+#pragma unroll
+                for (int l = kMaxSeg - 1; l >= 0; l--) {
+                    if (l >= ns) continue;
+                    const float4* sp = a.geom + (int64_t)l * 2 * T + g;
+                    float4 s0 = sp[0], s1 = sp[T];
+                    int cell = __float_as_int(s1.w);
+                    if (cell >= 0) {
+                        float al = G[cell] * td.kappa / fabsf(s0.z);
+                        lam0 = cadd(lam0, cscale(E0[l], al));
+                        lam1 = cadd(lam1, cscale(E1[l], al));
+                    }
+                    if (l == 0) continue;
+                    const float4* qp = a.geom + (int64_t)(l - 1) * 2 * T + g;
+                    float4 p0 = qp[0], p1 = qp[T];
+                    int hs = __float_as_int(p0.w);
+                    float4 nm = a.normals[hs];
+                    int mat = __float_as_int(nm.w);
+                    Bounce b = bounce_geometry(f3(p0.x, p0.y, p0.z), f3(p1.x, p1.y, p1.z), f3(nm.x, nm.y, nm.z));
+                    Fresnel F = fresnel<true>(b.c, cf{eps[mat], -sig[mat] * a.pl.inv_eps0_omega});
+                    cf u0 = cadd(cscale(E0[l - 1], b.w00), cscale(E1[l - 1], b.w01));
+                    cf u1 = cadd(cscale(E0[l - 1], b.w10), cscale(E1[l - 1], b.w11));
+                    cf z = csub(cmulc(lam0, cmul(F.drperp, u0)), cmulc(lam1, cmul(F.drpar, u1)));
+#pragma unroll
+                    for (int jj = 0; jj < kMaxMat; jj++) {
+                        if (jj == mat) {
+                            ge[jj] += 2.0f * z.re;
+                            gs[jj] += 2.0f * z.im * a.pl.inv_eps0_omega;
+                        }
+                    }
+                    cf v0 = cmulc(F.rperp, lam0);
+                    cf v1 = cmulc(F.rpar, lam1);
+                    v1 = cf{-v1.re, -v1.im};
+                    lam0 = cadd(cscale(v0, b.w00), cscale(v1, b.w10));
+                    lam1 = cadd(cscale(v0, b.w01), cscale(v1, b.w11));
+                }
+                go[0] = 2.0f * (lam0.re * (float)cth.d0 + lam1.re * (float)cph.d0);
+                go[1] = 2.0f * (lam0.re * (float)cth.d1 + lam1.re * (float)cph.d1);
+                go[2] = 2.0f * (lam0.re * (float)cth.d2 + lam1.re * (float)cph.d2);
+            }
+        }
+        if (GRAD) {
+            // peel the lanes of each transmitter slot (usually one per wave),
+            // sum them with a butterfly, one FP64 atomic per parameter
+            unsigned long long pend = __ballot(valid);
+            bool done = !valid;
+            while (pend) {
+                int leader = __ffsll((long long)pend) - 1;
+                int ls = __shfl(slot_out, leader);
+                bool mine = !done && slot_out == ls;
+                unsigned long long grp = __ballot(mine);
+                double* dst = a.gws + ((int64_t)ls * a.S + s) * a.P;
+                for (int j = 0; j < a.n_mat && j < kMaxMat; j++) {
+                    double v = wsum(mine ? (double)ge[j] : 0.0);
+                    double u = wsum(mine ? (double)gs[j] : 0.0);
+                    if (lane == leader) {
+                        unsafeAtomicAdd(dst + j, v);
+                        unsafeAtomicAdd(dst + a.n_mat + j, u);
+                    }
+                }
+                for (int j = 0; j < 3; j++) {
+                    double v = wsum(mine ? (double)go[j] : 0.0);
+                    if (lane == leader) unsafeAtomicAdd(dst + 2 * a.n_mat + j, v);
+                }
+                if (mine) done = true;
+                pend &= ~grp;
+            }
+        }
+    }
+}
+
+__global__ void k_zero_d(double* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void k_grads_out(const double* __restrict__ ws, float* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)ws[i];
+}
+
+}  // namespace
+
+// Grow the batched workspaces (never called while a graph is being captured).
+rt_status rt_batched_workspace(const BatchLaunch& b, hipStream_t st) {
+    rt_scene* s = const_cast<rt_scene*>(b.scene);
+    const bool grad = b.grad_maps != nullptr;
+    if (grad && (b.L + 1 > kMaxSeg || s->n_mat > kMaxMat))
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: gradients need max_depth <= 8 and <= 8 materials");
+    if (b.n_samples == 1 && !grad) return RT_OK;
+    size_t need = sizeof(float4) * 2 * (size_t)(b.L + 1) * (size_t)b.total_rays + sizeof(int) * (size_t)b.total_rays;
+    if (s->geom_ws_bytes < need) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(s->geom_ws);
+        s->geom_ws = nullptr;
+        s->geom_ws_bytes = 0;
+        hipError_t e = hipMalloc(&s->geom_ws, need);
+        if (e != hipSuccess) return rt_hip_fail(e, "rt_radio_map_batched: geometry tape");
+        s->geom_ws_bytes = need;
+    }
+    size_t gneed = sizeof(double) * (size_t)b.n_tx * b.n_samples * (2 * s->n_mat + 3);
+    if (grad && s->bgrad_ws_bytes < gneed) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(s->bgrad_ws);
+        s->bgrad_ws = nullptr;
+        s->bgrad_ws_bytes = 0;
+        hipError_t e = hipMalloc(&s->bgrad_ws, gneed);
+        if (e != hipSuccess) return rt_hip_fail(e, "rt_radio_map_batched: gradient workspace");
+        s->bgrad_ws_bytes = gneed;
+    }
+    return RT_OK;
+}
+
+// Queue the batched work on `st`.  Allocates nothing (rt_batched_workspace
+// must have run), so the sequence can be captured into a HIP graph.
+rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
+    rt_scene* s = const_cast<rt_scene*>(b.scene);
+    const int64_t HW = (int64_t)b.pl.W * b.pl.H;
+    const int S = b.n_samples;
+    const bool grad = b.grad_maps != nullptr;
+    const int deposit = s->tuned_deposit ? s->tuned_deposit : RT_DEPOSIT_ATOMIC;
+    if (S == 1 && !grad) {
+        return rt_launch_forward_multi(s, b.eps_r, b.sigma, b.pl, b.L, b.t_min, b.block, deposit, b.tx_dev,
+                                       b.prefix_dev, b.tx_slot_dev, b.n_tx, b.total_rays, false, b.maps, HW,
+                                       HW * b.n_tx, nullptr, nullptr, st);
+    }
+    size_t need = sizeof(float4) * 2 * (size_t)(b.L + 1) * (size_t)b.total_rays + sizeof(int) * (size_t)b.total_rays;
+    const int P = 2 * s->n_mat + 3;
+    if (s->geom_ws_bytes < need || (grad && s->bgrad_ws_bytes < sizeof(double) * (size_t)b.n_tx * S * P))
+        return rt_fail(RT_EINVAL, "rt_radio_map_batched: workspace not prepared");
+    float4* geom = (float4*)s->geom_ws;
+    int* nseg = (int*)((char*)s->geom_ws + sizeof(float4) * 2 * (size_t)(b.L + 1) * (size_t)b.total_rays);
+    if (grad) {
+        int64_t ng = (int64_t)b.n_tx * S * P;
+        hipLaunchKernelGGL(k_zero_d, dim3((unsigned)std::min<int64_t>(1024, (ng + 255) / 256)), dim3(256), 0, st,
+                           (double*)s->bgrad_ws, ng);
+    }
+    rt_status r = rt_launch_forward_multi(s, b.eps_r, b.sigma, b.pl, b.L, b.t_min, b.block, deposit, b.tx_dev,
+                                          b.prefix_dev, b.tx_slot_dev, b.n_tx, b.total_rays, true, b.maps, HW,
+                                          HW * b.n_tx * S, geom, nseg, st);
+    if (r != RT_OK) return r;
+    SampArgs a;
+    a.geom = geom;
+    a.nseg = nseg;
+    a.total = b.total_rays;
+    a.txs = b.tx_dev;
+    a.prefix = b.prefix_dev;
+    a.slots = b.tx_slot_dev;
+    a.n_tx = b.n_tx;
+    a.S = S;
+    a.normals = s->normals;
+    a.eps_r = b.eps_r;
+    a.sigma = b.sigma;
+    a.n_mat = s->n_mat;
+    a.pl = b.pl;
+    a.maps = b.maps;
+    a.grad_maps = b.grad_maps;
+    a.gws = (double*)s->bgrad_ws;
+    a.P = P;
+    unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65535, (b.total_rays + kSampBlock - 1) / kSampBlock));
+    if (b.total_rays > 0) {
+        if (grad) hipLaunchKernelGGL(k_samples<true>, dim3(bx, S), dim3(kSampBlock), 0, st, a);
+        else hipLaunchKernelGGL(k_samples<false>, dim3(bx, S), dim3(kSampBlock), 0, st, a);
+    }
+    if (grad) {
+        int64_t ng = (int64_t)b.n_tx * S * P;
+        hipLaunchKernelGGL(k_grads_out, dim3((unsigned)std::min<int64_t>(1024, (ng + 255) / 256)), dim3(256), 0, st,
+                           (const double*)s->bgrad_ws, b.grads, ng);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rt_hip_fail(e, "batched launch");
+    return RT_OK;
 }

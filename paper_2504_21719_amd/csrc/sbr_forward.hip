@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "sbr_common.h"
 
@@ -54,7 +55,30 @@ struct FwdArgs {
     int* spill;
     int64_t spill_stride;
     int spill_depth;
+    int tape_groups;         // float4 records per segment on the tape (4, or 2 = geometry only)
+    // several transmitters (MODE_MULTI, MODE_GEOM): device tables
+    const TxDesc* txs;       // ordered largest budget first
+    const int64_t* prefix;   // [n_tx + 1] exclusive prefix of the budgets
+    const int32_t* slots;    // output slot of each ordered transmitter
+    int n_tx;
+    int64_t slot_stride;     // floats between the maps of consecutive slots
 };
+
+// Kernel modes: one transmitter; several transmitters with one material set
+// (deposits into per-transmitter maps); several transmitters, geometry only
+// (records hit slots, cells, directions and bases for a later field pass).
+enum { MODE_SINGLE = 0, MODE_MULTI = 1, MODE_GEOM = 2 };
+
+// Index of the transmitter whose ray range holds global ray g.
+__device__ __forceinline__ int find_tx(const int64_t* __restrict__ prefix, int n_tx, int64_t g) {
+    int lo = 0, hi = n_tx;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -149,7 +173,7 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
     return slot_best;
 }
 
-template <bool BRUTE>
+template <bool BRUTE, int MODE>
 __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
     extern __shared__ int s_stack[];
     const int lstride = blockDim.x;
@@ -171,6 +195,8 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
     float3 o = f3(0, 0, 0), k = f3(0, 0, 0), es = f3(0, 0, 0);
     cf Ta = {1, 0}, Tb = {0, 0}, Tc = {0, 0}, Td = {1, 0};
     float c0t = 0.f, c0p = 0.f, c1t = 0.f, c1p = 0.f;   // C_T per polarisation
+    float kap = a.tx.kappa;   // lambda^2 / (4 pi N_S |M|) of the lane's transmitter
+    float* mapb = a.map;      // map of the lane's transmitter
 
     while (true) {
         // ---- refill lanes without a ray from the work counter
@@ -187,23 +213,35 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
                     unsigned long long my = base + (unsigned long long)__popcll(need & lt);
                     if (my < (unsigned long long)a.n_work) {
                         rid = (int64_t)my;
-                        const int64_t n = a.ray_begin + rid;
-                        Launch Lr = fib_launch(n, a.tx.n_rays);
-                        double ct0, cp0;
-                        tx_pattern<double>(Lr, a.tx.yaw, a.tx.pitch, a.tx.roll, a.tx.pattern, a.tx.q,
-                                           a.tx.pol == 1 ? 1 : 0, ct0, cp0);
-                        c0t = (float)ct0;
-                        c0p = (float)cp0;
-                        if (a.npol == 2) {
-                            double ct1, cp1;
-                            tx_pattern<double>(Lr, a.tx.yaw, a.tx.pitch, a.tx.roll, a.tx.pattern, a.tx.q, 1,
-                                               ct1, cp1);
-                            c1t = (float)ct1;
-                            c1p = (float)cp1;
+                        int64_t n;
+                        TxDesc td;
+                        if (MODE == MODE_SINGLE) {
+                            n = a.ray_begin + rid;
+                            td = a.tx;
+                        } else {
+                            int t = find_tx(a.prefix, a.n_tx, rid);
+                            n = rid - a.prefix[t];
+                            td = a.txs[t];
+                            kap = td.kappa;
+                            mapb = a.map + (int64_t)a.slots[t] * a.slot_stride;
+                        }
+                        Launch Lr = fib_launch(n, td.n_rays);
+                        if (MODE != MODE_GEOM) {
+                            double ct0, cp0;
+                            tx_pattern<double>(Lr, td.yaw, td.pitch, td.roll, td.pattern, td.q, td.pol == 1 ? 1 : 0,
+                                               ct0, cp0);
+                            c0t = (float)ct0;
+                            c0p = (float)cp0;
+                            if (a.npol == 2) {
+                                double ct1, cp1;
+                                tx_pattern<double>(Lr, td.yaw, td.pitch, td.roll, td.pattern, td.q, 1, ct1, cp1);
+                                c1t = (float)ct1;
+                                c1p = (float)cp1;
+                            }
                         }
                         k = f3((float)Lr.kx, (float)Lr.ky, (float)Lr.kz);
                         es = f3((float)Lr.tx, (float)Lr.ty, (float)Lr.tz);
-                        o = f3(a.tx.pos[0], a.tx.pos[1], a.tx.pos[2]);
+                        o = f3(td.pos[0], td.pos[1], td.pos[2]);
                         Ta = cf{1, 0};
                         Tb = cf{0, 0};
                         Tc = cf{0, 0};
@@ -252,7 +290,11 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
                     if (fx >= 0.0f && fy >= 0.0f && fx < (float)W && fy < (float)H) {
                         int i = min((int)fx, W - 1), j = min((int)fy, H - 1);
                         cell = j * W + i;
-                        float g = a.tx.kappa / fabsf(k.z);
+                        st_cross++;
+                    }
+                }
+                if (MODE != MODE_GEOM && cell >= 0) {
+                        float g = kap / fabsf(k.z);
                         cf e0 = cadd(cscale(Ta, c0t), cscale(Tb, c0p));
                         cf e1 = cadd(cscale(Tc, c0t), cscale(Td, c0p));
                         w0 = g * (cabs2(e0) + cabs2(e1));
@@ -261,8 +303,6 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
                             cf f1 = cadd(cscale(Tc, c1t), cscale(Td, c1p));
                             w1 = g * (cabs2(f0) + cabs2(f1));
                         }
-                        st_cross++;
-                    }
                 }
             }
             if (a.hits) a.hits[rid * stride + l] = hit_id;
@@ -270,16 +310,20 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
             if (a.weights) a.weights[rid * stride + l] = w0;
             if (a.tape_seg) {
                 const int64_t tn = a.tape_n;
-                float4* ts = a.tape_seg + (int64_t)l * 4 * tn + rid;
+                float4* ts = a.tape_seg + (int64_t)l * a.tape_groups * tn + rid;
                 ts[0] = make_float4(k.x, k.y, k.z, __int_as_float(slot));
                 ts[tn] = make_float4(es.x, es.y, es.z, __int_as_float(cell));
-                ts[2 * tn] = make_float4(Ta.re, Ta.im, Tb.re, Tb.im);
-                ts[3 * tn] = make_float4(Tc.re, Tc.im, Td.re, Td.im);
+                if (MODE != MODE_GEOM) {
+                    ts[2 * tn] = make_float4(Ta.re, Ta.im, Tb.re, Tb.im);
+                    ts[3 * tn] = make_float4(Tc.re, Tc.im, Td.re, Td.im);
+                }
             }
         }
 
         // ---- deposit (all lanes reconverged here)
-        if (a.deposit == 2) {
+        if (MODE == MODE_GEOM) {
+            // fields are computed later, per material sample
+        } else if (a.deposit == 2) {
             unsigned long long pend = __ballot(cell >= 0);
             bool done = cell < 0;
             while (pend) {
@@ -291,15 +335,15 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
                 float v1 = 0.0f;
                 if (a.npol == 2) v1 = wave_sum(mine ? w1 : 0.0f);
                 if (lane == leader) {
-                    unsafeAtomicAdd(a.map + lc, v0);
-                    if (a.npol == 2) unsafeAtomicAdd(a.map + a.map_stride + lc, v1);
+                    unsafeAtomicAdd(mapb + lc, v0);
+                    if (a.npol == 2) unsafeAtomicAdd(mapb + a.map_stride + lc, v1);
                 }
                 if (mine) done = true;
                 pend &= ~grp;
             }
         } else if (cell >= 0) {
-            unsafeAtomicAdd(a.map + cell, w0);
-            if (a.npol == 2) unsafeAtomicAdd(a.map + a.map_stride + cell, w1);
+            unsafeAtomicAdd(mapb + cell, w0);
+            if (a.npol == 2) unsafeAtomicAdd(mapb + a.map_stride + cell, w1);
         }
 
         // ---- reflect, or end the ray
@@ -311,18 +355,20 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
                 float4 nm = a.normals[slot];
                 int mat = __float_as_int(nm.w);
                 Bounce b = bounce_geometry(k, es, f3(nm.x, nm.y, nm.z));
-                cf eta = cf{a.eps_r[mat], -a.sigma[mat] * a.pl.inv_eps0_omega};
-                Fresnel F = fresnel<false>(b.c, eta);
-                // T <- diag(r_perp, -r_par) W T
-                cf na = cadd(cscale(Ta, b.w00), cscale(Tc, b.w01));
-                cf nb = cadd(cscale(Tb, b.w00), cscale(Td, b.w01));
-                cf nc = cadd(cscale(Ta, b.w10), cscale(Tc, b.w11));
-                cf nd = cadd(cscale(Tb, b.w10), cscale(Td, b.w11));
-                Ta = cmul(F.rperp, na);
-                Tb = cmul(F.rperp, nb);
-                cf mr = cf{-F.rpar.re, -F.rpar.im};
-                Tc = cmul(mr, nc);
-                Td = cmul(mr, nd);
+                if (MODE != MODE_GEOM) {
+                    cf eta = cf{a.eps_r[mat], -a.sigma[mat] * a.pl.inv_eps0_omega};
+                    Fresnel F = fresnel<false>(b.c, eta);
+                    // T <- diag(r_perp, -r_par) W T
+                    cf na = cadd(cscale(Ta, b.w00), cscale(Tc, b.w01));
+                    cf nb = cadd(cscale(Tb, b.w00), cscale(Td, b.w01));
+                    cf nc = cadd(cscale(Ta, b.w10), cscale(Tc, b.w11));
+                    cf nd = cadd(cscale(Tb, b.w10), cscale(Td, b.w11));
+                    Ta = cmul(F.rperp, na);
+                    Tb = cmul(F.rperp, nb);
+                    cf mr = cf{-F.rpar.re, -F.rpar.im};
+                    Tc = cmul(mr, nc);
+                    Td = cmul(mr, nd);
+                }
                 o = o + k * t_hit;
                 k = b.kr;
                 es = b.es_new;
@@ -370,22 +416,53 @@ int rt_persistent_blocks(int block, int device) {
     return cu[dev] * blocks_per_cu;
 }
 
-rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
-    const rt_scene* s = f.scene;
-    FwdArgs a;
+static void base_args(FwdArgs& a, const rt_scene* s, int block, const float* eps_r, const float* sigma,
+                      const PlaneDesc& pl, int L, float t_min) {
+    memset(&a, 0, sizeof(a));
     a.nodes = s->nodes;
     a.tris = s->tris;
     a.normals = s->normals;
     a.root = s->root;
     a.n_tri = (int)s->n_tri;
-    a.eps_r = f.eps_r;
-    a.sigma = f.sigma;
+    a.eps_r = eps_r;
+    a.sigma = sigma;
+    a.pl = pl;
+    a.L = L;
+    a.t_min = t_min;
+    a.counter = s->counters;
+    a.spill = s->spill;
+    a.tape_groups = 4;
+    a.npol = 1;
+}
+
+static rt_status size_spill(FwdArgs& a, const rt_scene* s, int block, int* blocks_out) {
+    int blocks = rt_persistent_blocks(block, s->device);
+    int64_t threads = (int64_t)blocks * block;
+    int64_t need_depth = std::max<int64_t>(0, (int64_t)s->depth + 1 - RT_STACK_LDS);
+    if ((int64_t)s->spill_entries < need_depth * threads)
+        return rt_fail(RT_EOVERFLOW, "traversal spill area too small for this launch");
+    a.spill_stride = threads;
+    a.spill_depth = (int)need_depth;
+    *blocks_out = blocks;
+    return RT_OK;
+}
+
+template <int MODE>
+static void launch_mode(const FwdArgs& a, int accel, int blocks, int block, hipStream_t st) {
+    size_t lds = sizeof(int) * RT_STACK_LDS * block;
+    if (accel == RT_ACCEL_BRUTE)
+        hipLaunchKernelGGL((k_forward<true, MODE>), dim3(blocks), dim3(block), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_forward<false, MODE>), dim3(blocks), dim3(block), lds, st, a);
+}
+
+rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
+    const rt_scene* s = f.scene;
+    FwdArgs a;
+    base_args(a, s, f.block, f.eps_r, f.sigma, f.pl, f.L, f.t_min);
     a.tx = f.tx;
-    a.pl = f.pl;
     a.ray_begin = f.ray_begin;
     a.n_work = f.ray_end - f.ray_begin;
-    a.L = f.L;
-    a.t_min = f.t_min;
     a.deposit = f.deposit;
     a.npol = f.tx.pol == RT_POL_DUAL ? 2 : 1;
     a.map = f.map;
@@ -397,33 +474,57 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
     a.cells = f.cells;
     a.weights = f.weights;
     a.stats = f.stats;
-    a.counter = s->counters;
-    const int block = f.block;
-    int blocks = rt_persistent_blocks(block, s->device);
-    int64_t threads = (int64_t)blocks * block;
-    int64_t need_depth = std::max<int64_t>(0, (int64_t)s->depth + 1 - RT_STACK_LDS);
-    if ((int64_t)s->spill_entries < need_depth * threads) {
-        // the spill area is owned by the scene and sized at build time for
-        // the largest supported block count; this cannot normally happen
-        return rt_fail(RT_EOVERFLOW, "traversal spill area too small for this launch");
-    }
-    a.spill = s->spill;
-    a.spill_stride = threads;
-    a.spill_depth = (int)need_depth;
+    int blocks = 0;
+    rt_status r = size_spill(a, s, f.block, &blocks);
+    if (r != RT_OK) return r;
     int64_t map_n = a.map_stride * a.npol;
     {
         int64_t zn = f.zero_map ? map_n : 0;
         int g = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (zn + 255) / 256));
         hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, f.map, zn, s->counters);
     }
-    if (a.n_work > 0) {
-        size_t lds = sizeof(int) * RT_STACK_LDS * block;
-        if (f.accel == RT_ACCEL_BRUTE)
-            hipLaunchKernelGGL(k_forward<true>, dim3(blocks), dim3(block), lds, st, a);
-        else
-            hipLaunchKernelGGL(k_forward<false>, dim3(blocks), dim3(block), lds, st, a);
-    }
+    if (a.n_work > 0) launch_mode<MODE_SINGLE>(a, f.accel, blocks, f.block, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rt_hip_fail(e, "forward launch");
+    return RT_OK;
+}
+
+// Several transmitters in one persistent launch.  geom_only = false: deposit
+// into maps[slot] (one material set, map stride slot_stride, maps zeroed
+// here); geom_only = true: write the geometry tape (2 records per segment).
+rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const float* sigma, const PlaneDesc& pl,
+                                  int L, float t_min, int block, int deposit, const TxDesc* txs,
+                                  const int64_t* prefix, const int32_t* slots, int n_tx, int64_t total_rays,
+                                  bool geom_only, float* maps, int64_t slot_stride, int64_t zero_floats,
+                                  float4* geom_seg, int* geom_nseg, hipStream_t st) {
+    FwdArgs a;
+    base_args(a, s, block, eps_r, sigma, pl, L, t_min);
+    a.ray_begin = 0;
+    a.n_work = total_rays;
+    a.deposit = deposit;
+    a.map = maps;
+    a.map_stride = (int64_t)pl.W * pl.H;
+    a.txs = txs;
+    a.prefix = prefix;
+    a.slots = slots;
+    a.n_tx = n_tx;
+    a.slot_stride = slot_stride;
+    if (geom_only) {
+        a.tape_seg = geom_seg;
+        a.tape_nseg = geom_nseg;
+        a.tape_n = total_rays;
+        a.tape_groups = 2;
+    }
+    int blocks = 0;
+    rt_status r = size_spill(a, s, block, &blocks);
+    if (r != RT_OK) return r;
+    int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (zero_floats + 255) / 256));
+    hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, maps, zero_floats, s->counters);
+    if (total_rays > 0) {
+        if (geom_only) launch_mode<MODE_GEOM>(a, RT_ACCEL_BVH, blocks, block, st);
+        else launch_mode<MODE_MULTI>(a, RT_ACCEL_BVH, blocks, block, st);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return rt_hip_fail(e, "batched forward launch");
     return RT_OK;
 }

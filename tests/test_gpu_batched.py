@@ -1,0 +1,120 @@
+"""Batched radio maps (rt_radio_map_batched) against per-call results.
+
+* several transmitters with uneven ray budgets in one persistent launch equal
+  the per-transmitter rt_radio_map maps (FP32 atomic order aside), so every
+  ray of every transmitter was traced exactly once;
+* several material samples (one traversal) equal per-sample rt_radio_map;
+* forward + backward for material samples equals per-sample rt_radio_map +
+  rt_radio_map_backward;
+* the captured HIP graph replays: every replay, with eager work in between,
+  equals the first (eager) result.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n_tx=6, seed=5, lo=2e4, hi=3e5, S=1):
+    import torch
+    import paper_2504_21719_amd as rt
+    scene = sg.manhattan_scene()
+    txs, budgets = sg.rooftop_transmitters(n_tx, seed=seed, buildings=sg.manhattan_buildings(scene),
+                                           budget_lo=lo, budget_hi=hi)
+    budgets[0] = 12_347          # a ragged small budget
+    plane = sg.Plane(1.5, -500.0, -500.0, 4.0, 4.0, 250, 250)
+    params = sg.Params(3.5e9, 1, 5)
+    s = rt.scene_from_mesh(scene)
+    return rt, torch, scene, s, txs, budgets, plane, params
+
+
+def _plain(rt, torch, s, eps, sig, tx, budget, plane, params):
+    out = torch.empty((1, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    p = sg.Params(params.freq_hz, int(budget), params.max_depth)
+    rt.rt_radio_map(s, eps, sig, tx, plane, p, out)
+    return out
+
+
+def test_multi_transmitter_matches_plain_loop():
+    rt, torch, scene, s, txs, budgets, plane, params = _setup()
+    eps = torch.tensor(scene.eps_r, dtype=torch.float32, device="cuda")
+    sig = torch.tensor(scene.sigma, dtype=torch.float32, device="cuda")
+    T = len(txs)
+    out = torch.full((T, 1, plane.H, plane.W), float("nan"), dtype=torch.float32, device="cuda")
+    rt.rt_radio_map_batched(s, eps[None], sig[None], txs, budgets, plane, params, out)
+    torch.cuda.synchronize()
+    first = out.clone()
+    for t in range(T):
+        ref = _plain(rt, torch, s, eps, sig, txs[t], budgets[t], plane, params)
+        torch.cuda.synchronize()
+        a, b = out[t, 0].cpu().numpy(), ref[0].cpu().numpy()
+        assert np.isfinite(a).all()
+        big = b > 1e-9 * b.max()
+        np.testing.assert_allclose(a[big], b[big], rtol=2e-5)
+        assert np.all(a[~big] <= 2e-9 * b.max())
+    # graph replays, with eager work between them
+    for rep in range(3):
+        _plain(rt, torch, s, eps, sig, txs[0], 5000, plane, params)
+        out.fill_(float("nan"))
+        rt.rt_radio_map_batched(s, eps[None], sig[None], txs, budgets, plane, params, out)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(out.cpu().numpy(), first.cpu().numpy(), rtol=2e-5, atol=1e-30)
+
+
+def test_material_samples_match_plain_calls():
+    rt, torch, scene, s, txs, budgets, plane, params = _setup(n_tx=3)
+    S = 4
+    E, Sg = sg.random_materials(scene, S, seed=5)
+    eps = torch.tensor(E, dtype=torch.float32, device="cuda")
+    sig = torch.tensor(Sg, dtype=torch.float32, device="cuda")
+    T = len(txs)
+    out = torch.empty((T, S, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    rt.rt_radio_map_batched(s, eps, sig, txs, budgets, plane, params, out)
+    torch.cuda.synchronize()
+    for t in range(T):
+        for k in range(S):
+            ref = _plain(rt, torch, s, eps[k].contiguous(), sig[k].contiguous(), txs[t], budgets[t], plane, params)
+            torch.cuda.synchronize()
+            a, b = out[t, k].cpu().numpy(), ref[0].cpu().numpy()
+            big = b > 1e-9 * b.max()
+            np.testing.assert_allclose(a[big], b[big], rtol=2e-5)
+
+
+def test_material_samples_fwd_bwd_match_plain_adjoint():
+    rt, torch, scene, s, txs, budgets, plane, params = _setup(n_tx=2)
+    txs = [sg.Tx(t.pos, yaw=0.4 + 0.3 * i, pitch=-0.15, pattern=sg.PATTERN_DIRECTIONAL) for i, t in enumerate(txs)]
+    S = 3
+    E, Sg = sg.random_materials(scene, S, seed=6)
+    eps = torch.tensor(E, dtype=torch.float32, device="cuda")
+    sig = torch.tensor(Sg, dtype=torch.float32, device="cuda")
+    T = len(txs)
+    g = torch.randn((T, S, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    # smooth upstream gradient (a blurred random field)
+    g = torch.nn.functional.avg_pool2d(g.view(T * S, 1, plane.H, plane.W), 9, 1, 4).view_as(g).contiguous()
+    out = torch.empty((T, S, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    nm = scene.n_materials
+    grads = torch.empty((T, S, 2 * nm + 3), dtype=torch.float32, device="cuda")
+    rt.rt_radio_map_batched(s, eps, sig, txs, budgets, plane, params, out, grad_maps=g, grads=grads)
+    torch.cuda.synchronize()
+    for t in range(T):
+        p = sg.Params(params.freq_hz, int(budgets[t]), params.max_depth)
+        for k in range(S):
+            m = torch.empty((1, plane.H, plane.W), dtype=torch.float32, device="cuda")
+            tape = rt.rt_tape_create(p)
+            e_k, s_k = eps[k].contiguous(), sig[k].contiguous()
+            rt.rt_radio_map(s, e_k, s_k, txs[t], plane, p, m, tape=tape)
+            ge = torch.empty(nm, device="cuda")
+            gs = torch.empty(nm, device="cuda")
+            go = torch.empty(3, device="cuda")
+            rt.rt_radio_map_backward(s, e_k, s_k, txs[t], plane, p, tape, g[t, k].contiguous()[None], ge, gs, go)
+            torch.cuda.synchronize()
+            ref = torch.cat([ge, gs, go]).cpu().numpy().astype(np.float64)
+            got = grads[t, k].cpu().numpy().astype(np.float64)
+            assert np.all(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-6 * np.abs(ref).max()), (t, k, got, ref)
+            a, b = out[t, k].cpu().numpy(), m[0].cpu().numpy()
+            big = b > 1e-9 * b.max()
+            np.testing.assert_allclose(a[big], b[big], rtol=2e-5)
