@@ -181,12 +181,22 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def extra_legs(rt, sg, cfg, scene, eps, sig, dev):
-    """fwd+bwd/fwd (differentiation workload) and batched vs plain loops."""
+def extra_legs(rt, sg, cfg, scene, eps, sig, dev, reps=5):
+    """Ratio legs on the same GPU, each against its plain per-call loop.
+
+    * fwd+bwd / fwd: differentiation workload (Manhattan, 1e6 rays, L = 4,
+      directional V-pol Tx at yaw 30 deg, pitch -10 deg): forward with a tape
+      plus the adjoint, over the forward without a tape;
+    * batched vs plain, 64 transmitters: seeded rooftop Tx with budgets
+      log-uniform in [1e5, 1e7], L = 5, 64 x 1000 x 1000 maps; one batched
+      call vs 64 rt_radio_map calls on one stream (same outputs, one sync);
+    * batched vs plain, 16 material samples fwd + bwd: differentiation Tx,
+      1e6 rays, L = 5; one batched call vs 16 forward-with-tape + backward.
+    """
     import numpy as np
     import torch
     out = {}
-    # ---- fwd+bwd / fwd on the differentiation workload (1e6 rays, L = 4)
+    # ---- fwd+bwd / fwd
     dc = sg.diff_config()
     H, W = dc.plane.H, dc.plane.W
     m = torch.empty((1, H, W), dtype=torch.float32, device=dev)
@@ -203,15 +213,68 @@ def extra_legs(rt, sg, cfg, scene, eps, sig, dev):
         rt.rt_radio_map(scene, eps, sig, dc.tx, dc.plane, dc.params, m, tape=tape)
         rt.rt_radio_map_backward(scene, eps, sig, dc.tx, dc.plane, dc.params, tape, g, ge, gs, go)
 
-    t_f = _time(fwd)
-    t_fb = _time(fwdbwd)
+    t_f = _time(fwd, reps)
+    t_fb = _time(fwdbwd, reps)
     out["fwd_bwd_over_fwd"] = round(t_fb / t_f, 3)
-    out["fwd_ms_diff"] = round(t_f, 4)
-    out["fwd_bwd_ms_diff"] = round(t_fb, 4)
+    out["diff_fwd_ms"] = round(t_f, 4)
+    out["diff_fwd_bwd_ms"] = round(t_fb, 4)
+    del tape
+
+    # ---- 64 transmitters, uneven budgets
+    txs, budgets = sg.rooftop_transmitters(64, seed=5, buildings=sg.manhattan_buildings(cfg.scene))
+    T = len(txs)
+    maps = torch.empty((T, 1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device=dev)
+    params = sg.Params(cfg.params.freq_hz, 1, 5)
+    plist = [sg.Params(cfg.params.freq_hz, int(b), 5) for b in budgets]
+
+    def plain_loop():
+        for t in range(T):
+            rt.rt_radio_map(scene, eps, sig, txs[t], cfg.plane, plist[t], maps[t])
+
+    def batched():
+        rt.rt_radio_map_batched(scene, eps[None], sig[None], txs, budgets, cfg.plane, params, maps)
+
+    t_plain = _time(plain_loop, reps, 1)
+    t_batch = _time(batched, reps, 1)
+    out["batched_tx_over_plain"] = round(t_plain / t_batch, 3)
+    out["batched_tx_ms"] = round(t_batch, 3)
+    out["plain_tx_loop_ms"] = round(t_plain, 3)
+    out["batched_tx_rays"] = int(np.sum(budgets))
+    del maps
+
+    # ---- 16 material samples, forward + backward
+    S = 16
+    E, Sg = sg.random_materials(cfg.scene, S, seed=5)
+    eS = torch.tensor(E, dtype=torch.float32, device=dev)
+    sS = torch.tensor(Sg, dtype=torch.float32, device=dev)
+    ptx = sg.Params(cfg.params.freq_hz, 1, 5)
+    p1 = sg.Params(cfg.params.freq_hz, 1_000_000, 5)
+    maps = torch.empty((1, S, H, W), dtype=torch.float32, device=dev)
+    gm = torch.randn((1, S, H, W), dtype=torch.float32, device=dev)
+    grads = torch.empty((1, S, 2 * cfg.scene.n_materials + 3), dtype=torch.float32, device=dev)
+    tape = rt.rt_tape_create(p1)
+    es_list = [eS[k].contiguous() for k in range(S)]
+    ss_list = [sS[k].contiguous() for k in range(S)]
+    g_list = [gm[0, k][None].contiguous() for k in range(S)]
+
+    def plain_samples():
+        for k in range(S):
+            rt.rt_radio_map(scene, es_list[k], ss_list[k], dc.tx, dc.plane, p1, maps[0, k][None], tape=tape)
+            rt.rt_radio_map_backward(scene, es_list[k], ss_list[k], dc.tx, dc.plane, p1, tape, g_list[k], ge, gs, go)
+
+    def batched_samples():
+        rt.rt_radio_map_batched(scene, eS, sS, [dc.tx], [1_000_000], dc.plane, ptx, maps, grad_maps=gm, grads=grads)
+
+    t_ps = _time(plain_samples, reps, 1)
+    t_bs = _time(batched_samples, reps, 1)
+    out["batched_samples_over_plain"] = round(t_ps / t_bs, 3)
+    out["batched_samples_ms"] = round(t_bs, 3)
+    out["plain_samples_loop_ms"] = round(t_ps, 3)
     return out
 
 
 def _time(fn, reps=10, warm=2):
+    """Average ms per call of fn() on the current stream (HIP events)."""
     import torch
     for _ in range(warm):
         fn()

@@ -69,7 +69,11 @@ typedef struct {
     int64_t n_nodes;          /* internal nodes (n_triangles - 1)             */
     int64_t device_bytes;     /* device memory held by the scene              */
     double build_ms;          /* device time of the last build                 */
-    float lo[3], hi[3];       /* scene bounds                                  */
+    int32_t tuned_block;      /* launch configuration chosen by rt_tune (0 =   */
+    int32_t tuned_deposit;    /* not tuned): workgroup size, deposit strategy, */
+    int32_t tuned_refill;     /* wavefront refill threshold (lanes), launch    */
+    int32_t tuned_order;      /* order (1 coherent patches, 2 lattice order)   */
+    float lo[3], hi[3];       /* bounds of the triangle AABB centres           */
 } rt_scene_info;
 
 /*
@@ -269,10 +273,15 @@ rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials materials,
 
 /* ------------------------------------------------------------- autotuner */
 /*
- * rt_tune -- time the forward kernel variants (block size, deposit strategy)
- * on this scene/tx/plane/params with `n_probe_rays` rays and remember the
- * fastest for later calls with RT_DEPOSIT_AUTO / block_size 0 on this scene.
- * Writes the chosen block size and deposit strategy (host ints, may be NULL).
+ * rt_tune -- time the forward kernel variants (workgroup size, deposit
+ * strategy, wavefront refill threshold, launch order) on this scene, tx,
+ * plane and params with the first `n_probe_rays` rays, and remember the
+ * fastest for later calls on this scene (RT_DEPOSIT_AUTO, block_size 0).
+ * Writes the chosen block size and deposit strategy (host ints, may be NULL);
+ * rt_scene_info_get reports the whole choice.
+ * Launch order: by default each chunk of consecutive lattice indices is
+ * launched sorted by azimuth, so that a wavefront starts on a small patch of
+ * directions (results are unchanged up to FP32 summation order).
  * Synchronises `stream`; `scratch_map` is device float32 of the map's size
  * and is overwritten.
  */

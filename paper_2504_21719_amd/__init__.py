@@ -37,7 +37,8 @@ class RtError(RuntimeError):
 class rt_scene_info(C.Structure):
     _fields_ = [("n_triangles", C.c_int64), ("n_materials", C.c_int32), ("bvh_depth", C.c_int32),
                 ("n_nodes", C.c_int64), ("device_bytes", C.c_int64), ("build_ms", C.c_double),
-                ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+                ("tuned_block", C.c_int32), ("tuned_deposit", C.c_int32), ("tuned_refill", C.c_int32),
+                ("tuned_order", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
 
 
 class rt_materials(C.Structure):

@@ -94,6 +94,7 @@ extern "C" rt_status rt_scene_destroy(rt_scene* s) {
     (void)hipFree(s->spill);
     (void)hipFree(s->tx_desc);
     (void)hipFree(s->grad_ws);
+    (void)hipFree(s->order);
     (void)hipFree(s->geom_ws);
     (void)hipFree(s->bgrad_ws);
     if (s->tx_desc_host) (void)hipHostFree(s->tx_desc_host);
@@ -111,6 +112,10 @@ extern "C" rt_status rt_scene_info_get(const rt_scene* s, rt_scene_info* out) {
     out->n_nodes = std::max<int64_t>(0, s->n_tri - 1);
     out->device_bytes = (int64_t)s->bytes;
     out->build_ms = s->build_ms;
+    out->tuned_block = s->tuned_block;
+    out->tuned_deposit = s->tuned_deposit;
+    out->tuned_refill = s->tuned_refill;
+    out->tuned_order = s->tuned_order;
     for (int a = 0; a < 3; a++) {
         out->lo[a] = s->lo[a];
         out->hi[a] = s->hi[a];
@@ -179,10 +184,25 @@ static void fill_tx(const rt_tx* t, int64_t n_rays, const rt_plane* p, double fr
     d->roll = t->roll;
     double ca = cos(t->yaw), sa = sin(t->yaw), cb = cos(t->pitch), sb = sin(t->pitch), cg = cos(t->roll),
            sg = sin(t->roll);
+    // R = Rz(yaw) Ry(pitch) Rx(roll) (eq. rotation) and its partial derivatives
     double R[9] = {ca * cb, ca * sb * sg - sa * cg, ca * sb * cg + sa * sg,
                    sa * cb, sa * sb * sg + ca * cg, sa * sb * cg - ca * sg,
                    -sb,     cb * sg,                cb * cg};
-    for (int i = 0; i < 9; i++) d->R[i] = R[i];
+    double dy[9] = {-sa * cb, -sa * sb * sg - ca * cg, -sa * sb * cg + ca * sg,
+                    ca * cb,  ca * sb * sg - sa * cg,  ca * sb * cg + sa * sg,
+                    0.0,      0.0,                     0.0};
+    double dp[9] = {-ca * sb, ca * cb * sg, ca * cb * cg,
+                    -sa * sb, sa * cb * sg, sa * cb * cg,
+                    -cb,      -sb * sg,     -sb * cg};
+    double dr[9] = {0.0, ca * sb * cg + sa * sg, -ca * sb * sg + sa * cg,
+                    0.0, sa * sb * cg - ca * sg, -sa * sb * sg - ca * cg,
+                    0.0, cb * cg,                -cb * sg};
+    for (int i = 0; i < 9; i++) {
+        d->R[i] = (float)R[i];
+        d->dR[0][i] = (float)dy[i];
+        d->dR[1][i] = (float)dp[i];
+        d->dR[2][i] = (float)dr[i];
+    }
     d->n_rays = n_rays;
     double lam = RT_C0 / freq;
     d->kappa = (float)(lam * lam / (4.0 * RT_PI * (double)n_rays * p->dx * p->dy));
@@ -262,6 +282,18 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
     f.accel = params->accel;
     f.deposit = pick_deposit(scene, params);
     f.block = pick_block(scene, params);
+    f.refill = scene->tuned_refill ? scene->tuned_refill : 1;
+    if (const char* env = getenv("RTMAP_REFILL")) f.refill = std::max(1, std::min(64, atoi(env)));
+    {
+        // coherent launch order: on unless tuned off or RTMAP_ORDER=0
+        const char* env = getenv("RTMAP_ORDER");
+        bool want = scene->tuned_order != 2 && !(env && env[0] == '0');
+        if (want && params->n_rays >= 4096) {
+            rt_status ro = rt_lattice_order(const_cast<rt_scene*>(scene), params->n_rays, (hipStream_t)stream);
+            if (ro != RT_OK) return ro;
+        }
+        f.ordered = want;
+    }
     f.zero_map = params->accumulate == 0;
     f.map = out_map;
     f.tape = tape;
@@ -505,41 +537,59 @@ extern "C" rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_t
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     if (he != hipSuccess) return rt_hip_fail(he, "rt_tune: hipEventCreate");
-    const int blocks[] = {64, 128, 256, 512};
+    // search: workgroup size x deposit strategy x wavefront refill threshold
+    // ("rays per wave" taken at once) x launch order; the traversal stack
+    // depth is fixed at compile time and spills to memory beyond it
+    const int blocks[] = {128, 256, 512};
     const int deps[] = {RT_DEPOSIT_ATOMIC, RT_DEPOSIT_WAVE};
+    const int refills[] = {1, 16, 48};
+    const int orders[] = {1, 2};
     float best = 1e30f;
-    int bb = 256, bd = RT_DEPOSIT_ATOMIC;
+    int bb = 256, bd = RT_DEPOSIT_ATOMIC, br = 1, bo = 1;
     rt_status r = RT_OK;
-    for (int bi : blocks) {
-        for (int di : deps) {
-            p.block_size = bi;
-            p.deposit = di;
-            // one warm-up, then the median of three timed runs
-            r = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
-            if (r != RT_OK) break;
-            float ts[3];
-            for (int rep = 0; rep < 3 && r == RT_OK; rep++) {
-                (void)hipEventRecord(e0, st);
-                r = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
-                (void)hipEventRecord(e1, st);
-                (void)hipEventSynchronize(e1);
-                (void)hipEventElapsedTime(&ts[rep], e0, e1);
-            }
-            if (r != RT_OK) break;
-            std::sort(ts, ts + 3);
-            if (ts[1] < best) {
-                best = ts[1];
-                bb = bi;
-                bd = di;
-            }
-        }
-        if (r != RT_OK) break;
-    }
+    const int saved[4] = {scene->tuned_block, scene->tuned_deposit, scene->tuned_refill, scene->tuned_order};
+    for (int oi : orders)
+        for (int bi : blocks)
+            for (int di : deps)
+                for (int ri : refills) {
+                    if (r != RT_OK) break;
+                    p.block_size = bi;
+                    p.deposit = di;
+                    scene->tuned_refill = ri;
+                    scene->tuned_order = oi;
+                    // one warm-up, then the median of three timed runs
+                    r = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
+                    if (r != RT_OK) break;
+                    float ts[3] = {0, 0, 0};
+                    for (int rep = 0; rep < 3 && r == RT_OK; rep++) {
+                        (void)hipEventRecord(e0, st);
+                        r = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
+                        (void)hipEventRecord(e1, st);
+                        (void)hipEventSynchronize(e1);
+                        (void)hipEventElapsedTime(&ts[rep], e0, e1);
+                    }
+                    std::sort(ts, ts + 3);
+                    if (r == RT_OK && ts[1] < best) {
+                        best = ts[1];
+                        bb = bi;
+                        bd = di;
+                        br = ri;
+                        bo = oi;
+                    }
+                }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (r != RT_OK) return r;
+    if (r != RT_OK) {
+        scene->tuned_block = saved[0];
+        scene->tuned_deposit = saved[1];
+        scene->tuned_refill = saved[2];
+        scene->tuned_order = saved[3];
+        return r;
+    }
     scene->tuned_block = bb;
     scene->tuned_deposit = bd;
+    scene->tuned_refill = br;
+    scene->tuned_order = bo;
     if (chosen_block) *chosen_block = bb;
     if (chosen_deposit) *chosen_deposit = bd;
     return RT_OK;

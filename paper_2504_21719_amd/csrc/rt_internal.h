@@ -49,6 +49,12 @@ struct rt_scene {
     // autotuned launch configuration (0 = not tuned)
     int tuned_block = 0;
     int tuned_deposit = 0;
+    int tuned_refill = 0;     // refill a wavefront once this many lanes are idle
+    int tuned_order = 0;      // 1 coherent launch order, 2 lattice order
+    // coherent launch order of the last N-ray lattice (device permutation)
+    int* order = nullptr;
+    int64_t order_n = 0;
+    int64_t order_chunk = 0;
     // backward workspace: per-block FP64 partial sums
     void* grad_ws = nullptr;
     size_t grad_ws_bytes = 0;
@@ -89,7 +95,8 @@ struct rt_tape {
 struct TxDesc {
     float pos[3];
     int32_t pattern;         // 0 iso, 1 directional
-    double R[9];             // rotation matrix, row-major
+    float R[9];              // R(yaw, pitch, roll), row-major
+    float dR[3][9];          // dR/d yaw, dR/d pitch, dR/d roll
     double yaw, pitch, roll;
     float q;
     int32_t pol;             // 0 V, 1 H, 2 dual
@@ -126,6 +133,8 @@ struct FwdLaunch {
     int accel;               // 0 BVH, 1 brute force
     int deposit;             // 1 atomic, 2 wave
     int block;
+    int refill;              // 1..64
+    bool ordered;            // use the scene's coherent launch order
     bool zero_map;
     float* map;
     rt_tape* tape;
@@ -180,3 +189,4 @@ rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const f
                                   float4* geom_seg, int* geom_nseg, hipStream_t st);
 
 int rt_persistent_blocks(int block, int device);
+rt_status rt_lattice_order(rt_scene* s, int64_t N, hipStream_t st);

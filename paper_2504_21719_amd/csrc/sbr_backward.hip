@@ -19,8 +19,8 @@
 // where dR/d eta = diag(dr_perp/d eta, -dr_par/d eta) W, d eta/d eps_r = 1,
 // d eta/d sigma = -j/(eps0 omega), and for the launch pattern
 //     dJ/dp = 2 Re( lambda_0^H dC/dp ),  p in {yaw, pitch, roll},
-// with dC/dp from forward-mode dual numbers through eq. rotation and
-// eq. theta_phi_prime.  Nothing is re-traced: geometry and fields come from
+// with dC/dp from FP32 forward-mode dual numbers through eq. theta_phi_prime,
+// fed with R and its angle derivatives (eq. rotation) computed on the host.  Nothing is re-traced: geometry and fields come from
 // the tape; only the normal (from the hit slot) and the Fresnel terms are
 // recomputed.
 //
@@ -83,10 +83,9 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
         Launch Lr = fib_launch(ray, a.tx.n_rays);
         for (int p = 0; p < a.npol; p++) {
             int pol_index = (a.npol == 2) ? p : (a.tx.pol == 1 ? 1 : 0);
-            dual3 cth, cph;
-            tx_pattern<dual3>(Lr, dual3{a.tx.yaw, 1.0, 0.0, 0.0}, dual3{a.tx.pitch, 0.0, 1.0, 0.0},
-                              dual3{a.tx.roll, 0.0, 0.0, 1.0}, a.tx.pattern, a.tx.q, pol_index, cth, cph);
-            const float ct = (float)cth.v, cp = (float)cph.v;
+            d3f cth, cph;
+            tx_pattern<d3f>(Lr, a.tx, pol_index, cth, cph);
+            const float ct = cth.v, cp = cph.v;
             const float* G = a.grad_map + (int64_t)p * a.map_stride;
             cf lam0 = {0, 0}, lam1 = {0, 0};
             for (int l = ns - 1; l >= 0; l--) {
@@ -140,9 +139,9 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
             }
             if (a.write_orient) {
                 // 2 Re(lambda_0^H dC), with C real
-                go0 += 2.0f * (lam0.re * (float)cth.d0 + lam1.re * (float)cph.d0);
-                go1 += 2.0f * (lam0.re * (float)cth.d1 + lam1.re * (float)cph.d1);
-                go2 += 2.0f * (lam0.re * (float)cth.d2 + lam1.re * (float)cph.d2);
+                go0 += 2.0f * (lam0.re * cth.d0 + lam1.re * cph.d0);
+                go1 += 2.0f * (lam0.re * cth.d1 + lam1.re * cph.d1);
+                go2 += 2.0f * (lam0.re * cth.d2 + lam1.re * cph.d2);
             }
         }
     }

@@ -66,145 +66,182 @@ __device__ __forceinline__ double wsum(double v) {
     return v;
 }
 
+// One thread per ray: the launch pattern and the geometry of every bounce
+// (basis change W, cos(theta_1), material, crossed cell, deposit factor) are
+// computed once and kept in registers; the loop over material samples then
+// only evaluates Fresnel coefficients and 2-vector field updates.
 template <bool GRAD>
 __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
-    const int s = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int64_t HW = (int64_t)a.pl.W * a.pl.H;
     const int64_t T = a.total;
+    const int S = a.S;
     for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < T; g0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t g = g0 + threadIdx.x;
         const bool valid = g < T;
-        int slot_out = -1;
-        float ge[kMaxMat], gs[kMaxMat], go[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < kMaxMat; j++) {
-            ge[j] = 0.f;
-            gs[j] = 0.f;
-        }
+        int slot_out = -1, ns = 0;
+        TxDesc td;
+        float w00[kMaxSeg], w01[kMaxSeg], w10[kMaxSeg], w11[kMaxSeg], cth1[kMaxSeg], gk[kMaxSeg];
+        int matl[kMaxSeg], cell[kMaxSeg];
+        d3f cth = {0, 0, 0, 0}, cph = {0, 0, 0, 0};
         if (valid) {
             const int t = find_tx_s(a.prefix, a.n_tx, g);
-            const TxDesc td = a.txs[t];
+            td = a.txs[t];
             slot_out = a.slots[t];
             const int64_t n = g - a.prefix[t];
-            const int ns = a.nseg[g];
-            const float* eps = a.eps_r + (int64_t)s * a.n_mat;
-            const float* sig = a.sigma + (int64_t)s * a.n_mat;
-            float* map = a.maps + ((int64_t)slot_out * a.S + s) * HW;
+            ns = a.nseg[g];
             Launch Lr = fib_launch(n, td.n_rays);
-            dual3 cth, cph;
             if (GRAD) {
-                tx_pattern<dual3>(Lr, dual3{td.yaw, 1.0, 0.0, 0.0}, dual3{td.pitch, 0.0, 1.0, 0.0},
-                                  dual3{td.roll, 0.0, 0.0, 1.0}, td.pattern, td.q, td.pol == 1 ? 1 : 0, cth, cph);
+                tx_pattern<d3f>(Lr, td, td.pol == 1 ? 1 : 0, cth, cph);
             } else {
-                double a0, a1;
-                tx_pattern<double>(Lr, td.yaw, td.pitch, td.roll, td.pattern, td.q, td.pol == 1 ? 1 : 0, a0, a1);
-                cth = mkd(a0);
-                cph = mkd(a1);
+                tx_pattern<float>(Lr, td, td.pol == 1 ? 1 : 0, cth.v, cph.v);
             }
-            cf e0 = {(float)cth.v, 0.f}, e1 = {(float)cph.v, 0.f};
-            cf E0[kMaxSeg], E1[kMaxSeg];
-            // forward: deposit every crossing, propagate E through the bounce
-            auto step = [&](int l) {
+#pragma unroll
+            for (int l = 0; l < kMaxSeg; l++) {
+                if (l >= ns) break;
                 const float4* sp = a.geom + (int64_t)l * 2 * T + g;
                 float4 s0 = sp[0], s1 = sp[T];
-                int cell = __float_as_int(s1.w);
-                if (cell >= 0) {
-                    float w = td.kappa / fabsf(s0.z) * (cabs2(e0) + cabs2(e1));
-                    unsafeAtomicAdd(map + cell, w);
-                }
+                cell[l] = __float_as_int(s1.w);
+                gk[l] = td.kappa / fabsf(s0.z);
                 if (l + 1 < ns) {
-                    int hs = __float_as_int(s0.w);
-                    float4 nm = a.normals[hs];
-                    int mat = __float_as_int(nm.w);
+                    float4 nm = a.normals[__float_as_int(s0.w)];
+                    matl[l] = __float_as_int(nm.w);
                     Bounce b = bounce_geometry(f3(s0.x, s0.y, s0.z), f3(s1.x, s1.y, s1.z), f3(nm.x, nm.y, nm.z));
-                    Fresnel F = fresnel<false>(b.c, cf{eps[mat], -sig[mat] * a.pl.inv_eps0_omega});
-                    cf u0 = cadd(cscale(e0, b.w00), cscale(e1, b.w01));
-                    cf u1 = cadd(cscale(e0, b.w10), cscale(e1, b.w11));
-                    e0 = cmul(F.rperp, u0);
-                    e1 = cmul(cf{-F.rpar.re, -F.rpar.im}, u1);
+                    w00[l] = b.w00;
+                    w01[l] = b.w01;
+                    w10[l] = b.w10;
+                    w11[l] = b.w11;
+                    cth1[l] = b.c;
                 }
-            };
-            if constexpr (GRAD) {
-                // the fields of every segment stay in registers for the reverse sweep
+            }
+        }
+        for (int s = 0; s < S; s++) {
+            float ge[kMaxMat], gs[kMaxMat], go[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 0; j < kMaxMat; j++) {
+                ge[j] = 0.f;
+                gs[j] = 0.f;
+            }
+            if (valid) {
+                const float* eps = a.eps_r + (int64_t)s * a.n_mat;
+                const float* sig = a.sigma + (int64_t)s * a.n_mat;
+                float* map = a.maps + ((int64_t)slot_out * S + s) * HW;
+                cf e0 = {cth.v, 0.f}, e1 = {cph.v, 0.f};
+                cf E0[kMaxSeg], E1[kMaxSeg];
 #pragma unroll
                 for (int l = 0; l < kMaxSeg; l++) {
                     if (l >= ns) break;
+                    if (cell[l] >= 0) unsafeAtomicAdd(map + cell[l], gk[l] * (cabs2(e0) + cabs2(e1)));
                     E0[l] = e0;
                     E1[l] = e1;
-                    step(l);
+                    if (l + 1 < ns) {
+                        int m = matl[l];
+                        Fresnel F = fresnel<false>(cth1[l], cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
+                        cf u0 = cadd(cscale(e0, w00[l]), cscale(e1, w01[l]));
+                        cf u1 = cadd(cscale(e0, w10[l]), cscale(e1, w11[l]));
+                        e0 = cmul(F.rperp, u0);
+                        e1 = cmul(cf{-F.rpar.re, -F.rpar.im}, u1);
+                    }
                 }
-            } else {
-                for (int l = 0; l < ns; l++) step(l);
+                if (GRAD) {
+                    const float* G = a.grad_maps + ((int64_t)slot_out * S + s) * HW;
+                    cf lam0 = {0, 0}, lam1 = {0, 0};
+#pragma unroll
+                    for (int l = kMaxSeg - 1; l >= 0; l--) {
+                        if (l >= ns) continue;
+                        if (cell[l] >= 0) {
+                            float al = G[cell[l]] * gk[l];
+                            lam0 = cadd(lam0, cscale(E0[l], al));
+                            lam1 = cadd(lam1, cscale(E1[l], al));
+                        }
+                        if (l == 0) continue;
+                        const int k = l - 1;      // the bounce that ends segment l-1
+                        int m = matl[k];
+                        Fresnel F = fresnel<true>(cth1[k], cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
+                        cf u0 = cadd(cscale(E0[k], w00[k]), cscale(E1[k], w01[k]));
+                        cf u1 = cadd(cscale(E0[k], w10[k]), cscale(E1[k], w11[k]));
+                        cf z = csub(cmulc(lam0, cmul(F.drperp, u0)), cmulc(lam1, cmul(F.drpar, u1)));
+#pragma unroll
+                        for (int jj = 0; jj < kMaxMat; jj++) {
+                            if (jj == m) {
+                                ge[jj] += 2.0f * z.re;
+                                gs[jj] += 2.0f * z.im * a.pl.inv_eps0_omega;
+                            }
+                        }
+                        cf v0 = cmulc(F.rperp, lam0);
+                        cf v1 = cmulc(F.rpar, lam1);
+                        v1 = cf{-v1.re, -v1.im};
+                        lam0 = cadd(cscale(v0, w00[k]), cscale(v1, w10[k]));
+                        lam1 = cadd(cscale(v0, w01[k]), cscale(v1, w11[k]));
+                    }
+                    go[0] = 2.0f * (lam0.re * cth.d0 + lam1.re * cph.d0);
+                    go[1] = 2.0f * (lam0.re * cth.d1 + lam1.re * cph.d1);
+                    go[2] = 2.0f * (lam0.re * cth.d2 + lam1.re * cph.d2);
+                }
             }
             if (GRAD) {
-                const float* G = a.grad_maps + ((int64_t)slot_out * a.S + s) * HW;
-                cf lam0 = {0, 0}, lam1 = {0, 0};
-#pragma unroll
-                for (int l = kMaxSeg - 1; l >= 0; l--) {
-                    if (l >= ns) continue;
-                    const float4* sp = a.geom + (int64_t)l * 2 * T + g;
-                    float4 s0 = sp[0], s1 = sp[T];
-                    int cell = __float_as_int(s1.w);
-                    if (cell >= 0) {
-                        float al = G[cell] * td.kappa / fabsf(s0.z);
-                        lam0 = cadd(lam0, cscale(E0[l], al));
-                        lam1 = cadd(lam1, cscale(E1[l], al));
-                    }
-                    if (l == 0) continue;
-                    const float4* qp = a.geom + (int64_t)(l - 1) * 2 * T + g;
-                    float4 p0 = qp[0], p1 = qp[T];
-                    int hs = __float_as_int(p0.w);
-                    float4 nm = a.normals[hs];
-                    int mat = __float_as_int(nm.w);
-                    Bounce b = bounce_geometry(f3(p0.x, p0.y, p0.z), f3(p1.x, p1.y, p1.z), f3(nm.x, nm.y, nm.z));
-                    Fresnel F = fresnel<true>(b.c, cf{eps[mat], -sig[mat] * a.pl.inv_eps0_omega});
-                    cf u0 = cadd(cscale(E0[l - 1], b.w00), cscale(E1[l - 1], b.w01));
-                    cf u1 = cadd(cscale(E0[l - 1], b.w10), cscale(E1[l - 1], b.w11));
-                    cf z = csub(cmulc(lam0, cmul(F.drperp, u0)), cmulc(lam1, cmul(F.drpar, u1)));
-#pragma unroll
-                    for (int jj = 0; jj < kMaxMat; jj++) {
-                        if (jj == mat) {
-                            ge[jj] += 2.0f * z.re;
-                            gs[jj] += 2.0f * z.im * a.pl.inv_eps0_omega;
+                // peel the lanes of each transmitter slot (usually one per wave),
+                // sum them with a butterfly, one FP64 atomic per parameter
+                unsigned long long pend = __ballot(valid);
+                bool done = !valid;
+                while (pend) {
+                    int leader = __ffsll((long long)pend) - 1;
+                    int ls = __shfl(slot_out, leader);
+                    bool mine = !done && slot_out == ls;
+                    unsigned long long grp = __ballot(mine);
+                    double* dst = a.gws + ((int64_t)ls * S + s) * a.P;
+                    for (int j = 0; j < a.n_mat && j < kMaxMat; j++) {
+                        double v = wsum(mine ? (double)ge[j] : 0.0);
+                        double u = wsum(mine ? (double)gs[j] : 0.0);
+                        if (lane == leader) {
+                            unsafeAtomicAdd(dst + j, v);
+                            unsafeAtomicAdd(dst + a.n_mat + j, u);
                         }
                     }
-                    cf v0 = cmulc(F.rperp, lam0);
-                    cf v1 = cmulc(F.rpar, lam1);
-                    v1 = cf{-v1.re, -v1.im};
-                    lam0 = cadd(cscale(v0, b.w00), cscale(v1, b.w10));
-                    lam1 = cadd(cscale(v0, b.w01), cscale(v1, b.w11));
+                    for (int j = 0; j < 3; j++) {
+                        double v = wsum(mine ? (double)go[j] : 0.0);
+                        if (lane == leader) unsafeAtomicAdd(dst + 2 * a.n_mat + j, v);
+                    }
+                    if (mine) done = true;
+                    pend &= ~grp;
                 }
-                go[0] = 2.0f * (lam0.re * (float)cth.d0 + lam1.re * (float)cph.d0);
-                go[1] = 2.0f * (lam0.re * (float)cth.d1 + lam1.re * (float)cph.d1);
-                go[2] = 2.0f * (lam0.re * (float)cth.d2 + lam1.re * (float)cph.d2);
             }
         }
-        if (GRAD) {
-            // peel the lanes of each transmitter slot (usually one per wave),
-            // sum them with a butterfly, one FP64 atomic per parameter
-            unsigned long long pend = __ballot(valid);
-            bool done = !valid;
-            while (pend) {
-                int leader = __ffsll((long long)pend) - 1;
-                int ls = __shfl(slot_out, leader);
-                bool mine = !done && slot_out == ls;
-                unsigned long long grp = __ballot(mine);
-                double* dst = a.gws + ((int64_t)ls * a.S + s) * a.P;
-                for (int j = 0; j < a.n_mat && j < kMaxMat; j++) {
-                    double v = wsum(mine ? (double)ge[j] : 0.0);
-                    double u = wsum(mine ? (double)gs[j] : 0.0);
-                    if (lane == leader) {
-                        unsafeAtomicAdd(dst + j, v);
-                        unsafeAtomicAdd(dst + a.n_mat + j, u);
-                    }
-                }
-                for (int j = 0; j < 3; j++) {
-                    double v = wsum(mine ? (double)go[j] : 0.0);
-                    if (lane == leader) unsafeAtomicAdd(dst + 2 * a.n_mat + j, v);
-                }
-                if (mine) done = true;
-                pend &= ~grp;
+    }
+}
+
+// Depth > 8 without gradients: one thread per (ray, sample), geometry
+// recomputed per sample.
+__global__ void __launch_bounds__(kSampBlock) k_samples_deep(const SampArgs a) {
+    const int s = blockIdx.y;
+    const int64_t HW = (int64_t)a.pl.W * a.pl.H;
+    const int64_t T = a.total;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < T; g += (int64_t)gridDim.x * blockDim.x) {
+        const int t = find_tx_s(a.prefix, a.n_tx, g);
+        const TxDesc td = a.txs[t];
+        const int slot_out = a.slots[t];
+        const int ns = a.nseg[g];
+        const float* eps = a.eps_r + (int64_t)s * a.n_mat;
+        const float* sig = a.sigma + (int64_t)s * a.n_mat;
+        float* map = a.maps + ((int64_t)slot_out * a.S + s) * HW;
+        Launch Lr = fib_launch(g - a.prefix[t], td.n_rays);
+        float ct, cp;
+        tx_pattern<float>(Lr, td, td.pol == 1 ? 1 : 0, ct, cp);
+        cf e0 = {ct, 0.f}, e1 = {cp, 0.f};
+        for (int l = 0; l < ns; l++) {
+            const float4* sp = a.geom + (int64_t)l * 2 * T + g;
+            float4 s0 = sp[0], s1 = sp[T];
+            int cell = __float_as_int(s1.w);
+            if (cell >= 0) unsafeAtomicAdd(map + cell, td.kappa / fabsf(s0.z) * (cabs2(e0) + cabs2(e1)));
+            if (l + 1 < ns) {
+                float4 nm = a.normals[__float_as_int(s0.w)];
+                int m = __float_as_int(nm.w);
+                Bounce b = bounce_geometry(f3(s0.x, s0.y, s0.z), f3(s1.x, s1.y, s1.z), f3(nm.x, nm.y, nm.z));
+                Fresnel F = fresnel<false>(b.c, cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
+                cf u0 = cadd(cscale(e0, b.w00), cscale(e1, b.w01));
+                cf u1 = cadd(cscale(e0, b.w10), cscale(e1, b.w11));
+                e0 = cmul(F.rperp, u0);
+                e1 = cmul(cf{-F.rpar.re, -F.rpar.im}, u1);
             }
         }
     }
@@ -298,10 +335,16 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
     a.grad_maps = b.grad_maps;
     a.gws = (double*)s->bgrad_ws;
     a.P = P;
-    unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(65535, (b.total_rays + kSampBlock - 1) / kSampBlock));
+    unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1 << 20, (b.total_rays + kSampBlock - 1) / kSampBlock));
     if (b.total_rays > 0) {
-        if (grad) hipLaunchKernelGGL(k_samples<true>, dim3(bx, S), dim3(kSampBlock), 0, st, a);
-        else hipLaunchKernelGGL(k_samples<false>, dim3(bx, S), dim3(kSampBlock), 0, st, a);
+        if (grad) {
+            hipLaunchKernelGGL(k_samples<true>, dim3(bx), dim3(kSampBlock), 0, st, a);
+        } else if (b.L + 1 <= kMaxSeg) {
+            hipLaunchKernelGGL(k_samples<false>, dim3(bx), dim3(kSampBlock), 0, st, a);
+        } else {
+            unsigned by = (unsigned)std::min<int64_t>(65535, (b.total_rays + kSampBlock - 1) / kSampBlock);
+            hipLaunchKernelGGL(k_samples_deep, dim3(by, S), dim3(kSampBlock), 0, st, a);
+        }
     }
     if (grad) {
         int64_t ng = (int64_t)b.n_tx * S * P;

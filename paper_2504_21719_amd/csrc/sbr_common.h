@@ -21,54 +21,52 @@ namespace rtd {
 constexpr uint64_t kPhiFrac = 0x9e3779b97f4a7c16ull;
 
 // ---------------------------------------------------------------- duals
-// Forward-mode scalar carrying d/d(yaw, pitch, roll).
-struct dual3 {
-    double v, d0, d1, d2;
+// FP32 forward-mode scalar carrying d/d(yaw, pitch, roll).
+struct d3f {
+    float v, d0, d1, d2;
 };
-__device__ __forceinline__ dual3 mkd(double v) { return dual3{v, 0.0, 0.0, 0.0}; }
-__device__ __forceinline__ dual3 operator+(dual3 a, dual3 b) { return dual3{a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2}; }
-__device__ __forceinline__ dual3 operator-(dual3 a, dual3 b) { return dual3{a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2}; }
-__device__ __forceinline__ dual3 operator-(dual3 a) { return dual3{-a.v, -a.d0, -a.d1, -a.d2}; }
-__device__ __forceinline__ dual3 operator*(dual3 a, dual3 b) {
-    return dual3{a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1, a.d2 * b.v + a.v * b.d2};
+__device__ __forceinline__ d3f operator+(d3f a, d3f b) { return d3f{a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2}; }
+__device__ __forceinline__ d3f operator-(d3f a, d3f b) { return d3f{a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2}; }
+__device__ __forceinline__ d3f operator-(d3f a) { return d3f{-a.v, -a.d0, -a.d1, -a.d2}; }
+__device__ __forceinline__ d3f operator*(d3f a, d3f b) {
+    return d3f{a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1, a.d2 * b.v + a.v * b.d2};
 }
-__device__ __forceinline__ dual3 chain(dual3 a, double f, double fp) { return dual3{f, fp * a.d0, fp * a.d1, fp * a.d2}; }
-__device__ __forceinline__ dual3 dsin(dual3 a) { return chain(a, sin(a.v), cos(a.v)); }
-__device__ __forceinline__ dual3 dcos(dual3 a) { return chain(a, cos(a.v), -sin(a.v)); }
-__device__ __forceinline__ dual3 dsqrt(dual3 a) {
-    double s = sqrt(fmax(a.v, 0.0));
-    return chain(a, s, s > 0.0 ? 0.5 / s : 0.0);
+__device__ __forceinline__ d3f chainf(d3f a, float f, float fp) { return d3f{f, fp * a.d0, fp * a.d1, fp * a.d2}; }
+__device__ __forceinline__ d3f dsqrtf(d3f a) {
+    float r = sqrtf(fmaxf(a.v, 0.0f));
+    return chainf(a, r, r > 0.0f ? 0.5f / r : 0.0f);
 }
-__device__ __forceinline__ dual3 dpow(dual3 a, double p) {
-    double f = pow(a.v, p);
-    return chain(a, f, a.v > 0.0 ? p * pow(a.v, p - 1.0) : 0.0);
+__device__ __forceinline__ d3f drecip(d3f a) {
+    float r = 1.0f / a.v;
+    return chainf(a, r, -r * r);
 }
-__device__ __forceinline__ dual3 datan2(dual3 y, dual3 x) {
-    double q = x.v * x.v + y.v * y.v;
-    double s = q > 0.0 ? 1.0 / q : 0.0;
-    return dual3{atan2(y.v, x.v), (x.v * y.d0 - y.v * x.d0) * s, (x.v * y.d1 - y.v * x.d1) * s,
-                 (x.v * y.d2 - y.v * x.d2) * s};
+__device__ __forceinline__ d3f dpowf(d3f a, float p) {
+    float f = powf(fmaxf(a.v, 0.0f), p);
+    return chainf(a, f, a.v > 0.0f ? p * f / a.v : 0.0f);
 }
-__device__ __forceinline__ dual3 dacos(dual3 a) {
-    double c = fmin(1.0, fmax(-1.0, a.v));
-    double s = sqrt(fmax(0.0, 1.0 - c * c));
-    return chain(a, acos(c), s > 0.0 ? -1.0 / s : 0.0);
-}
-// plain-double overloads with the same names
-__device__ __forceinline__ double mkd_d(double v) { return v; }
-__device__ __forceinline__ double dsin(double a) { return sin(a); }
-__device__ __forceinline__ double dcos(double a) { return cos(a); }
-__device__ __forceinline__ double dsqrt(double a) { return sqrt(fmax(a, 0.0)); }
-__device__ __forceinline__ double dpow(double a, double p) { return pow(a, p); }
-__device__ __forceinline__ double datan2(double y, double x) { return atan2(y, x); }
-__device__ __forceinline__ double dacos(double a) { return acos(fmin(1.0, fmax(-1.0, a))); }
+__device__ __forceinline__ float dsqrtf(float a) { return sqrtf(fmaxf(a, 0.0f)); }
+__device__ __forceinline__ float drecip(float a) { return 1.0f / a; }
+__device__ __forceinline__ float dpowf(float a, float p) { return powf(fmaxf(a, 0.0f), p); }
+__device__ __forceinline__ float val(float a) { return a; }
+__device__ __forceinline__ float val(d3f a) { return a.v; }
 
 template <typename S>
-__device__ __forceinline__ S scal(double v);
+__device__ __forceinline__ S cst(float v);
 template <>
-__device__ __forceinline__ double scal<double>(double v) { return v; }
+__device__ __forceinline__ float cst<float>(float v) { return v; }
 template <>
-__device__ __forceinline__ dual3 scal<dual3>(double v) { return mkd(v); }
+__device__ __forceinline__ d3f cst<d3f>(float v) { return d3f{v, 0.f, 0.f, 0.f}; }
+
+// Entry (i, j) of R = Rz(yaw) Ry(pitch) Rx(roll) (eq. rotation) with its
+// angle derivatives, both precomputed on the host per transmitter.
+template <typename S>
+__device__ __forceinline__ S rot(const TxDesc& t, int ij);
+template <>
+__device__ __forceinline__ float rot<float>(const TxDesc& t, int ij) { return t.R[ij]; }
+template <>
+__device__ __forceinline__ d3f rot<d3f>(const TxDesc& t, int ij) {
+    return d3f{t.R[ij], t.dR[0][ij], t.dR[1][ij], t.dR[2][ij]};
+}
 
 // ------------------------------------------------------------ ray launch
 struct Launch {
@@ -103,41 +101,51 @@ __device__ __forceinline__ Launch fib_launch(int64_t n, int64_t N) {
     return L;
 }
 
-// Transmit pattern components (C_theta, C_phi) in the launch basis for one
-// polarisation (pol_index 0: C' = sqrt(G) theta_hat', 1: sqrt(G) phi_hat').
-// The local direction is u = R^T k; the local field is rotated back by R and
-// projected on (theta_hat, phi_hat) of k, which is eq. F_prime_2_F.
+// Transmit pattern components (C_theta, C_phi) on the launch basis
+// (theta_hat, phi_hat) of direction k, for one polarisation (pol_index 0:
+// C' = sqrt(G) theta_hat', 1: C' = sqrt(G) phi_hat').  The local direction is
+// u = R^T k (eq. theta_phi_prime); theta_hat' and phi_hat' of eq. spherical_vecs
+// are written in Cartesian components of u (cos theta' = u_z,
+// sin theta' = rho = |u_xy|, (cos, sin) phi' = u_xy / rho, and phi' = 0 on the
+// local poles, which is atan2(0, 0)); the local field is rotated back by R
+// and projected on the launch basis, which is eq. F_prime_2_F.  With S = d3f
+// the same code yields d/d(yaw, pitch, roll).
 template <typename S>
-__device__ __forceinline__ void tx_pattern(const Launch& L, S yaw, S pitch, S roll, int pattern, double q,
-                                           int pol_index, S& c_theta, S& c_phi) {
-    S ca = dcos(yaw), sa = dsin(yaw), cb = dcos(pitch), sb = dsin(pitch), cg = dcos(roll), sg = dsin(roll);
-    // R = Rz(yaw) Ry(pitch) Rx(roll), eq. rotation, multiplied out
-    S R00 = ca * cb, R01 = ca * sb * sg - sa * cg, R02 = ca * sb * cg + sa * sg;
-    S R10 = sa * cb, R11 = sa * sb * sg + ca * cg, R12 = sa * sb * cg - ca * sg;
-    S R20 = -sb, R21 = cb * sg, R22 = cb * cg;
-    S kx = scal<S>(L.kx), ky = scal<S>(L.ky), kz = scal<S>(L.kz);
-    S ux = R00 * kx + R10 * ky + R20 * kz;
-    S uy = R01 * kx + R11 * ky + R21 * kz;
-    S uz = R02 * kx + R12 * ky + R22 * kz;
-    S th = dacos(uz), ph = datan2(uy, ux);
-    S ct = dcos(th), st = dsin(th), cp = dcos(ph), sp = dsin(ph);
-    S amp = scal<S>(1.0);
-    if (pattern == 1) amp = dsqrt(scal<S>(q + 1.0) * dpow((scal<S>(1.0) + ux) * scal<S>(0.5), q));
+__device__ __forceinline__ void tx_pattern(const Launch& L, const TxDesc& t, int pol_index, S& c_theta, S& c_phi) {
+    const float kx = (float)L.kx, ky = (float)L.ky, kz = (float)L.kz;
+    S R00 = rot<S>(t, 0), R01 = rot<S>(t, 1), R02 = rot<S>(t, 2);
+    S R10 = rot<S>(t, 3), R11 = rot<S>(t, 4), R12 = rot<S>(t, 5);
+    S R20 = rot<S>(t, 6), R21 = rot<S>(t, 7), R22 = rot<S>(t, 8);
+    S ux = R00 * cst<S>(kx) + R10 * cst<S>(ky) + R20 * cst<S>(kz);
+    S uy = R01 * cst<S>(kx) + R11 * cst<S>(ky) + R21 * cst<S>(kz);
+    S uz = R02 * cst<S>(kx) + R12 * cst<S>(ky) + R22 * cst<S>(kz);
+    S rho = dsqrtf(ux * ux + uy * uy);
+    S cp, sp;
+    if (val(rho) > 1e-12f) {
+        S ir = drecip(rho);
+        cp = ux * ir;
+        sp = uy * ir;
+    } else {
+        cp = cst<S>(1.0f);
+        sp = cst<S>(0.0f);
+    }
+    S amp = cst<S>(1.0f);
+    if (t.pattern == 1) amp = dsqrtf(cst<S>(t.q + 1.0f) * dpowf((cst<S>(1.0f) + ux) * cst<S>(0.5f), t.q));
     S fx, fy, fz;
     if (pol_index == 0) {
-        fx = amp * ct * cp;
-        fy = amp * ct * sp;
-        fz = -(amp * st);
+        fx = amp * uz * cp;
+        fy = amp * uz * sp;
+        fz = -(amp * rho);
     } else {
         fx = -(amp * sp);
         fy = amp * cp;
-        fz = scal<S>(0.0);
+        fz = cst<S>(0.0f);
     }
     S gx = R00 * fx + R01 * fy + R02 * fz;
     S gy = R10 * fx + R11 * fy + R12 * fz;
     S gz = R20 * fx + R21 * fy + R22 * fz;
-    c_theta = scal<S>(L.tx) * gx + scal<S>(L.ty) * gy + scal<S>(L.tz) * gz;
-    c_phi = scal<S>(L.px) * gx + scal<S>(L.py) * gy;
+    c_theta = cst<S>((float)L.tx) * gx + cst<S>((float)L.ty) * gy + cst<S>((float)L.tz) * gz;
+    c_phi = cst<S>((float)L.px) * gx + cst<S>((float)L.py) * gy;
 }
 
 // ------------------------------------------------------------ geometry

@@ -56,6 +56,10 @@ struct FwdArgs {
     int64_t spill_stride;
     int spill_depth;
     int tape_groups;         // float4 records per segment on the tape (4, or 2 = geometry only)
+    const int* order;        // coherent launch order of the lattice, or null
+    int64_t order_chunk;     // the order permutes within chunks of this many indices
+    int64_t ray_end;
+    int refill;              // refill a wavefront once this many lanes are idle
     // several transmitters (MODE_MULTI, MODE_GEOM): device tables
     const TxDesc* txs;       // ordered largest budget first
     const int64_t* prefix;   // [n_tx + 1] exclusive prefix of the budgets
@@ -202,7 +206,7 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
         // ---- refill lanes without a ray from the work counter
         if (!exhausted) {
             unsigned long long need = __ballot(!active);
-            if (need) {
+            if (need && (__popcll(need) >= a.refill || need == ~0ull)) {
                 int leader = __ffsll((long long)need) - 1;
                 unsigned cnt = (unsigned)__popcll(need);
                 unsigned long long base = 0;
@@ -217,6 +221,13 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
                         TxDesc td;
                         if (MODE == MODE_SINGLE) {
                             n = a.ray_begin + rid;
+                            if (a.order) {
+                                // permuted only inside chunks that the range covers entirely
+                                int64_t c0 = (n / a.order_chunk) * a.order_chunk;
+                                if (c0 >= a.ray_begin && min(c0 + a.order_chunk, a.tx.n_rays) <= a.ray_end)
+                                    n = a.order[n];
+                            }
+                            rid = n - a.ray_begin;   // records stay indexed by lattice index
                             td = a.tx;
                         } else {
                             int t = find_tx(a.prefix, a.n_tx, rid);
@@ -227,17 +238,8 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
                         }
                         Launch Lr = fib_launch(n, td.n_rays);
                         if (MODE != MODE_GEOM) {
-                            double ct0, cp0;
-                            tx_pattern<double>(Lr, td.yaw, td.pitch, td.roll, td.pattern, td.q, td.pol == 1 ? 1 : 0,
-                                               ct0, cp0);
-                            c0t = (float)ct0;
-                            c0p = (float)cp0;
-                            if (a.npol == 2) {
-                                double ct1, cp1;
-                                tx_pattern<double>(Lr, td.yaw, td.pitch, td.roll, td.pattern, td.q, 1, ct1, cp1);
-                                c1t = (float)ct1;
-                                c1p = (float)cp1;
-                            }
+                            tx_pattern<float>(Lr, td, td.pol == 1 ? 1 : 0, c0t, c0p);
+                            if (a.npol == 2) tx_pattern<float>(Lr, td, 1, c1t, c1p);
                         }
                         k = f3((float)Lr.kx, (float)Lr.ky, (float)Lr.kz);
                         es = f3((float)Lr.tx, (float)Lr.ty, (float)Lr.tz);
@@ -433,6 +435,7 @@ static void base_args(FwdArgs& a, const rt_scene* s, int block, const float* eps
     a.spill = s->spill;
     a.tape_groups = 4;
     a.npol = 1;
+    a.refill = 1;
 }
 
 static rt_status size_spill(FwdArgs& a, const rt_scene* s, int block, int* blocks_out) {
@@ -474,6 +477,12 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
     a.cells = f.cells;
     a.weights = f.weights;
     a.stats = f.stats;
+    a.refill = std::max(1, std::min(64, f.refill));
+    a.ray_end = f.ray_end;
+    if (f.ordered && s->order && s->order_n == f.tx.n_rays) {
+        a.order = s->order;
+        a.order_chunk = s->order_chunk;
+    }
     int blocks = 0;
     rt_status r = size_spill(a, s, f.block, &blocks);
     if (r != RT_OK) return r;

@@ -24,6 +24,15 @@
 
 #include "rt_internal.h"
 
+#define HIPCHK(x)                                            \
+    do {                                                     \
+        hipError_t _e = (x);                                 \
+        if (_e != hipSuccess) {                              \
+            cleanup();                                       \
+            return rt_hip_fail(_e, #x);                      \
+        }                                                    \
+    } while (0)
+
 namespace {
 
 constexpr int kBlock = 256;
@@ -323,16 +332,89 @@ __global__ void k_gather(const float4* __restrict__ raw, const uint32_t* __restr
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)std::max<int64_t>(1, (n + block - 1) / block); }
 
+// Sort key of lattice index n for the coherent launch order: the chunk
+// (M consecutive indices, i.e. a thin band of polar angle) in the high bits,
+// the Fibonacci azimuth frac(n (phi_g - 1)) in the low 32 bits.
+__global__ void k_order_keys(int64_t N, int64_t M, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    uint64_t az = ((uint64_t)n * 0x9e3779b97f4a7c16ull) >> 32;
+    keys[n] = ((uint64_t)(n / M) << 32) | az;
+    vals[n] = (uint32_t)n;
+}
+
 }  // namespace
 
-#define HIPCHK(x)                                            \
-    do {                                                     \
-        hipError_t _e = (x);                                 \
-        if (_e != hipSuccess) {                              \
-            cleanup();                                       \
-            return rt_hip_fail(_e, #x);                      \
-        }                                                    \
-    } while (0)
+// LSD radix sort of (key, value) pairs on the low `bits` bits of the keys.
+// Results end in (k0, v0) when the number of 8-bit passes is even, else in
+// (k1, v1); the return value says which (0 or 1).
+int rt_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t n, int bits, unsigned* hist,
+                  hipStream_t st) {
+    const int rs_blocks = (int)((n + kRsTile - 1) / kRsTile);
+    uint64_t *ka = k0, *kb = k1;
+    uint32_t *va = v0, *vb = v1;
+    int which = 0;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(rs_blocks), dim3(kBlock), 0, st, ka, n, shift, hist, rs_blocks);
+        hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * rs_blocks);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(rs_blocks), dim3(kBlock), 0, st, ka, va, kb, vb, n, shift, hist,
+                           rs_blocks);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+        which ^= 1;
+    }
+    return which;
+}
+
+// Build (or reuse) the coherent launch order of an N-ray lattice: within each
+// chunk of M consecutive indices the rays are sorted by azimuth, so the 64
+// lanes of a wavefront start on a small patch of directions.  Returns the
+// device permutation (lattice index at each work position) or nullptr.
+rt_status rt_lattice_order(rt_scene* s, int64_t N, hipStream_t st) {
+    if (s->order && s->order_n == N) return RT_OK;
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(s->order);
+    s->order = nullptr;
+    s->order_n = 0;
+    if (N < 4096 || N > 0x7fffffffll) return RT_OK;
+    // wave patches of roughly equal extent in polar and azimuthal angle:
+    // a chunk spans 2M/N in z, a wave 2 pi 64/M in azimuth -> M^2 = 64 pi N
+    int64_t M = (int64_t)std::sqrt(64.0 * 3.14159265358979 * (double)N);
+    M = std::max<int64_t>(4096, ((M + 63) / 64) * 64);
+    int64_t chunks = (N + M - 1) / M;
+    int bits = 32;
+    while (((int64_t)1 << (bits - 32)) < chunks) bits++;
+    bits = ((bits + 7) / 8) * 8;
+    uint64_t *k0 = nullptr, *k1 = nullptr;
+    uint32_t *v0 = nullptr, *v1 = nullptr;
+    unsigned* hist = nullptr;
+    const int rs_blocks = (int)((N + kRsTile - 1) / kRsTile);
+    bool keep = false;
+    auto cleanup = [&]() {
+        (void)hipFree(k0);
+        (void)hipFree(k1);
+        (void)hipFree(v1);
+        (void)hipFree(hist);
+        if (!keep) (void)hipFree(v0);
+    };
+    HIPCHK(hipMalloc(&k0, sizeof(uint64_t) * N));
+    HIPCHK(hipMalloc(&k1, sizeof(uint64_t) * N));
+    HIPCHK(hipMalloc(&v0, sizeof(uint32_t) * N));
+    HIPCHK(hipMalloc(&v1, sizeof(uint32_t) * N));
+    HIPCHK(hipMalloc(&hist, sizeof(unsigned) * 256 * (size_t)rs_blocks));
+    hipLaunchKernelGGL(k_order_keys, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, st, N, M, k0, v0);
+    int which = rt_radix_sort(k0, v0, k1, v1, N, bits, hist, st);
+    if (which) std::swap(v0, v1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    keep = true;
+    cleanup();
+    s->order = (int*)v0;
+    s->order_n = N;
+    s->order_chunk = M;
+    return RT_OK;
+}
+
 
 rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t* F, const int32_t* M,
                         hipStream_t st) {
