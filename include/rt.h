@@ -73,6 +73,7 @@ typedef struct {
     int32_t tuned_deposit;    /* not tuned): workgroup size, deposit strategy, */
     int32_t tuned_refill;     /* wavefront refill threshold (lanes), launch    */
     int32_t tuned_order;      /* order (1 coherent patches, 2 lattice order)   */
+    int32_t tuned_width;      /* and tree width (2 or 4)                       */
     float lo[3], hi[3];       /* bounds of the triangle AABB centres           */
 } rt_scene_info;
 
@@ -143,7 +144,7 @@ typedef struct {
     int32_t W, H;
 } rt_plane;
 
-enum { RT_ACCEL_BVH = 0, RT_ACCEL_BRUTE = 1 };
+enum { RT_ACCEL_BVH = 0, RT_ACCEL_BRUTE = 1, RT_ACCEL_BVH2 = 2, RT_ACCEL_BVH4 = 3 };
 enum { RT_DEPOSIT_AUTO = 0, RT_DEPOSIT_ATOMIC = 1, RT_DEPOSIT_WAVE = 2 };
 
 /*
@@ -158,8 +159,11 @@ enum { RT_DEPOSIT_AUTO = 0, RT_DEPOSIT_ATOMIC = 1, RT_DEPOSIT_WAVE = 2 };
  *   accumulate  0: the map is overwritten; 1: contributions are added to it
  *   t_min       spawned rays accept hits at t > t_min (metres); the triangle
  *               just hit is always excluded
- *   accel       RT_ACCEL_BVH, or RT_ACCEL_BRUTE (every triangle is tested;
- *               same intersection test, for validation)
+ *   accel       RT_ACCEL_BVH (tuned tree width), RT_ACCEL_BVH2 (binary LBVH),
+ *               RT_ACCEL_BVH4 (4-wide tree collapsed from it), or
+ *               RT_ACCEL_BRUTE (every triangle is tested with the same
+ *               intersection test, for validation).  All four give
+ *               identical hits.
  *   deposit     plane deposit strategy: AUTO (tuned), ATOMIC (one FP32 atomic
  *               per crossing) or WAVE (same-cell crossings of a wavefront are
  *               summed before one atomic)

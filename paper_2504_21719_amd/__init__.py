@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtmap.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EOVERFLOW, RT_EUNSUPPORTED = range(6)
-RT_ACCEL_BVH, RT_ACCEL_BRUTE = 0, 1
+RT_ACCEL_BVH, RT_ACCEL_BRUTE, RT_ACCEL_BVH2, RT_ACCEL_BVH4 = 0, 1, 2, 3
 RT_DEPOSIT_AUTO, RT_DEPOSIT_ATOMIC, RT_DEPOSIT_WAVE = 0, 1, 2
 RT_POL_V, RT_POL_H, RT_POL_DUAL = 0, 1, 2
 
@@ -38,7 +38,8 @@ class rt_scene_info(C.Structure):
     _fields_ = [("n_triangles", C.c_int64), ("n_materials", C.c_int32), ("bvh_depth", C.c_int32),
                 ("n_nodes", C.c_int64), ("device_bytes", C.c_int64), ("build_ms", C.c_double),
                 ("tuned_block", C.c_int32), ("tuned_deposit", C.c_int32), ("tuned_refill", C.c_int32),
-                ("tuned_order", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+                ("tuned_order", C.c_int32), ("tuned_width", C.c_int32), ("lo", C.c_float * 3),
+                ("hi", C.c_float * 3)]
 
 
 class rt_materials(C.Structure):

@@ -69,7 +69,7 @@ extern "C" rt_status rt_build_scene(const float* vertices, int64_t n_vertices, c
     }
     // traversal spill: (depth + 1 - RT_STACK_LDS) entries for every lane of
     // the largest persistent grid (a fixed number of lanes per CU)
-    int64_t need_depth = std::max<int64_t>(0, (int64_t)s->depth + 1 - RT_STACK_LDS);
+    int64_t need_depth = std::max<int64_t>(0, rt_stack_need(s) - RT_STACK_LDS);
     int64_t lanes = (int64_t)rt_persistent_blocks(64, s->device) * 64;
     s->spill_entries = (size_t)(need_depth * lanes);
     if (s->spill_entries) {
@@ -90,6 +90,7 @@ extern "C" rt_status rt_scene_destroy(rt_scene* s) {
     (void)hipFree(s->nodes);
     (void)hipFree(s->tris);
     (void)hipFree(s->normals);
+    (void)hipFree(s->wide);
     (void)hipFree(s->counters);
     (void)hipFree(s->spill);
     (void)hipFree(s->tx_desc);
@@ -116,6 +117,7 @@ extern "C" rt_status rt_scene_info_get(const rt_scene* s, rt_scene_info* out) {
     out->tuned_deposit = s->tuned_deposit;
     out->tuned_refill = s->tuned_refill;
     out->tuned_order = s->tuned_order;
+    out->tuned_width = s->tuned_width;
     for (int a = 0; a < 3; a++) {
         out->lo[a] = s->lo[a];
         out->hi[a] = s->hi[a];
@@ -150,7 +152,7 @@ static rt_status check_params(const rt_sbr_params* p, int64_t* b, int64_t* e) {
     CHECK_ARG(p->n_rays >= 1 && p->n_rays <= ((int64_t)1 << 40), "n_rays must be in [1, 2^40]");
     CHECK_ARG(p->max_depth >= 0 && p->max_depth <= 64, "max_depth must be in [0, 64]");
     CHECK_ARG(std::isfinite(p->t_min) && p->t_min >= 0.0f, "t_min must be finite and >= 0");
-    CHECK_ARG(p->accel == RT_ACCEL_BVH || p->accel == RT_ACCEL_BRUTE, "accel must be 0 or 1");
+    CHECK_ARG(p->accel >= RT_ACCEL_BVH && p->accel <= RT_ACCEL_BVH4, "accel must be 0, 1, 2 or 3");
     CHECK_ARG(p->deposit >= RT_DEPOSIT_AUTO && p->deposit <= RT_DEPOSIT_WAVE, "deposit must be 0, 1 or 2");
     CHECK_ARG(p->block_size == 0 || p->block_size == 64 || p->block_size == 128 || p->block_size == 256 ||
                   p->block_size == 512,
@@ -197,6 +199,9 @@ static void fill_tx(const rt_tx* t, int64_t n_rays, const rt_plane* p, double fr
     double dr[9] = {0.0, ca * sb * cg + sa * sg, -ca * sb * sg + sa * cg,
                     0.0, sa * sb * cg - ca * sg, -sa * sb * sg - ca * cg,
                     0.0, cb * cg,                -cb * sg};
+    d->ax[0] = R[0];
+    d->ax[1] = R[3];
+    d->ax[2] = R[6];
     for (int i = 0; i < 9; i++) {
         d->R[i] = (float)R[i];
         d->dR[0][i] = (float)dy[i];
@@ -542,21 +547,27 @@ extern "C" rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_t
     // depth is fixed at compile time and spills to memory beyond it
     const int blocks[] = {128, 256, 512};
     const int deps[] = {RT_DEPOSIT_ATOMIC, RT_DEPOSIT_WAVE};
-    const int refills[] = {1, 16, 48};
+    const int refills[] = {1, 32};
     const int orders[] = {1, 2};
+    const int widths[] = {4, 2};
     float best = 1e30f;
-    int bb = 256, bd = RT_DEPOSIT_ATOMIC, br = 1, bo = 1;
+    int bb = 256, bd = RT_DEPOSIT_ATOMIC, br = 1, bo = 1, bw = 4;
     rt_status r = RT_OK;
-    const int saved[4] = {scene->tuned_block, scene->tuned_deposit, scene->tuned_refill, scene->tuned_order};
+    const int saved[5] = {scene->tuned_block, scene->tuned_deposit, scene->tuned_refill, scene->tuned_order,
+                          scene->tuned_width};
+    p.accel = RT_ACCEL_BVH;
+    for (int wi : widths)
     for (int oi : orders)
         for (int bi : blocks)
             for (int di : deps)
                 for (int ri : refills) {
                     if (r != RT_OK) break;
+                    if (wi == 4 && !scene->wide) continue;
                     p.block_size = bi;
                     p.deposit = di;
                     scene->tuned_refill = ri;
                     scene->tuned_order = oi;
+                    scene->tuned_width = wi;
                     // one warm-up, then the median of three timed runs
                     r = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
                     if (r != RT_OK) break;
@@ -575,6 +586,7 @@ extern "C" rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_t
                         bd = di;
                         br = ri;
                         bo = oi;
+                        bw = wi;
                     }
                 }
     (void)hipEventDestroy(e0);
@@ -584,12 +596,14 @@ extern "C" rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_t
         scene->tuned_deposit = saved[1];
         scene->tuned_refill = saved[2];
         scene->tuned_order = saved[3];
+        scene->tuned_width = saved[4];
         return r;
     }
     scene->tuned_block = bb;
     scene->tuned_deposit = bd;
     scene->tuned_refill = br;
     scene->tuned_order = bo;
+    scene->tuned_width = bw;
     if (chosen_block) *chosen_block = bb;
     if (chosen_deposit) *chosen_deposit = bd;
     return RT_OK;

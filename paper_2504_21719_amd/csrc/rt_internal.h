@@ -19,6 +19,9 @@
 // spill to a per-lane global buffer sized from the BVH depth.
 #define RT_STACK_LDS 16
 
+// Empty child slot of a 4-wide node.
+#define RT_WIDE_EMPTY 0x7fffffff
+
 // LBVH layout.  Internal node = 4 x float4 (64 B, one cache line):
 //   q0 = (L.lo.x, L.hi.x, L.lo.y, L.hi.y)
 //   q1 = (R.lo.x, R.hi.x, R.lo.y, R.hi.y)
@@ -39,6 +42,13 @@ struct rt_scene {
     float4* nodes = nullptr;
     float4* tris = nullptr;
     float4* normals = nullptr;
+    // 4-wide BVH collapsed from the binary one: 8 x float4 (128 B) per node,
+    //   w0..w1 = x (lo, hi) of children 0..3, w2..w3 = y, w4..w5 = z,
+    //   w6 = child refs (>= 0 wide node, < 0 leaf slot ~r, RT_WIDE_EMPTY);
+    // node 0 is the root.  Built when n_tri >= 2.
+    float4* wide = nullptr;
+    int64_t n_wide = 0;
+    int tuned_width = 0;      // 2 binary, 4 wide (0 = default)
     size_t bytes = 0;
     double build_ms = 0.0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -97,6 +107,7 @@ struct TxDesc {
     int32_t pattern;         // 0 iso, 1 directional
     float R[9];              // R(yaw, pitch, roll), row-major
     float dR[3][9];          // dR/d yaw, dR/d pitch, dR/d roll
+    double ax[3];            // local +x axis in global coordinates (first column of R), FP64
     double yaw, pitch, roll;
     float q;
     int32_t pol;             // 0 V, 1 H, 2 dual
@@ -189,4 +200,9 @@ rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const f
                                   float4* geom_seg, int* geom_nseg, hipStream_t st);
 
 int rt_persistent_blocks(int block, int device);
+
+// Traversal stack entries a query can need: the binary tree pushes at most one
+// entry per level; the wide tree at most three per wide level, and a wide
+// level spans at least one binary level.
+inline int64_t rt_stack_need(const rt_scene* s) { return 3 * (int64_t)s->depth + 2; }
 rt_status rt_lattice_order(rt_scene* s, int64_t N, hipStream_t st);

@@ -49,6 +49,8 @@ __device__ __forceinline__ float drecip(float a) { return 1.0f / a; }
 __device__ __forceinline__ float dpowf(float a, float p) { return powf(fmaxf(a, 0.0f), p); }
 __device__ __forceinline__ float val(float a) { return a; }
 __device__ __forceinline__ float val(d3f a) { return a.v; }
+__device__ __forceinline__ float with_value(float, float v) { return v; }
+__device__ __forceinline__ d3f with_value(d3f a, float v) { return d3f{v, a.d0, a.d1, a.d2}; }
 
 template <typename S>
 __device__ __forceinline__ S cst(float v);
@@ -130,7 +132,14 @@ __device__ __forceinline__ void tx_pattern(const Launch& L, const TxDesc& t, int
         sp = cst<S>(0.0f);
     }
     S amp = cst<S>(1.0f);
-    if (t.pattern == 1) amp = dsqrtf(cst<S>(t.q + 1.0f) * dpowf((cst<S>(1.0f) + ux) * cst<S>(0.5f), t.q));
+    if (t.pattern == 1) {
+        // (1 + cos alpha)/2 with cos alpha = u_x = (R x_hat) . k, evaluated in
+        // FP64: near the back lobe 1 + u_x cancels and FP32 would lose it
+        double hx = 0.5 * (1.0 + (t.ax[0] * L.kx + t.ax[1] * L.ky + t.ax[2] * L.kz));
+        S half = ux * cst<S>(0.5f);          // carries d(u_x)/d angle / 2
+        half = with_value(half, (float)fmax(hx, 0.0));
+        amp = dsqrtf(cst<S>(t.q + 1.0f) * dpowf(half, t.q));
+    }
     S fx, fy, fz;
     if (pol_index == 0) {
         fx = amp * uz * cp;
@@ -240,6 +249,25 @@ __device__ __forceinline__ void box2(const Ray& r, float4 q0, float4 q1, float4 
     hitR = aR <= fminf(bR, tmax);
     tL = aL;
     tR = aR;
+}
+
+// Slab test of the four children of a wide node (same arithmetic as box2).
+__device__ __forceinline__ void box4(const Ray& r, const float4* __restrict__ w, float tmin, float tmax, bool hit[4],
+                                     float tent[4]) {
+    float4 x01 = w[0], x23 = w[1], y01 = w[2], y23 = w[3], z01 = w[4], z23 = w[5];
+    const float xl[4] = {x01.x, x01.z, x23.x, x23.z}, xh[4] = {x01.y, x01.w, x23.y, x23.w};
+    const float yl[4] = {y01.x, y01.z, y23.x, y23.z}, yh[4] = {y01.y, y01.w, y23.y, y23.w};
+    const float zl[4] = {z01.x, z01.z, z23.x, z23.z}, zh[4] = {z01.y, z01.w, z23.y, z23.w};
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        float tx0 = (xl[c] - r.ox) * r.ix, tx1 = (xh[c] - r.ox) * r.ix;
+        float ty0 = (yl[c] - r.oy) * r.iy, ty1 = (yh[c] - r.oy) * r.iy;
+        float tz0 = (zl[c] - r.oz) * r.iz, tz1 = (zh[c] - r.oz) * r.iz;
+        float a = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
+        float b = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * kBoxSlack;
+        hit[c] = a <= fminf(b, tmax);
+        tent[c] = a;
+    }
 }
 
 // ------------------------------------------------------------ Fresnel

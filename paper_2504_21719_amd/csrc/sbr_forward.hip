@@ -28,6 +28,7 @@ namespace {
 
 struct FwdArgs {
     const float4* nodes;
+    const float4* wide;
     const float4* tris;
     const float4* normals;
     int root;
@@ -99,9 +100,10 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 // Closest hit of ray r among all triangles but `last` (a slot).  Ties in t go
 // to the smallest original triangle id.  Returns the slot or -1.
-template <bool BRUTE>
+template <bool BRUTE, bool WIDE>
 __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int last, float& t_best, int& id_best,
-                                           int* __restrict__ lstack, int lstride, int64_t gtid,
+                                           int* __restrict__ lstack, float* __restrict__ tstack, int lstride,
+                                           int64_t gtid,
                                            unsigned& n_nodes, unsigned& n_tris, unsigned& overflow) {
     t_best = INFINITY;
     id_best = 0x7fffffff;
@@ -130,6 +132,82 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
         test(~a.root);
         return slot_best;
     }
+    if (WIDE) {
+        // 4-wide traversal: four slab tests per node fetch; leaf children are
+        // tested at once, internal hits are sorted by entry distance, the
+        // nearest is descended and the others are pushed farthest first
+        int sp = 0;
+        int node = 0;
+        for (int guard = 0; guard < a.n_tri; guard++) {
+            n_nodes++;
+            const float4* w = a.wide + 8 * (int64_t)node;
+            bool h[4];
+            float te[4];
+            box4(r, w, tmin, t_best * kBoxSlack, h, te);
+            float4 rf = w[6];
+            int ref[4] = {__float_as_int(rf.x), __float_as_int(rf.y), __float_as_int(rf.z), __float_as_int(rf.w)};
+            float key[4];
+            int nint = 0;
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                bool hc = h[c] && ref[c] != RT_WIDE_EMPTY;
+                if (hc && ref[c] < 0) {
+                    test(~ref[c]);
+                    hc = false;
+                }
+                key[c] = hc ? te[c] : INFINITY;
+                nint += hc ? 1 : 0;
+            }
+            if (nint > 0) {
+                // sort the four (key, ref) pairs by key (misses sort last)
+#define RT_CSWAP(i, j)                                  \
+    if (key[j] < key[i]) {                              \
+        float tk = key[i];                              \
+        key[i] = key[j];                                \
+        key[j] = tk;                                    \
+        int tr = ref[i];                                \
+        ref[i] = ref[j];                                \
+        ref[j] = tr;                                    \
+    }
+                RT_CSWAP(0, 1) RT_CSWAP(2, 3) RT_CSWAP(0, 2) RT_CSWAP(1, 3) RT_CSWAP(1, 2)
+#undef RT_CSWAP
+#pragma unroll
+                for (int c = 3; c >= 1; c--) {
+                    if (c < nint) {
+                        if (sp < RT_STACK_LDS) {
+                            lstack[sp * lstride] = ref[c];
+                            tstack[sp * lstride] = key[c];
+                            sp++;
+                        } else if (sp - RT_STACK_LDS < a.spill_depth) {
+                            a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid] = ref[c];
+                            sp++;
+                        } else {
+                            overflow++;
+                        }
+                    }
+                }
+                node = ref[0];
+            } else {
+                bool found = false;
+                while (sp > 0) {
+                    sp--;
+                    if (sp < RT_STACK_LDS) {
+                        if (tstack[sp * lstride] <= t_best * kBoxSlack) {
+                            node = lstack[sp * lstride];
+                            found = true;
+                            break;
+                        }
+                    } else {
+                        node = a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid];
+                        found = true;
+                        break;
+                    }
+                }
+                if (!found) break;
+            }
+        }
+        return slot_best;
+    }
     int sp = 0;
     int node = a.root;
     // every internal node is visited at most once per query; the bound only
@@ -153,8 +231,12 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
         if (hL && hR) {
             int nearc = tL <= tR ? cl : cr;
             int farc = tL <= tR ? cr : cl;
+            float tfar = tL <= tR ? tR : tL;
+            // the far child's entry distance goes with it, so that it can be
+            // dropped at pop time without fetching its node
             if (sp < RT_STACK_LDS) {
                 lstack[sp * lstride] = farc;
+                tstack[sp * lstride] = tfar;
                 sp++;
             } else if (sp - RT_STACK_LDS < a.spill_depth) {
                 a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid] = farc;
@@ -169,19 +251,33 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
             node = cr;
         } else {
             // pop until a node whose box may still hold a closer hit
-            if (sp == 0) break;
-            sp--;
-            node = (sp < RT_STACK_LDS) ? lstack[sp * lstride] : a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid];
+            bool found = false;
+            while (sp > 0) {
+                sp--;
+                if (sp < RT_STACK_LDS) {
+                    if (tstack[sp * lstride] <= t_best * kBoxSlack) {
+                        node = lstack[sp * lstride];
+                        found = true;
+                        break;
+                    }
+                } else {
+                    node = a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid];
+                    found = true;
+                    break;
+                }
+            }
+            if (!found) break;
         }
     }
     return slot_best;
 }
 
-template <bool BRUTE, int MODE>
-__global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
+template <bool BRUTE, int MODE, bool WIDE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_forward(const FwdArgs a) {
     extern __shared__ int s_stack[];
     const int lstride = blockDim.x;
     int* lstack = s_stack + threadIdx.x;
+    float* tstack = (float*)(s_stack + RT_STACK_LDS * blockDim.x) + threadIdx.x;
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
     const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -280,7 +376,8 @@ __global__ void __launch_bounds__(512) k_forward(const FwdArgs a) {
             r.dz = k.z;
             ray_setup(r);
             int idb;
-            slot = closest_hit<BRUTE>(a, r, last, t_hit, idb, lstack, lstride, gtid, st_nodes, st_tris, st_over);
+            slot = closest_hit<BRUTE, WIDE>(a, r, last, t_hit, idb, lstack, tstack, lstride, gtid, st_nodes,
+                                            st_tris, st_over);
             hit_id = slot >= 0 ? idb : -1;
             st_seg++;
             // ---- plane crossing of this segment
@@ -422,6 +519,7 @@ static void base_args(FwdArgs& a, const rt_scene* s, int block, const float* eps
                       const PlaneDesc& pl, int L, float t_min) {
     memset(&a, 0, sizeof(a));
     a.nodes = s->nodes;
+    a.wide = s->wide;
     a.tris = s->tris;
     a.normals = s->normals;
     a.root = s->root;
@@ -441,7 +539,8 @@ static void base_args(FwdArgs& a, const rt_scene* s, int block, const float* eps
 static rt_status size_spill(FwdArgs& a, const rt_scene* s, int block, int* blocks_out) {
     int blocks = rt_persistent_blocks(block, s->device);
     int64_t threads = (int64_t)blocks * block;
-    int64_t need_depth = std::max<int64_t>(0, (int64_t)s->depth + 1 - RT_STACK_LDS);
+    // a wide traversal pushes up to 3 entries per wide level (= 2 binary levels)
+    int64_t need_depth = std::max<int64_t>(0, rt_stack_need(s) - RT_STACK_LDS);
     if ((int64_t)s->spill_entries < need_depth * threads)
         return rt_fail(RT_EOVERFLOW, "traversal spill area too small for this launch");
     a.spill_stride = threads;
@@ -451,12 +550,22 @@ static rt_status size_spill(FwdArgs& a, const rt_scene* s, int block, int* block
 }
 
 template <int MODE>
-static void launch_mode(const FwdArgs& a, int accel, int blocks, int block, hipStream_t st) {
-    size_t lds = sizeof(int) * RT_STACK_LDS * block;
+static void launch_mode(const FwdArgs& a, int accel, bool wide, int blocks, int block, hipStream_t st) {
+    size_t lds = 2 * sizeof(int) * RT_STACK_LDS * block;   // node ids + entry distances
     if (accel == RT_ACCEL_BRUTE)
-        hipLaunchKernelGGL((k_forward<true, MODE>), dim3(blocks), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((k_forward<true, MODE, false>), dim3(blocks), dim3(block), lds, st, a);
+    else if (wide)
+        hipLaunchKernelGGL((k_forward<false, MODE, true>), dim3(blocks), dim3(block), lds, st, a);
     else
-        hipLaunchKernelGGL((k_forward<false, MODE>), dim3(blocks), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((k_forward<false, MODE, false>), dim3(blocks), dim3(block), lds, st, a);
+}
+
+// Tree width: forced by accel, else tuned (or overridden), default 4-wide.
+static bool use_wide(const rt_scene* s, int accel = RT_ACCEL_BVH) {
+    if (!s->wide || s->root < 0 || accel == RT_ACCEL_BVH2 || accel == RT_ACCEL_BRUTE) return false;
+    if (accel == RT_ACCEL_BVH4) return true;
+    if (const char* env = getenv("RTMAP_WIDTH")) return atoi(env) != 2;
+    return s->tuned_width != 2;
 }
 
 rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
@@ -492,7 +601,7 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
         int g = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (zn + 255) / 256));
         hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, f.map, zn, s->counters);
     }
-    if (a.n_work > 0) launch_mode<MODE_SINGLE>(a, f.accel, blocks, f.block, st);
+    if (a.n_work > 0) launch_mode<MODE_SINGLE>(a, f.accel, use_wide(s, f.accel), blocks, f.block, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rt_hip_fail(e, "forward launch");
     return RT_OK;
@@ -530,8 +639,8 @@ rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const f
     int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (zero_floats + 255) / 256));
     hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, maps, zero_floats, s->counters);
     if (total_rays > 0) {
-        if (geom_only) launch_mode<MODE_GEOM>(a, RT_ACCEL_BVH, blocks, block, st);
-        else launch_mode<MODE_MULTI>(a, RT_ACCEL_BVH, blocks, block, st);
+        if (geom_only) launch_mode<MODE_GEOM>(a, RT_ACCEL_BVH, use_wide(s), blocks, block, st);
+        else launch_mode<MODE_MULTI>(a, RT_ACCEL_BVH, use_wide(s), blocks, block, st);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rt_hip_fail(e, "batched forward launch");

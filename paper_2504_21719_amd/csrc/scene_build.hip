@@ -303,6 +303,101 @@ __global__ void k_refit_level(const int4* __restrict__ child, const int* __restr
     nodes[4 * i + 3] = make_float4(__int_as_float(c.x), __int_as_float(c.y), 0.0f, 0.0f);
 }
 
+// ---- 4-wide collapse -------------------------------------------------------
+// A wide node is rooted at a binary node; its children are obtained by
+// repeatedly replacing the internal child with the largest box surface area by
+// its two children, until there are four children or only leaves.
+__device__ __forceinline__ float box_area(const float lo[3], const float hi[3]) {
+    float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__device__ __forceinline__ int wide_children(const int4* __restrict__ child, const float4* __restrict__ nodes, int i,
+                                             int refs[4]) {
+    int4 c = child[i];
+    refs[0] = c.x;
+    refs[1] = c.y;
+    int cnt = 2;
+    while (cnt < 4) {
+        int best = -1;
+        float bestA = -1.0f;
+        for (int j = 0; j < cnt; j++) {
+            if (refs[j] >= 0) {
+                float lo[3], hi[3];
+                node_box(nodes, refs[j], lo, hi);
+                float A = box_area(lo, hi);
+                if (A > bestA) {
+                    bestA = A;
+                    best = j;
+                }
+            }
+        }
+        if (best < 0) break;
+        int4 g = child[refs[best]];
+        refs[best] = g.x;
+        refs[cnt++] = g.y;
+    }
+    return cnt;
+}
+
+__global__ void k_wide_mark(const int4* __restrict__ child, const float4* __restrict__ nodes,
+                            const int* __restrict__ depth, int level, int64_t n_int, int* __restrict__ is_root) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_int || depth[i] != level || !is_root[i]) return;
+    int refs[4];
+    int cnt = wide_children(child, nodes, (int)i, refs);
+    for (int j = 0; j < cnt; j++)
+        if (refs[j] >= 0) is_root[refs[j]] = 1;
+}
+
+__global__ void k_wide_emit(const int4* __restrict__ child, const float4* __restrict__ nodes,
+                            const float4* __restrict__ tris, const int* __restrict__ is_root,
+                            const unsigned* __restrict__ index4, int64_t n_int, float4* __restrict__ wide) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_int || !is_root[i]) return;
+    int refs[4];
+    int cnt = wide_children(child, nodes, (int)i, refs);
+    float lo[4][3], hi[4][3];
+    int out[4];
+    for (int j = 0; j < 4; j++) {
+        if (j >= cnt) {
+            for (int a = 0; a < 3; a++) {
+                lo[j][a] = 0.0f;
+                hi[j][a] = 0.0f;
+            }
+            out[j] = RT_WIDE_EMPTY;
+        } else if (refs[j] < 0) {
+            int64_t sl = ~refs[j];
+            float4 a0 = tris[3 * sl], a1 = tris[3 * sl + 1], a2 = tris[3 * sl + 2];
+            lo[j][0] = fminf(fminf(a0.x, a1.x), a2.x);
+            lo[j][1] = fminf(fminf(a0.y, a1.y), a2.y);
+            lo[j][2] = fminf(fminf(a0.z, a1.z), a2.z);
+            hi[j][0] = fmaxf(fmaxf(a0.x, a1.x), a2.x);
+            hi[j][1] = fmaxf(fmaxf(a0.y, a1.y), a2.y);
+            hi[j][2] = fmaxf(fmaxf(a0.z, a1.z), a2.z);
+            out[j] = refs[j];
+        } else {
+            node_box(nodes, refs[j], lo[j], hi[j]);
+            out[j] = (int)index4[refs[j]];
+        }
+    }
+    float4* w = wide + 8 * (int64_t)index4[i];
+    w[0] = make_float4(lo[0][0], hi[0][0], lo[1][0], hi[1][0]);
+    w[1] = make_float4(lo[2][0], hi[2][0], lo[3][0], hi[3][0]);
+    w[2] = make_float4(lo[0][1], hi[0][1], lo[1][1], hi[1][1]);
+    w[3] = make_float4(lo[2][1], hi[2][1], lo[3][1], hi[3][1]);
+    w[4] = make_float4(lo[0][2], hi[0][2], lo[1][2], hi[1][2]);
+    w[5] = make_float4(lo[2][2], hi[2][2], lo[3][2], hi[3][2]);
+    w[6] = make_float4(__int_as_float(out[0]), __int_as_float(out[1]), __int_as_float(out[2]),
+                       __int_as_float(out[3]));
+    w[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+__global__ void k_flags_to_u32(const int* __restrict__ f, unsigned* __restrict__ u, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) u[i] = (unsigned)f[i];
+}
+
 __global__ void k_gather(const float4* __restrict__ raw, const uint32_t* __restrict__ order,
                          const int32_t* __restrict__ M, int64_t n, float4* __restrict__ tris,
                          float4* __restrict__ normals) {
@@ -537,6 +632,31 @@ rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t*
     hipLaunchKernelGGL(k_gather, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, st, raw, va, M, n, s->tris,
                        s->normals);
     HIPCHK(hipGetLastError());
+    if (n_int > 0) {
+        // 4-wide collapse: mark wide roots top-down, number them, emit
+        int* is_root = (int*)k1;                 // reuse the sort buffers (>= 8 n bytes each)
+        unsigned* index4 = (unsigned*)(k1) + n_int;
+        HIPCHK(hipMemsetAsync(is_root, 0, sizeof(int) * n_int, st));
+        int one = 1;
+        HIPCHK(hipMemcpyAsync(is_root, &one, sizeof(int), hipMemcpyHostToDevice, st));
+        for (int lvl = 0; lvl < maxdepth; lvl++)
+            hipLaunchKernelGGL(k_wide_mark, dim3(grid_for(n_int, kBlock)), dim3(kBlock), 0, st, child, s->nodes,
+                               depth, lvl, n_int, is_root);
+        hipLaunchKernelGGL(k_flags_to_u32, dim3(grid_for(n_int, kBlock)), dim3(kBlock), 0, st, is_root, index4,
+                           n_int);
+        unsigned last_flag = 0, last_index = 0;
+        HIPCHK(hipMemcpyAsync(&last_flag, index4 + n_int - 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, index4, n_int);
+        HIPCHK(hipMemcpyAsync(&last_index, index4 + n_int - 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int64_t n4 = (int64_t)last_index + last_flag;
+        HIPCHK(hipMalloc(&s->wide, sizeof(float4) * 8 * n4));
+        s->bytes += sizeof(float4) * 8 * n4;
+        hipLaunchKernelGGL(k_wide_emit, dim3(grid_for(n_int, kBlock)), dim3(kBlock), 0, st, child, s->nodes,
+                           s->tris, is_root, index4, n_int, s->wide);
+        HIPCHK(hipGetLastError());
+        s->n_wide = n4;
+    }
     HIPCHK(hipEventRecord(e1, st));
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0.0f;

@@ -65,7 +65,7 @@ def _params(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(n_rays=0), dict(max_depth=-1), dict(max_depth=65), dict(freq_hz=0.0),
-                                 dict(ray_begin=5, ray_end=3), dict(ray_end=2000), dict(accel=3), dict(deposit=7),
+                                 dict(ray_begin=5, ray_end=3), dict(ray_end=2000), dict(accel=4), dict(deposit=7),
                                  dict(block_size=100), dict(accumulate=2), dict(t_min=-1.0)])
 def test_invalid_params_rejected_on_host(bad):
     import paper_2504_21719_amd as rt

@@ -35,15 +35,16 @@ def test_tiny_full_parity():
 
 
 def test_tiny_ragged_range_and_brute_force():
-    """A ragged sub-range (not a multiple of the wave or block size) and the
-    brute-force intersection give bit-identical hits to the LBVH."""
+    """A ragged sub-range (not a multiple of the wave or block size): the binary
+    LBVH, the 4-wide tree and brute-force intersection give bit-identical hits."""
     cfg = sg.tiny_config(n_rays=100_000)
     s = gpu_scene(cfg.scene)
-    a = gpu_radio_map(cfg, scene_handle=s, ray_begin=12_345, ray_end=12_345 + 4_999)
-    b = gpu_radio_map(cfg, scene_handle=s, ray_begin=12_345, ray_end=12_345 + 4_999, accel=1)
-    assert np.array_equal(a.hits, b.hits)
-    assert np.array_equal(a.cells, b.cells)
-    assert np.array_equal(a.weights, b.weights)
+    a = gpu_radio_map(cfg, scene_handle=s, ray_begin=12_345, ray_end=12_345 + 4_999, accel=2)
+    for accel in (1, 3, 0):
+        b = gpu_radio_map(cfg, scene_handle=s, ray_begin=12_345, ray_end=12_345 + 4_999, accel=accel)
+        assert np.array_equal(a.hits, b.hits), accel
+        assert np.array_equal(a.cells, b.cells), accel
+        assert np.array_equal(a.weights, b.weights), accel
     o = _oracle(cfg, 12_345, 12_345 + 4_999)
     rep, _ = compare_hits(a.hits, o.hits, o.flags, cfg.params.n_rays)
     assert rep["ok"], rep
@@ -61,6 +62,31 @@ def test_manhattan_reduced_parity(pol, pattern):
     print("manhattan", d)
     assert d["n_cells"] >= 100
     assert_parity(d)
+
+
+@pytest.mark.parametrize("scene_kind", ["manhattan", "large"])
+def test_tree_widths_match_brute_force(scene_kind):
+    """Binary LBVH, 4-wide tree and brute force: bit-identical hits on the
+    Manhattan scene and on a strided ray subset of the 1 M-triangle scene."""
+    if scene_kind == "manhattan":
+        cfg = sg.manhattan_config(n_rays=1_000_000)
+        ranges = [(0, 1_000_000)]
+        accels = (1, 2, 3)
+    else:
+        cfg = sg.large_config()
+        ranges = [(int(n), int(n) + 64) for n in np.linspace(0, cfg.params.n_rays - 64, 12)]
+        accels = (2, 3)           # brute force over 1 M triangles is too slow here
+    s = gpu_scene(cfg.scene)
+    for b, e in ranges:
+        ref = None
+        for accel in accels:
+            g = gpu_radio_map(cfg, scene_handle=s, ray_begin=b, ray_end=e, accel=accel)
+            if ref is None:
+                ref = g
+            else:
+                assert np.array_equal(ref.hits, g.hits), (accel, b)
+                assert np.array_equal(ref.cells, g.cells), (accel, b)
+                assert np.array_equal(ref.weights, g.weights), (accel, b)
 
 
 def test_dual_pol_matches_single_pols():
