@@ -10,10 +10,18 @@ all its segments through the LBVH, reflect, deposit.  The metric is traced
 segments ("ray-bounces", one closest-hit query each) per second, counted on
 the device.  Inputs are resident in HBM before timing starts.
 
+Before timing, rt_tune picks the launch configuration (tree width, launch
+order, workgroup size, deposit strategy, refill threshold) on a spread sample
+of the same lattice; its time is reported separately.
+
 Printed: one JSON line with the metric, a roofline object for the forward
-kernel (algorithmic bytes per launch from the node/triangle/deposit counters,
-over the kernel's event-timed duration), and the FP64 oracle timed on a
-bounded strided sample of the same lattice on one host core.
+kernel, and the FP64 oracle timed on a bounded sample of the same lattice on
+one host core.  Roofline: the Manhattan BVH and triangles (about 0.3 MB) stay
+in the L2 caches, so HBM does not bound this workload; the forward kernel is
+reported against the VALU issue rate (256 CUs x 64 lanes x 2.4 GHz = 39.3 T
+FP32 lane-operations/s) with an algorithmic operation count per segment
+(see ALU_OPS below); the algorithmic HBM byte model is reported beside it
+("hbm_model") and is meaningful on the 1 M-triangle scene ("large" leg).
 """
 from __future__ import annotations
 
@@ -29,6 +37,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SBR radio map M ray-bounces/s; fwd+bwd/fwd and batched vs plain at 1e-3 tol"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one FP32 lane-op each
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic FP32 operations per unit of work (the arithmetic the method needs,
+# one op per add/mul/fma/min/max/compare):
+#   slab test of one child box against a ray with precomputed inverse
+#     direction: 6 fma + 3 min + 3 max + 2 combine + 1 compare = 15
+#   watertight triangle test: 9 sub + 6 shear + 9 (U,V,W) + 3 scale + 5 (T) +
+#     1 div + 6 sign/range tests + 6 = 45
+#   per segment: ray set-up, plane crossing and weight, bounce (basis,
+#     Fresnel with complex sqrt and divisions, 2x2 complex update) = 250
+ALU_OPS = {"child_box": 15, "tri": 45, "segment": 250}
+# Algorithmic bytes (HBM byte model): per binary node visit 2 child boxes +
+# 2 refs = 56 B (a 4-wide node: 4 boxes + 4 refs = 112 B), per triangle test
+# 3 vertices + id = 40 B, per deposit a 4 B read-modify-write = 8 B
+NODE_BYTES = {2: 56, 4: 112}
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "forward_manhattan_counters.json")
 KERNEL_SOURCES = ["paper_2504_21719_amd/csrc/sbr_forward.hip", "paper_2504_21719_amd/csrc/sbr_common.h",
                   "paper_2504_21719_amd/csrc/rt_device.h"]
@@ -50,6 +73,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-extras", action="store_true", help="skip the fwd+bwd and batched ratio legs")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1 M-triangle leg")
+    ap.add_argument("--no-tune", action="store_true", help="use the untuned launch defaults")
+    ap.add_argument("--launch", default="", help="width,order,block,deposit,refill: apply instead of tuning")
     ap.add_argument("--calib-copy", action="store_true", help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run N forward steps (for rocprofv3)")
     return ap.parse_args()
@@ -58,8 +84,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the map would be "
-              "all-reduced over RCCL after tracing disjoint ray ranges; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the map would be "
+              "all-reduced over RCCL after tracing disjoint ray ranges).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -73,12 +99,22 @@ def main():
     torch.cuda.set_device(dev)
     cfg = sg.manhattan_config()
     scene = rt.scene_from_mesh(cfg.scene)
-    info = scene.info()
     eps = torch.tensor(cfg.scene.eps_r, dtype=torch.float32, device=dev)
     sig = torch.tensor(cfg.scene.sigma, dtype=torch.float32, device=dev)
     H, W = cfg.plane.H, cfg.plane.W
     out = torch.empty((1, H, W), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
+
+    # launch configuration from the autotuner (its own timing, outside the steps)
+    t0 = time.perf_counter()
+    if args.launch:
+        rt.rt_set_launch_config(scene, *[int(x) for x in args.launch.split(",")])
+    elif not args.no_tune:
+        rt.rt_tune(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, 2_000_000, out)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    info = scene.info()
+    width = info.tuned_width or 4
 
     if args.profile_steps:
         for _ in range(args.profile_steps):
@@ -89,7 +125,8 @@ def main():
             for _ in range(3):
                 b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_steps": args.profile_steps, "calib_copy_bytes": (64 << 20) * 4 if args.calib_copy else 0}))
+        print(json.dumps({"profile_steps": args.profile_steps,
+                          "calib_copy_bytes": (64 << 20) * 4 if args.calib_copy else 0}))
         return
 
     # device counters of one pass: segments, crossings, node visits, triangle tests
@@ -98,7 +135,6 @@ def main():
     torch.cuda.synchronize()
     st = stats.cpu().numpy().astype(np.int64)
     n_seg, n_cross, n_node, n_tri = int(st[0]), int(st[1]), int(st[2]), int(st[3])
-    alg_bytes = 56 * n_node + 40 * n_tri + 8 * n_cross
 
     for _ in range(args.warmup):
         rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out)
@@ -117,28 +153,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = n_seg / (ms_per_step * 1e-3) / 1e6
 
-    # forward-kernel duration: the same call with accumulate = 1 queues only the
-    # work-counter reset (one thread) besides the forward kernel
-    evk = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    for s, e in evk:
-        s.record(stream)
-        rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out, accumulate=1)
-        e.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = float(np.mean([s.elapsed_time(e) for s, e in evk]))
-    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-
-    traffic = None
-    try:
-        with open(PROFILE_COUNTERS) as f:
-            pc = json.load(f)
-        if pc.get("kernel_source_sha") == kernel_source_sha():
-            traffic = {"fetch_bytes": pc["fetch_bytes_per_launch"], "write_bytes": pc["write_bytes_per_launch"],
-                       "total_bytes": pc["fetch_bytes_per_launch"] + pc["write_bytes_per_launch"],
-                       "source": os.path.relpath(PROFILE_COUNTERS, ROOT)}
-    except (OSError, KeyError, ValueError):
-        traffic = None
-
+    kern_ms = kernel_ms(rt, scene, eps, sig, cfg, out, stream, args.steps)
     result = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -161,24 +176,109 @@ def main():
         "event_ms_per_step_median": round(float(np.median(step_ms)), 4),
         "build_ms": round(info.build_ms, 3),
         "bvh_depth": info.bvh_depth,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_forward<false>", "kernel_ms": round(kern_ms, 4),
-                     "alg_bytes_per_launch": int(alg_bytes),
-                     "byte_model": "56 B per node visit + 40 B per triangle test + 8 B per deposit",
-                     "node_visits": n_node, "tri_tests": n_tri},
+        "tuned": {"width": width, "order": "coherent" if info.tuned_order != 2 else "lattice",
+                  "block": info.tuned_block, "deposit": "wave" if info.tuned_deposit == 2 else "atomic",
+                  "refill": info.tuned_refill, "tune_s": round(tune_s, 3),
+                  "launch": "%d,%d,%d,%d,%d" % (info.tuned_width, info.tuned_order, info.tuned_block,
+                                                info.tuned_deposit, info.tuned_refill)},
+        "roofline": rooflines(n_seg, n_cross, n_node, n_tri, width, kern_ms, traffic_from_profile()),
     }
+    result["hbm_model"] = result["roofline"].pop("hbm_model")
 
     if not args.no_extras:
         try:
             result.update(extra_legs(rt, sg, cfg, scene, eps, sig, dev))
         except rt.RtError as e:
             result["extras_error"] = str(e)
-
+    if not args.no_large:
+        try:
+            result["large"] = large_leg(rt, sg, dev, args)
+        except rt.RtError as e:
+            result["large_error"] = str(e)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
 
     print(json.dumps(result), flush=True)
+
+
+def kernel_ms(rt, scene, eps, sig, cfg, out, stream, steps):
+    """Average duration of the forward launch alone: with accumulate = 1 a call
+    queues only the work-counter reset (one thread) and the launch-order
+    rotations (a few hundred threads) besides the forward kernel."""
+    import numpy as np
+    import torch
+    evk = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for s, e in evk:
+        s.record(stream)
+        rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out, accumulate=1)
+        e.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([s.elapsed_time(e) for s, e in evk]))
+
+
+def rooflines(n_seg, n_cross, n_node, n_tri, width, kern_ms, traffic,
+              note="the Manhattan tree and triangles stay in L2: this is a model, not DRAM traffic"):
+    """ALU roofline (primary) and the algorithmic HBM byte model for the forward kernel."""
+    ops = ALU_OPS["child_box"] * width * n_node + ALU_OPS["tri"] * n_tri + ALU_OPS["segment"] * n_seg
+    alg_bytes = NODE_BYTES[width] * n_node + 40 * n_tri + 8 * n_cross
+    t = kern_ms * 1e-3
+    alu = ops / t / 1e12
+    hbm = alg_bytes / t / 1e9
+    return {"bound": "alu", "achieved": round(alu, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+            "frac": round(alu / ALU_PEAK_TOPS, 4),
+            "traffic": (traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None,
+            "traffic_detail": traffic,
+            "op_unit": "one FP32 VALU lane-operation (add/mul/min/max/compare); peak = 256 CUs x 64 lanes x 2.4 GHz",
+            "kernel": "k_forward", "kernel_ms": round(kern_ms, 4), "alg_ops_per_launch": int(ops),
+            "ops_model": "%d per child box x %d children per node visit + %d per triangle test + %d per segment" % (
+                ALU_OPS["child_box"], width, ALU_OPS["tri"], ALU_OPS["segment"]),
+            "node_visits": n_node, "tri_tests": n_tri, "tree_width": width,
+            "hbm_model": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(hbm / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(alg_bytes),
+                          "byte_model": "%d B per node visit + 40 B per triangle test + 8 B per deposit" % NODE_BYTES[width],
+                          "note": note}}
+
+
+def traffic_from_profile():
+    try:
+        with open(PROFILE_COUNTERS) as f:
+            pc = json.load(f)
+        if pc.get("kernel_source_sha") == kernel_source_sha():
+            return {"fetch_bytes": pc["fetch_bytes_per_launch"], "write_bytes": pc["write_bytes_per_launch"],
+                    "calibration_factor": pc.get("calibration_factor"),
+                    "source": os.path.relpath(PROFILE_COUNTERS, ROOT)}
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
+
+def large_leg(rt, sg, dev, args, reps=3):
+    """1.02 M-triangle terrain + buildings, 1e8 rays, L = 8, 2 m cells: the
+    workload on which the tree no longer fits the L2 caches."""
+    import numpy as np
+    import torch
+    cfg = sg.large_config()
+    scene = rt.scene_from_mesh(cfg.scene)
+    eps = torch.tensor(cfg.scene.eps_r, dtype=torch.float32, device=dev)
+    sig = torch.tensor(cfg.scene.sigma, dtype=torch.float32, device=dev)
+    out = torch.empty((1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device=dev)
+    if not args.no_tune:
+        rt.rt_tune(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, 4_000_000, out)
+    info = scene.info()
+    width = info.tuned_width or 4
+    stats = torch.zeros(8, dtype=torch.int64, device=dev)
+    rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out, stats=stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy().astype(np.int64)
+    t = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out), reps, 1)
+    r = rooflines(int(st[0]), int(st[1]), int(st[2]), int(st[3]), width, t, None,
+                  note="tree + triangles about %d MB: larger than L2, partly held in the 256 MB MALL"
+                  % (info.device_bytes >> 20))
+    return {"workload": "large: 1,021,074 triangles, 1e8 rays, max depth 8, 1000x1000 cells of 2 m",
+            "value": round(int(st[0]) / (t * 1e-3) / 1e6, 3), "unit": "M ray-bounces/s", "ms_per_step": round(t, 3),
+            "segments_per_step": int(st[0]), "build_ms": round(info.build_ms, 3), "bvh_depth": info.bvh_depth,
+            "tuned_width": width, "roofline_hbm_model": r["hbm_model"],
+            "roofline_alu": {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac")}}
 
 
 def extra_legs(rt, sg, cfg, scene, eps, sig, dev, reps=5):

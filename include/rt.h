@@ -277,10 +277,12 @@ rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials materials,
 
 /* ------------------------------------------------------------- autotuner */
 /*
- * rt_tune -- time the forward kernel variants (workgroup size, deposit
- * strategy, wavefront refill threshold, launch order) on this scene, tx,
- * plane and params with the first `n_probe_rays` rays, and remember the
- * fastest for later calls on this scene (RT_DEPOSIT_AUTO, block_size 0).
+ * rt_tune -- time the forward kernel variants (tree width, launch order,
+ * workgroup size, deposit strategy, wavefront refill threshold) on this
+ * scene, tx, plane and params, with about `n_probe_rays` rays taken from
+ * eight sub-ranges spread over the lattice, and remember the fastest for
+ * later calls on this scene (accel RT_ACCEL_BVH, deposit RT_DEPOSIT_AUTO,
+ * block_size 0).
  * Writes the chosen block size and deposit strategy (host ints, may be NULL);
  * rt_scene_info_get reports the whole choice.
  * Launch order: by default each chunk of consecutive lattice indices is
@@ -293,6 +295,20 @@ rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_tx* tx,
                   const rt_plane* plane, const rt_sbr_params* params,
                   int64_t n_probe_rays, float* scratch_map, void* stream,
                   int32_t* chosen_block, int32_t* chosen_deposit);
+
+/*
+ * rt_set_launch_config -- apply a launch configuration reported earlier by
+ * rt_scene_info_get after rt_tune (tree width 2 or 4, order 1 coherent or
+ * 2 lattice, workgroup size, deposit strategy, refill threshold in lanes),
+ * so that a caller can reuse a tuning result without timing again.  A zero
+ * field selects the untuned default for that choice.  Results do not depend
+ * on the configuration beyond FP32 summation order.  Host-only: no device
+ * work, no synchronisation.
+ * Errors: RT_EINVAL for a NULL scene, a value outside the ranges above, or
+ * width 4 on a scene without a 4-wide tree (fewer than two triangles).
+ */
+rt_status rt_set_launch_config(rt_scene* scene, int32_t width, int32_t order,
+                               int32_t block, int32_t deposit, int32_t refill);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,7 @@ RT_POL_V, RT_POL_H, RT_POL_DUAL = 0, 1, 2
 
 EXPORTED = ["rt_last_error", "rt_build_scene", "rt_scene_destroy", "rt_scene_info_get", "rt_radio_map",
             "rt_tape_bytes", "rt_tape_create", "rt_tape_destroy", "rt_radio_map_backward",
-            "rt_radio_map_batched", "rt_tune"]
+            "rt_radio_map_batched", "rt_tune", "rt_set_launch_config"]
 
 
 class RtError(RuntimeError):
@@ -104,6 +104,8 @@ def lib():
     L.rt_tune.restype = C.c_int
     L.rt_tune.argtypes = [vp, rt_materials, C.POINTER(rt_tx), C.POINTER(rt_plane), C.POINTER(rt_sbr_params),
                           i64, vp, vp, C.POINTER(i32), C.POINTER(i32)]
+    L.rt_set_launch_config.restype = C.c_int
+    L.rt_set_launch_config.argtypes = [vp, i32, i32, i32, i32, i32]
     _lib = L
     return L
 
@@ -274,3 +276,8 @@ def rt_tune(scene: RtScene, eps_r, sigma, tx, plane, params, n_probe_rays, scrat
     _check(lib().rt_tune(scene.handle, materials(eps_r, sigma), C.byref(t), C.byref(pl), C.byref(p),
                          int(n_probe_rays), _ptr(scratch_map), _stream(stream), C.byref(b), C.byref(d)))
     return b.value, d.value
+
+
+def rt_set_launch_config(scene: RtScene, width=0, order=0, block=0, deposit=0, refill=0):
+    """Apply a launch configuration (as reported by RtScene.info() after rt_tune)."""
+    _check(lib().rt_set_launch_config(scene.handle, int(width), int(order), int(block), int(deposit), int(refill)))

@@ -95,7 +95,11 @@ extern "C" rt_status rt_scene_destroy(rt_scene* s) {
     (void)hipFree(s->spill);
     (void)hipFree(s->tx_desc);
     (void)hipFree(s->grad_ws);
-    (void)hipFree(s->order);
+    for (int i = 0; i < s->n_otab; i++) {
+        (void)hipFree(s->otab[i].perm);
+        (void)hipFree(s->otab[i].az);
+    }
+    (void)hipFree(s->shifts);
     (void)hipFree(s->geom_ws);
     (void)hipFree(s->bgrad_ws);
     if (s->tx_desc_host) (void)hipHostFree(s->tx_desc_host);
@@ -122,6 +126,24 @@ extern "C" rt_status rt_scene_info_get(const rt_scene* s, rt_scene_info* out) {
         out->lo[a] = s->lo[a];
         out->hi[a] = s->hi[a];
     }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_set_launch_config(rt_scene* s, int32_t width, int32_t order, int32_t block,
+                                         int32_t deposit, int32_t refill) {
+    CHECK_ARG(s != nullptr, "rt_set_launch_config: NULL scene");
+    CHECK_ARG(width == 0 || width == 2 || width == 4, "rt_set_launch_config: width must be 0, 2 or 4");
+    CHECK_ARG(width != 4 || s->wide != nullptr, "rt_set_launch_config: this scene has no 4-wide tree");
+    CHECK_ARG(order >= 0 && order <= 2, "rt_set_launch_config: order must be 0, 1 or 2");
+    CHECK_ARG(block == 0 || block == 64 || block == 128 || block == 256 || block == 512,
+              "rt_set_launch_config: block must be 0, 64, 128, 256 or 512");
+    CHECK_ARG(deposit >= 0 && deposit <= 2, "rt_set_launch_config: deposit must be 0, 1 or 2");
+    CHECK_ARG(refill >= 0 && refill <= 64, "rt_set_launch_config: refill must be in [0, 64]");
+    s->tuned_width = width;
+    s->tuned_order = order;
+    s->tuned_block = block;
+    s->tuned_deposit = deposit;
+    s->tuned_refill = refill;
     return RT_OK;
 }
 
@@ -243,10 +265,36 @@ static int pick_block(const rt_scene* s, const rt_sbr_params* p) {
     return 256;
 }
 
+// Untuned defaults (from a sweep on the Manhattan workload): same-cell
+// summation across the wavefront, refill once 48 lanes are idle, coherent
+// launch order, 4-wide tree.
 static int pick_deposit(const rt_scene* s, const rt_sbr_params* p) {
     if (p->deposit) return p->deposit;
     if (s->tuned_deposit) return s->tuned_deposit;
-    return RT_DEPOSIT_ATOMIC;
+    return RT_DEPOSIT_WAVE;
+}
+
+static int pick_refill(const rt_scene* s) {
+    int r = s->tuned_refill ? s->tuned_refill : 48;
+    if (const char* env = getenv("RTMAP_REFILL")) r = atoi(env);
+    return std::max(1, std::min(64, r));
+}
+
+static bool want_order(const rt_scene* s) {
+    const char* env = getenv("RTMAP_ORDER");
+    if (env) return env[0] != '0';
+    return s->tuned_order != 2;
+}
+
+// Launch-order table for an N-ray lattice and room for its chunk rotations
+// (synchronous on first use of a chunk size or a larger lattice).
+static rt_status prepare_order(rt_scene* s, int64_t N, size_t chunks_total, int log2m, hipStream_t st,
+                               const rt_scene::OrderTable** out) {
+    *out = nullptr;
+    if (!want_order(s) || N < 4096) return RT_OK;
+    rt_status r = rt_order_table(s, log2m, st, out);
+    if (r != RT_OK) return r;
+    return rt_order_reserve(s, chunks_total, st);
 }
 
 static rt_status check_device(const rt_scene* s) {
@@ -287,17 +335,12 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
     f.accel = params->accel;
     f.deposit = pick_deposit(scene, params);
     f.block = pick_block(scene, params);
-    f.refill = scene->tuned_refill ? scene->tuned_refill : 1;
-    if (const char* env = getenv("RTMAP_REFILL")) f.refill = std::max(1, std::min(64, atoi(env)));
+    f.refill = pick_refill(scene);
     {
-        // coherent launch order: on unless tuned off or RTMAP_ORDER=0
-        const char* env = getenv("RTMAP_ORDER");
-        bool want = scene->tuned_order != 2 && !(env && env[0] == '0');
-        if (want && params->n_rays >= 4096) {
-            rt_status ro = rt_lattice_order(const_cast<rt_scene*>(scene), params->n_rays, (hipStream_t)stream);
-            if (ro != RT_OK) return ro;
-        }
-        f.ordered = want;
+        int l = rt_order_log2m(params->n_rays);
+        rt_status ro = prepare_order(const_cast<rt_scene*>(scene), params->n_rays,
+                                     (size_t)(params->n_rays >> l), l, (hipStream_t)stream, &f.order);
+        if (ro != RT_OK) return ro;
     }
     f.zero_map = params->accumulate == 0;
     f.map = out_map;
@@ -429,14 +472,30 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     int64_t* hp = (int64_t*)(hb.data() + sizeof(TxDesc) * n_tx);
     int32_t* hslot = (int32_t*)(hb.data() + sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1));
     int64_t total = 0;
+    // one launch-order chunk size for the whole batch (from the largest lattice)
+    const int olog2m = rt_order_log2m(rays_per_tx[order[0]]);
+    int64_t chunks_total = 0, max_chunks = 0;
     for (int i = 0; i < n_tx; i++) {
         int t = order[i];
         fill_tx(&txs[t], rays_per_tx[t], plane, params->freq_hz, &hd[i]);
+        hd[i].n_chunks = rays_per_tx[t] >> olog2m;
+        hd[i].shift0 = chunks_total;
+        chunks_total += hd[i].n_chunks;
+        max_chunks = std::max(max_chunks, hd[i].n_chunks);
         hp[i] = total;
         hslot[i] = t;
         total += rays_per_tx[t];
     }
     hp[n_tx] = total;
+    const rt_scene::OrderTable* otab = nullptr;
+    {
+        rt_status ro = prepare_order(s, rays_per_tx[order[0]], (size_t)chunks_total, olog2m, hs, &otab);
+        if (ro != RT_OK) return ro;
+        if (!otab) {
+            for (int i = 0; i < n_tx; i++) hd[i].n_chunks = 0;
+            max_chunks = 0;
+        }
+    }
     BatchLaunch bl{};
     bl.scene = scene;
     bl.eps_r = materials.eps_r;
@@ -448,10 +507,15 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     bl.L = params->max_depth;
     bl.t_min = params->t_min;
     bl.block = pick_block(scene, params);
+    bl.deposit = pick_deposit(scene, params);
+    bl.refill = pick_refill(scene);
+    bl.order = otab;
+    bl.max_chunks = max_chunks;
     bl.maps = out_maps;
     bl.grad_maps = grad_maps;
     bl.grads = grads;
-    // identity of the whole step: descriptors, pointers and sizes
+    // identity of the whole step: descriptors, pointers (including the
+    // library workspaces the captured kernels read) and sizes
     uint64_t key = 1469598103934665603ull;
     key = mix(key, hb.data(), hb.size());
     const void* ptrs[5] = {materials.eps_r, materials.sigma, out_maps, grad_maps, grads};
@@ -462,7 +526,13 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     key = mix(key, &bl.block, sizeof(bl.block));
     key = mix(key, &n_samples, sizeof(n_samples));
     key = mix(key, &params->freq_hz, sizeof(double));
-    key = mix(key, &s->tuned_deposit, sizeof(int));
+    key = mix(key, &bl.deposit, sizeof(int));
+    key = mix(key, &bl.refill, sizeof(int));
+    const void* ws[6] = {otab, s->shifts, s->tx_desc, s->geom_ws, s->bgrad_ws, s->wide};
+    key = mix(key, ws, sizeof(ws));
+    int width = s->tuned_width;
+    if (const char* env = getenv("RTMAP_WIDTH")) width = atoi(env);
+    key = mix(key, &width, sizeof(width));
     const bool use_graph = getenv("RTMAP_NO_GRAPH") == nullptr;
     if (use_graph && s->graph_exec && s->graph_key == key) {
         hipError_t he = hipGraphLaunch(s->graph_exec, hs);
@@ -533,64 +603,84 @@ extern "C" rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_t
                              void* stream, int32_t* chosen_block, int32_t* chosen_deposit) {
     CHECK_ARG(scene != nullptr && scratch_map != nullptr, "rt_tune: NULL argument");
     CHECK_ARG(n_probe_rays >= 1, "rt_tune: n_probe_rays must be >= 1");
-    rt_sbr_params p = *params;
-    p.ray_begin = 0;
-    p.ray_end = std::min<int64_t>(n_probe_rays, params->n_rays);
-    p.accumulate = 0;
+    int64_t b0, e0r;
+    rt_status r = check_params(params, &b0, &e0r);
+    if (r != RT_OK) return r;
     hipStream_t st = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    hipError_t he = hipEventCreate(&e0);
-    if (he == hipSuccess) he = hipEventCreate(&e1);
+    // probe: eight sub-ranges spread evenly over the lattice, aligned to the
+    // launch-order chunks, so that every direction band is represented
+    const int64_t N = params->n_rays;
+    const int64_t M = (int64_t)1 << rt_order_log2m(N);
+    const int n_sub = 8;
+    int64_t sub = std::min<int64_t>(N, std::max<int64_t>(M, ((n_probe_rays / n_sub + M - 1) / M) * M));
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    for (int i = 0; i < n_sub; i++) {
+        int64_t b = ((N - sub) * i / std::max(1, n_sub - 1)) / M * M;
+        ranges.push_back({b, std::min(N, b + sub)});
+        if (sub >= N) break;
+    }
+    hipEvent_t ev0, ev1;
+    hipError_t he = hipEventCreate(&ev0);
+    if (he == hipSuccess) he = hipEventCreate(&ev1);
     if (he != hipSuccess) return rt_hip_fail(he, "rt_tune: hipEventCreate");
-    // search: workgroup size x deposit strategy x wavefront refill threshold
-    // ("rays per wave" taken at once) x launch order; the traversal stack
-    // depth is fixed at compile time and spills to memory beyond it
+    rt_sbr_params p = *params;
+    p.accel = RT_ACCEL_BVH;
+    auto run_once = [&]() -> rt_status {
+        for (size_t i = 0; i < ranges.size(); i++) {
+            p.ray_begin = ranges[i].first;
+            p.ray_end = ranges[i].second;
+            p.accumulate = i ? 1 : 0;
+            rt_status q = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
+            if (q != RT_OK) return q;
+        }
+        return RT_OK;
+    };
+    // search: tree width x launch order x workgroup size x deposit strategy x
+    // wavefront refill threshold ("rays per wave" taken at once); the LDS part
+    // of the traversal stack is fixed at compile time and spills beyond it
     const int blocks[] = {128, 256, 512};
     const int deps[] = {RT_DEPOSIT_ATOMIC, RT_DEPOSIT_WAVE};
-    const int refills[] = {1, 32};
+    const int refills[] = {32, 56};
     const int orders[] = {1, 2};
     const int widths[] = {4, 2};
     float best = 1e30f;
-    int bb = 256, bd = RT_DEPOSIT_ATOMIC, br = 1, bo = 1, bw = 4;
-    rt_status r = RT_OK;
+    int bb = 256, bd = RT_DEPOSIT_WAVE, br = 48, bo = 1, bw = 4;
     const int saved[5] = {scene->tuned_block, scene->tuned_deposit, scene->tuned_refill, scene->tuned_order,
                           scene->tuned_width};
-    p.accel = RT_ACCEL_BVH;
     for (int wi : widths)
-    for (int oi : orders)
-        for (int bi : blocks)
-            for (int di : deps)
-                for (int ri : refills) {
-                    if (r != RT_OK) break;
-                    if (wi == 4 && !scene->wide) continue;
-                    p.block_size = bi;
-                    p.deposit = di;
-                    scene->tuned_refill = ri;
-                    scene->tuned_order = oi;
-                    scene->tuned_width = wi;
-                    // one warm-up, then the median of three timed runs
-                    r = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
-                    if (r != RT_OK) break;
-                    float ts[3] = {0, 0, 0};
-                    for (int rep = 0; rep < 3 && r == RT_OK; rep++) {
-                        (void)hipEventRecord(e0, st);
-                        r = rt_radio_map(scene, materials, tx, plane, &p, scratch_map, nullptr, nullptr, stream);
-                        (void)hipEventRecord(e1, st);
-                        (void)hipEventSynchronize(e1);
-                        (void)hipEventElapsedTime(&ts[rep], e0, e1);
+        for (int oi : orders)
+            for (int bi : blocks)
+                for (int di : deps)
+                    for (int ri : refills) {
+                        if (r != RT_OK) break;
+                        if (wi == 4 && !scene->wide) continue;
+                        p.block_size = bi;
+                        p.deposit = di;
+                        scene->tuned_refill = ri;
+                        scene->tuned_order = oi;
+                        scene->tuned_width = wi;
+                        r = run_once();   // warm-up (also builds order tables)
+                        if (r != RT_OK) break;
+                        float ts[3] = {0, 0, 0};
+                        for (int rep = 0; rep < 3 && r == RT_OK; rep++) {
+                            (void)hipEventRecord(ev0, st);
+                            r = run_once();
+                            (void)hipEventRecord(ev1, st);
+                            (void)hipEventSynchronize(ev1);
+                            (void)hipEventElapsedTime(&ts[rep], ev0, ev1);
+                        }
+                        std::sort(ts, ts + 3);
+                        if (r == RT_OK && ts[1] < best) {
+                            best = ts[1];
+                            bb = bi;
+                            bd = di;
+                            br = ri;
+                            bo = oi;
+                            bw = wi;
+                        }
                     }
-                    std::sort(ts, ts + 3);
-                    if (r == RT_OK && ts[1] < best) {
-                        best = ts[1];
-                        bb = bi;
-                        bd = di;
-                        br = ri;
-                        bo = oi;
-                        bw = wi;
-                    }
-                }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
     if (r != RT_OK) {
         scene->tuned_block = saved[0];
         scene->tuned_deposit = saved[1];

@@ -61,10 +61,17 @@ struct rt_scene {
     int tuned_deposit = 0;
     int tuned_refill = 0;     // refill a wavefront once this many lanes are idle
     int tuned_order = 0;      // 1 coherent launch order, 2 lattice order
-    // coherent launch order of the last N-ray lattice (device permutation)
-    int* order = nullptr;
-    int64_t order_n = 0;
-    int64_t order_chunk = 0;
+    // coherent launch order: per chunk size 2^log2m, the azimuth-sorted order
+    // of j in [0, 2^log2m) (perm) and its sorted azimuths (az); any chunk's
+    // order is a rotation of it (see rt_order_table)
+    struct OrderTable {
+        int log2m = 0;
+        int* perm = nullptr;
+        unsigned* az = nullptr;
+    } otab[12];
+    int n_otab = 0;
+    int* shifts = nullptr;          // per-call rotation of every full chunk
+    size_t shifts_cap = 0;
     // backward workspace: per-block FP64 partial sums
     void* grad_ws = nullptr;
     size_t grad_ws_bytes = 0;
@@ -112,6 +119,8 @@ struct TxDesc {
     float q;
     int32_t pol;             // 0 V, 1 H, 2 dual
     int64_t n_rays;          // N_S of this transmitter's lattice
+    int64_t shift0;          // first entry of this lattice's chunks in the shift table
+    int64_t n_chunks;        // full chunks of the launch order (0 = lattice order)
     float kappa;             // lambda^2 / (4 pi N_S dx dy)
     int32_t pad;
 };
@@ -145,7 +154,7 @@ struct FwdLaunch {
     int deposit;             // 1 atomic, 2 wave
     int block;
     int refill;              // 1..64
-    bool ordered;            // use the scene's coherent launch order
+    const rt_scene::OrderTable* order;   // coherent launch order, or null
     bool zero_map;
     float* map;
     rt_tape* tape;
@@ -186,6 +195,10 @@ struct BatchLaunch {
     int32_t L;
     float t_min;
     int block;
+    int deposit;
+    int refill;
+    const rt_scene::OrderTable* order;   // coherent launch order, or null
+    int64_t max_chunks;      // largest number of full chunks of one lattice
     float* maps;             // [n_tx][S][H][W]
     const float* grad_maps;  // [n_tx][S][H][W] or null
     float* grads;            // [n_tx][S][2 n_mat + 3] or null
@@ -194,7 +207,8 @@ rt_status rt_batched_workspace(const BatchLaunch& b, hipStream_t st);
 rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st);
 
 rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const float* sigma, const PlaneDesc& pl,
-                                  int L, float t_min, int block, int deposit, const TxDesc* txs,
+                                  int L, float t_min, int block, int deposit, int refill,
+                                  const rt_scene::OrderTable* order, int64_t max_chunks, const TxDesc* txs,
                                   const int64_t* prefix, const int32_t* slots, int n_tx, int64_t total_rays,
                                   bool geom_only, float* maps, int64_t slot_stride, int64_t zero_floats,
                                   float4* geom_seg, int* geom_nseg, hipStream_t st);
@@ -205,4 +219,14 @@ int rt_persistent_blocks(int block, int device);
 // entry per level; the wide tree at most three per wide level, and a wide
 // level spans at least one binary level.
 inline int64_t rt_stack_need(const rt_scene* s) { return 3 * (int64_t)s->depth + 2; }
-rt_status rt_lattice_order(rt_scene* s, int64_t N, hipStream_t st);
+
+// Coherent launch order.  rt_order_log2m picks the chunk size for an N-ray
+// lattice; rt_order_table builds (once, synchronously) the sorted order of a
+// chunk; rt_order_reserve grows the shift table (synchronously, outside any
+// capture); rt_order_shifts_* queue the per-chunk rotations.
+int rt_order_log2m(int64_t N);
+rt_status rt_order_table(rt_scene* s, int log2m, hipStream_t st, const rt_scene::OrderTable** out);
+rt_status rt_order_reserve(rt_scene* s, size_t entries, hipStream_t st);
+void rt_order_shifts_single(const rt_scene::OrderTable* t, int64_t N, int* shifts, hipStream_t st);
+void rt_order_shifts_multi(const rt_scene::OrderTable* t, const TxDesc* txs, int n_tx, int64_t max_chunks,
+                           int* shifts, hipStream_t st);

@@ -296,11 +296,10 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
     const int64_t HW = (int64_t)b.pl.W * b.pl.H;
     const int S = b.n_samples;
     const bool grad = b.grad_maps != nullptr;
-    const int deposit = s->tuned_deposit ? s->tuned_deposit : RT_DEPOSIT_ATOMIC;
     if (S == 1 && !grad) {
-        return rt_launch_forward_multi(s, b.eps_r, b.sigma, b.pl, b.L, b.t_min, b.block, deposit, b.tx_dev,
-                                       b.prefix_dev, b.tx_slot_dev, b.n_tx, b.total_rays, false, b.maps, HW,
-                                       HW * b.n_tx, nullptr, nullptr, st);
+        return rt_launch_forward_multi(s, b.eps_r, b.sigma, b.pl, b.L, b.t_min, b.block, b.deposit, b.refill,
+                                       b.order, b.max_chunks, b.tx_dev, b.prefix_dev, b.tx_slot_dev, b.n_tx,
+                                       b.total_rays, false, b.maps, HW, HW * b.n_tx, nullptr, nullptr, st);
     }
     size_t need = sizeof(float4) * 2 * (size_t)(b.L + 1) * (size_t)b.total_rays + sizeof(int) * (size_t)b.total_rays;
     const int P = 2 * s->n_mat + 3;
@@ -313,9 +312,9 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
         hipLaunchKernelGGL(k_zero_d, dim3((unsigned)std::min<int64_t>(1024, (ng + 255) / 256)), dim3(256), 0, st,
                            (double*)s->bgrad_ws, ng);
     }
-    rt_status r = rt_launch_forward_multi(s, b.eps_r, b.sigma, b.pl, b.L, b.t_min, b.block, deposit, b.tx_dev,
-                                          b.prefix_dev, b.tx_slot_dev, b.n_tx, b.total_rays, true, b.maps, HW,
-                                          HW * b.n_tx * S, geom, nseg, st);
+    rt_status r = rt_launch_forward_multi(s, b.eps_r, b.sigma, b.pl, b.L, b.t_min, b.block, b.deposit, b.refill,
+                                          b.order, b.max_chunks, b.tx_dev, b.prefix_dev, b.tx_slot_dev, b.n_tx,
+                                          b.total_rays, true, b.maps, HW, HW * b.n_tx * S, geom, nseg, st);
     if (r != RT_OK) return r;
     SampArgs a;
     a.geom = geom;

@@ -57,8 +57,9 @@ struct FwdArgs {
     int64_t spill_stride;
     int spill_depth;
     int tape_groups;         // float4 records per segment on the tape (4, or 2 = geometry only)
-    const int* order;        // coherent launch order of the lattice, or null
-    int64_t order_chunk;     // the order permutes within chunks of this many indices
+    const int* operm;        // coherent launch order: sorted chunk order, or null
+    const int* oshift;       // rotation of every full chunk
+    int olog2m;              // chunk size 2^olog2m
     int64_t ray_end;
     int refill;              // refill a wavefront once this many lanes are idle
     // several transmitters (MODE_MULTI, MODE_GEOM): device tables
@@ -315,13 +316,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                         rid = (int64_t)my;
                         int64_t n;
                         TxDesc td;
+                        const int64_t M = (int64_t)1 << a.olog2m;
                         if (MODE == MODE_SINGLE) {
                             n = a.ray_begin + rid;
-                            if (a.order) {
-                                // permuted only inside chunks that the range covers entirely
-                                int64_t c0 = (n / a.order_chunk) * a.order_chunk;
-                                if (c0 >= a.ray_begin && min(c0 + a.order_chunk, a.tx.n_rays) <= a.ray_end)
-                                    n = a.order[n];
+                            if (a.operm) {
+                                // permuted only inside full chunks that the range covers
+                                int64_t c = n >> a.olog2m, c0 = c << a.olog2m;
+                                if (c < (a.tx.n_rays >> a.olog2m) && c0 >= a.ray_begin && c0 + M <= a.ray_end)
+                                    n = c0 + a.operm[((n - c0) + a.oshift[c]) & (M - 1)];
                             }
                             rid = n - a.ray_begin;   // records stay indexed by lattice index
                             td = a.tx;
@@ -329,6 +331,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                             int t = find_tx(a.prefix, a.n_tx, rid);
                             n = rid - a.prefix[t];
                             td = a.txs[t];
+                            if (a.operm && (n >> a.olog2m) < td.n_chunks) {
+                                int64_t c = n >> a.olog2m, c0 = c << a.olog2m;
+                                n = c0 + a.operm[((n - c0) + a.oshift[td.shift0 + c]) & (M - 1)];
+                                rid = a.prefix[t] + n;   // the geometry tape is indexed by lattice index
+                            }
                             kap = td.kappa;
                             mapb = a.map + (int64_t)a.slots[t] * a.slot_stride;
                         }
@@ -588,9 +595,10 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
     a.stats = f.stats;
     a.refill = std::max(1, std::min(64, f.refill));
     a.ray_end = f.ray_end;
-    if (f.ordered && s->order && s->order_n == f.tx.n_rays) {
-        a.order = s->order;
-        a.order_chunk = s->order_chunk;
+    if (f.order) {
+        a.operm = f.order->perm;
+        a.oshift = s->shifts;
+        a.olog2m = f.order->log2m;
     }
     int blocks = 0;
     rt_status r = size_spill(a, s, f.block, &blocks);
@@ -601,6 +609,7 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
         int g = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (zn + 255) / 256));
         hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, f.map, zn, s->counters);
     }
+    if (f.order) rt_order_shifts_single(f.order, f.tx.n_rays, s->shifts, st);
     if (a.n_work > 0) launch_mode<MODE_SINGLE>(a, f.accel, use_wide(s, f.accel), blocks, f.block, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rt_hip_fail(e, "forward launch");
@@ -611,7 +620,8 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
 // into maps[slot] (one material set, map stride slot_stride, maps zeroed
 // here); geom_only = true: write the geometry tape (2 records per segment).
 rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const float* sigma, const PlaneDesc& pl,
-                                  int L, float t_min, int block, int deposit, const TxDesc* txs,
+                                  int L, float t_min, int block, int deposit, int refill,
+                                  const rt_scene::OrderTable* order, int64_t max_chunks, const TxDesc* txs,
                                   const int64_t* prefix, const int32_t* slots, int n_tx, int64_t total_rays,
                                   bool geom_only, float* maps, int64_t slot_stride, int64_t zero_floats,
                                   float4* geom_seg, int* geom_nseg, hipStream_t st) {
@@ -627,6 +637,12 @@ rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const f
     a.slots = slots;
     a.n_tx = n_tx;
     a.slot_stride = slot_stride;
+    a.refill = std::max(1, std::min(64, refill));
+    if (order) {
+        a.operm = order->perm;
+        a.oshift = s->shifts;
+        a.olog2m = order->log2m;
+    }
     if (geom_only) {
         a.tape_seg = geom_seg;
         a.tape_nseg = geom_nseg;
@@ -638,6 +654,7 @@ rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const f
     if (r != RT_OK) return r;
     int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (zero_floats + 255) / 256));
     hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, maps, zero_floats, s->counters);
+    if (order) rt_order_shifts_multi(order, txs, n_tx, max_chunks, s->shifts, st);
     if (total_rays > 0) {
         if (geom_only) launch_mode<MODE_GEOM>(a, RT_ACCEL_BVH, use_wide(s), blocks, block, st);
         else launch_mode<MODE_MULTI>(a, RT_ACCEL_BVH, use_wide(s), blocks, block, st);

@@ -438,6 +438,39 @@ __global__ void k_order_keys(int64_t N, int64_t M, uint64_t* __restrict__ keys, 
     vals[n] = (uint32_t)n;
 }
 
+__global__ void k_low32(const uint64_t* __restrict__ k, unsigned* __restrict__ out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (unsigned)(k[i] & 0xffffffffu);
+}
+
+// Rotation of every full chunk c of a lattice: the azimuths of the rays
+// c M + j are those of j shifted by the (fixed-point) azimuth of c M, so the
+// chunk's sorted order starts at the first sorted j whose azimuth is at
+// least 2^32 minus that shift.  (Carries from the low 32 bits are ignored:
+// the order only needs to be nearly sorted.)
+__global__ void k_order_shifts(const TxDesc* __restrict__ txs, int64_t N1, int log2m, const unsigned* __restrict__ az,
+                               int* __restrict__ shifts, int64_t max_chunks) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t chunks, base;
+    if (txs) {
+        chunks = txs[blockIdx.y].n_chunks;
+        base = txs[blockIdx.y].shift0;
+    } else {
+        chunks = N1 >> log2m;
+        base = 0;
+    }
+    if (c >= chunks || c >= max_chunks) return;
+    unsigned off = (unsigned)(((uint64_t)(c << log2m) * 0x9e3779b97f4a7c16ull) >> 32);
+    unsigned target = 0u - off;
+    int lo = 0, hi = 1 << log2m;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (az[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    shifts[base + c] = (lo == (1 << log2m)) ? 0 : lo;
+}
+
 }  // namespace
 
 // LSD radix sort of (key, value) pairs on the low `bits` bits of the keys.
@@ -461,55 +494,91 @@ int rt_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_
     return which;
 }
 
-// Build (or reuse) the coherent launch order of an N-ray lattice: within each
-// chunk of M consecutive indices the rays are sorted by azimuth, so the 64
-// lanes of a wavefront start on a small patch of directions.  Returns the
-// device permutation (lattice index at each work position) or nullptr.
-rt_status rt_lattice_order(rt_scene* s, int64_t N, hipStream_t st) {
-    if (s->order && s->order_n == N) return RT_OK;
-    (void)hipStreamSynchronize(st);
-    (void)hipFree(s->order);
-    s->order = nullptr;
-    s->order_n = 0;
-    if (N < 4096 || N > 0x7fffffffll) return RT_OK;
+int rt_order_log2m(int64_t N) {
     // wave patches of roughly equal extent in polar and azimuthal angle:
-    // a chunk spans 2M/N in z, a wave 2 pi 64/M in azimuth -> M^2 = 64 pi N
-    int64_t M = (int64_t)std::sqrt(64.0 * 3.14159265358979 * (double)N);
-    M = std::max<int64_t>(4096, ((M + 63) / 64) * 64);
-    int64_t chunks = (N + M - 1) / M;
-    int bits = 32;
-    while (((int64_t)1 << (bits - 32)) < chunks) bits++;
-    bits = ((bits + 7) / 8) * 8;
+    // a chunk spans 2M/N in z, a wave 2 pi 64/M in azimuth -> M^2 ~ 64 pi N
+    double m = std::sqrt(64.0 * 3.14159265358979 * (double)N);
+    int l = (int)std::lround(std::log2(std::max(m, 1.0)));
+    return std::max(12, std::min(18, l));
+}
+
+// Sorted azimuths of j in [0, 2^log2m): key = top 32 bits of j (phi_g - 1)
+// in 64-bit fixed point.
+rt_status rt_order_table(rt_scene* s, int log2m, hipStream_t st, const rt_scene::OrderTable** out) {
+    for (int i = 0; i < s->n_otab; i++)
+        if (s->otab[i].log2m == log2m) {
+            *out = &s->otab[i];
+            return RT_OK;
+        }
+    if (s->n_otab >= 12) return rt_fail(RT_EINVAL, "launch order: too many chunk sizes");
+    const int64_t M = (int64_t)1 << log2m;
     uint64_t *k0 = nullptr, *k1 = nullptr;
     uint32_t *v0 = nullptr, *v1 = nullptr;
-    unsigned* hist = nullptr;
-    const int rs_blocks = (int)((N + kRsTile - 1) / kRsTile);
+    unsigned *hist = nullptr, *az = nullptr;
+    const int rs_blocks = (int)((M + kRsTile - 1) / kRsTile);
     bool keep = false;
     auto cleanup = [&]() {
         (void)hipFree(k0);
         (void)hipFree(k1);
         (void)hipFree(v1);
         (void)hipFree(hist);
-        if (!keep) (void)hipFree(v0);
+        if (!keep) {
+            (void)hipFree(v0);
+            (void)hipFree(az);
+        }
     };
-    HIPCHK(hipMalloc(&k0, sizeof(uint64_t) * N));
-    HIPCHK(hipMalloc(&k1, sizeof(uint64_t) * N));
-    HIPCHK(hipMalloc(&v0, sizeof(uint32_t) * N));
-    HIPCHK(hipMalloc(&v1, sizeof(uint32_t) * N));
+    HIPCHK(hipMalloc(&k0, sizeof(uint64_t) * M));
+    HIPCHK(hipMalloc(&k1, sizeof(uint64_t) * M));
+    HIPCHK(hipMalloc(&v0, sizeof(uint32_t) * M));
+    HIPCHK(hipMalloc(&v1, sizeof(uint32_t) * M));
+    HIPCHK(hipMalloc(&az, sizeof(unsigned) * M));
     HIPCHK(hipMalloc(&hist, sizeof(unsigned) * 256 * (size_t)rs_blocks));
-    hipLaunchKernelGGL(k_order_keys, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, st, N, M, k0, v0);
-    int which = rt_radix_sort(k0, v0, k1, v1, N, bits, hist, st);
-    if (which) std::swap(v0, v1);
+    hipLaunchKernelGGL(k_order_keys, dim3(grid_for(M, kBlock)), dim3(kBlock), 0, st, M, M, k0, v0);
+    int which = rt_radix_sort(k0, v0, k1, v1, M, 32, hist, st);
+    if (which) {
+        std::swap(v0, v1);
+        std::swap(k0, k1);
+    }
+    hipLaunchKernelGGL(k_low32, dim3(grid_for(M, kBlock)), dim3(kBlock), 0, st, k0, az, M);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     keep = true;
     cleanup();
-    s->order = (int*)v0;
-    s->order_n = N;
-    s->order_chunk = M;
+    rt_scene::OrderTable& t = s->otab[s->n_otab++];
+    t.log2m = log2m;
+    t.perm = (int*)v0;
+    t.az = az;
+    s->bytes += sizeof(int) * 2 * M;
+    *out = &t;
     return RT_OK;
 }
 
+rt_status rt_order_reserve(rt_scene* s, size_t entries, hipStream_t st) {
+    if (s->shifts_cap >= entries) return RT_OK;
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(s->shifts);
+    s->shifts = nullptr;
+    s->shifts_cap = 0;
+    size_t cap = std::max<size_t>(entries, 4096);
+    hipError_t e = hipMalloc(&s->shifts, sizeof(int) * cap);
+    if (e != hipSuccess) return rt_hip_fail(e, "launch order: shift table");
+    s->shifts_cap = cap;
+    return RT_OK;
+}
+
+void rt_order_shifts_single(const rt_scene::OrderTable* t, int64_t N, int* shifts, hipStream_t st) {
+    int64_t chunks = N >> t->log2m;
+    if (chunks <= 0) return;
+    hipLaunchKernelGGL(k_order_shifts, dim3(grid_for(chunks, kBlock), 1), dim3(kBlock), 0, st,
+                       (const TxDesc*)nullptr, N, t->log2m, (const unsigned*)t->az, shifts, chunks);
+}
+
+void rt_order_shifts_multi(const rt_scene::OrderTable* t, const TxDesc* txs, int n_tx, int64_t max_chunks,
+                           int* shifts, hipStream_t st) {
+    if (max_chunks <= 0) return;
+    hipLaunchKernelGGL(k_order_shifts, dim3(grid_for(max_chunks, kBlock), n_tx), dim3(kBlock), 0, st, txs,
+                       (int64_t)0, t->log2m, (const unsigned*)t->az, shifts, max_chunks);
+}
 
 rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t* F, const int32_t* M,
                         hipStream_t st) {

@@ -126,6 +126,7 @@ def test_null_arguments_rejected():
     assert L.rt_build_scene(None, 3, None, 5, None, 1, None, C.byref(h)) == rt.RT_EINVAL
     assert L.rt_build_scene(None, 0, None, 0, None, 0, None, C.byref(h)) == rt.RT_EINVAL
     assert L.rt_scene_destroy(None) == rt.RT_OK
+    assert L.rt_set_launch_config(None, 4, 1, 256, 2, 48) == rt.RT_EINVAL
     assert L.rt_tape_destroy(None) == rt.RT_OK
     assert L.rt_tape_bytes(C.byref(_params(n_rays=0))) == 0
     assert L.rt_tape_bytes(C.byref(_params(n_rays=100, max_depth=3))) == 100 * 4 * 64 + 100 * 4

@@ -125,6 +125,26 @@ def test_ranges_accumulate_and_deposit_modes():
     np.testing.assert_allclose(out.cpu().numpy(), full.map, rtol=2e-5, atol=1e-30)
 
 
+def test_launch_config_roundtrip():
+    """rt_set_launch_config reapplies a configuration; every choice gives the
+    same map up to FP32 summation order, and bad values are refused."""
+    import paper_2504_21719_amd as rt
+    cfg = sg.manhattan_config(n_rays=300_001, max_depth=4)
+    cfg.plane = sg.Plane(1.5, -500.0, -500.0, 10.0, 10.0, 100, 100)
+    s = gpu_scene(cfg.scene)
+    ref = gpu_radio_map(cfg, scene_handle=s, records=False)
+    for conf in [(2, 2, 128, 1, 32), (4, 1, 512, 2, 56), (4, 2, 64, 1, 1), (2, 1, 256, 2, 64)]:
+        rt.rt_set_launch_config(s, *conf)
+        i = s.info()
+        assert (i.tuned_width, i.tuned_order, i.tuned_block, i.tuned_deposit, i.tuned_refill) == conf
+        g = gpu_radio_map(cfg, scene_handle=s, records=False)
+        np.testing.assert_allclose(g.map, ref.map, rtol=2e-5, atol=1e-30)
+    for bad in [(3, 1, 256, 2, 48), (4, 3, 256, 2, 48), (4, 1, 96, 2, 48), (4, 1, 256, 3, 48), (4, 1, 256, 2, 65)]:
+        with pytest.raises(rt.RtError):
+            rt.rt_set_launch_config(s, *bad)
+    rt.rt_set_launch_config(s)
+
+
 def test_degenerate_inputs():
     """Empty scene, a single triangle, one ray, depth 0."""
     pl = sg.Plane(1.5, -20.0, -20.0, 1.0, 1.0, 40, 40)
