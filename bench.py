@@ -78,11 +78,52 @@ def parse():
     ap.add_argument("--launch", default="", help="width,order,block,deposit,refill: apply instead of tuning")
     ap.add_argument("--calib-copy", action="store_true", help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run N forward steps (for rocprofv3)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs of a --profile-steps --calib-copy "
+                         "run into the per-launch traffic record, then exit")
     return ap.parse_args()
+
+
+CALIB_COPY_BYTES = (64 << 20) * 4
+
+
+def ingest_counters(fetch_csv, write_csv):
+    """Per-launch HBM traffic of the forward kernel from two counter runs.
+
+    Each run holds the forward dispatches and three plain device copies of
+    CALIB_COPY_BYTES; a counter's scale factor is the copy's true byte count
+    over what the counter reports for it."""
+    import csv
+    out = {"kernel_source_sha": kernel_source_sha(), "kernel": "k_forward (single transmitter, 4-wide tree)",
+           "workload": "manhattan, 1e7 rays, L = 5"}
+    for path, counter, key in ((fetch_csv, "FETCH_SIZE", "fetch"), (write_csv, "WRITE_SIZE", "write")):
+        with open(path) as f:
+            rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+        fwd = [float(r["Counter_Value"]) for r in rows if "k_forward<false, 0" in r["Kernel_Name"]]
+        copies = sorted((int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows
+                        if "copyBuffer" in r["Kernel_Name"])[-3:]
+        if not fwd or len(copies) < 3:
+            raise SystemExit("%s: no forward dispatches or calibration copies" % path)
+        copy_kib = sum(v for _, v in copies) / 3
+        factor = CALIB_COPY_BYTES / 1024.0 / copy_kib
+        kib = sum(fwd) / len(fwd)
+        out[key + "_kib_raw"] = round(kib, 3)
+        out[key + "_copy_kib_raw"] = round(copy_kib, 3)
+        out[key + "_factor"] = round(factor, 4)
+        out[key + "_bytes_per_launch"] = int(round(kib * 1024 * factor))
+        out[key + "_dispatches"] = len(fwd)
+    out["calibration_factor"] = {"fetch": out["fetch_factor"], "write": out["write_factor"]}
+    with open(PROFILE_COUNTERS, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
 
 
 def main():
     args = parse()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the map would be "
               "all-reduced over RCCL after tracing disjoint ray ranges).", file=sys.stderr)
@@ -120,13 +161,13 @@ def main():
         for _ in range(args.profile_steps):
             rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out)
         if args.calib_copy:
-            a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+            a = torch.empty(CALIB_COPY_BYTES // 4, dtype=torch.float32, device=dev)
             b = torch.empty_like(a)
             for _ in range(3):
                 b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"profile_steps": args.profile_steps,
-                          "calib_copy_bytes": (64 << 20) * 4 if args.calib_copy else 0}))
+                          "calib_copy_bytes": CALIB_COPY_BYTES if args.calib_copy else 0}))
         return
 
     # device counters of one pass: segments, crossings, node visits, triangle tests

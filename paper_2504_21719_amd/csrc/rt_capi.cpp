@@ -56,7 +56,7 @@ extern "C" rt_status rt_build_scene(const float* vertices, int64_t n_vertices, c
     }
     s->n_tri = n_triangles;
     s->n_mat = n_materials;
-    e = hipMalloc(&s->counters, sizeof(unsigned long long) * 8);
+    e = hipMalloc(&s->counters, sizeof(unsigned long long) * RT_QUEUES * RT_QUEUE_STRIDE);
     if (e != hipSuccess) {
         delete s;
         return rt_hip_fail(e, "hipMalloc(counters)");

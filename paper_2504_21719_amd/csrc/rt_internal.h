@@ -21,6 +21,11 @@
 
 // Empty child slot of a 4-wide node.
 #define RT_WIDE_EMPTY 0x7fffffff
+// Work queues of the persistent kernels: the launch's work indices are split
+// into up to RT_QUEUES contiguous ranges, each with its own counter on its own
+// 256-byte line, so that lane refills do not serialise on one address.
+#define RT_QUEUES 256
+#define RT_QUEUE_STRIDE 32
 
 // LBVH layout.  Internal node = 4 x float4 (64 B, one cache line):
 //   q0 = (L.lo.x, L.hi.x, L.lo.y, L.hi.y)
@@ -52,7 +57,7 @@ struct rt_scene {
     size_t bytes = 0;
     double build_ms = 0.0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    // per-scene workspace: [0] work counter, [1] overflow flag, [2..] spare
+    // per-scene workspace: RT_QUEUES work-queue heads, RT_QUEUE_STRIDE apart
     unsigned long long* counters = nullptr;
     int* spill = nullptr;     // traversal stack spill
     size_t spill_entries = 0; // ints available in `spill`

@@ -1,9 +1,11 @@
 // sbr_forward.hip -- persistent SBR radio-map kernel for gfx950.
 //
 // One lane carries one ray at a time.  A lane whose ray has ended takes the
-// next lattice index from a device work counter (one atomic per wavefront,
+// next lattice index from a device work queue (one atomic per wavefront,
 // shared out with ballot/mbcnt), so wavefronts stay full while ray lengths
-// differ.  Per traced segment l the lane
+// differ.  The work indices are split into contiguous queues with separate
+// counters; a wavefront starts on its own queue and moves on to the next once
+// that is drained, until it has found every queue drained.  Per traced segment l the lane
 //   1. finds the closest hit through the LBVH (short LDS stack, spill to a
 //      per-lane global area sized from the tree depth), or by testing every
 //      triangle when accel = brute force (validation);
@@ -52,7 +54,8 @@ struct FwdArgs {
     int32_t* cells;
     float* weights;
     unsigned long long* stats;
-    unsigned long long* counter;
+    unsigned long long* counter;   // RT_QUEUES heads, RT_QUEUE_STRIDE apart
+    int nq;                        // queues in use (1..RT_QUEUES)
     int* spill;
     int64_t spill_stride;
     int spill_depth;
@@ -148,16 +151,31 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
             float4 rf = w[6];
             int ref[4] = {__float_as_int(rf.x), __float_as_int(rf.y), __float_as_int(rf.z), __float_as_int(rf.w)};
             float key[4];
-            int nint = 0;
+            unsigned leaves = 0;
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 bool hc = h[c] && ref[c] != RT_WIDE_EMPTY;
                 if (hc && ref[c] < 0) {
-                    test(~ref[c]);
+                    leaves |= 1u << c;
                     hc = false;
                 }
                 key[c] = hc ? te[c] : INFINITY;
-                nint += hc ? 1 : 0;
+            }
+            // one triangle-test body for the whole wavefront: it runs as many
+            // times as the lane with the most leaf hits needs
+            while (leaves) {
+                const int c = __builtin_ctz(leaves);
+                leaves &= leaves - 1u;
+                test(~(c == 0 ? ref[0] : c == 1 ? ref[1] : c == 2 ? ref[2] : ref[3]));
+            }
+            // children whose entry lies beyond the closest hit found so far
+            // are dropped (the same outcome as a box test with the new bound)
+            const float lim = t_best * kBoxSlack;
+            int nint = 0;
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                if (key[c] > lim) key[c] = INFINITY;
+                nint += key[c] < INFINITY ? 1 : 0;
             }
             if (nint > 0) {
                 // sort the four (key, ref) pairs by key (misses sort last)
@@ -290,6 +308,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
 
     bool active = false;
     bool exhausted = false;
+    const unsigned long long nw = (unsigned long long)a.n_work;
+    const int nq = a.nq;
+    int q = (int)((gtid >> 6) % nq);   // this wavefront's first queue
+    int drained = 0;                   // queues found drained so far
     int64_t rid = 0;          // ray index relative to ray_begin
     int l = 0;
     int last = -1;
@@ -300,19 +322,35 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     float* mapb = a.map;      // map of the lane's transmitter
 
     while (true) {
-        // ---- refill lanes without a ray from the work counter
+        // ---- refill lanes without a ray from the work queues
         if (!exhausted) {
             unsigned long long need = __ballot(!active);
             if (need && (__popcll(need) >= a.refill || need == ~0ull)) {
                 int leader = __ffsll((long long)need) - 1;
                 unsigned cnt = (unsigned)__popcll(need);
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)cnt);
-                base = shfl_u64(base, leader);
-                if (base + cnt >= (unsigned long long)a.n_work) exhausted = true;
-                if (!active) {
+                unsigned long long base = 0, end = 0;
+                // wave-uniform: every value below is the same on all lanes
+                while (true) {
+                    const unsigned long long qb = (unsigned long long)q * nw / nq;
+                    const unsigned long long qe = (unsigned long long)(q + 1) * nw / nq;
+                    unsigned long long b = 0;
+                    if (lane == leader) b = atomicAdd(a.counter + q * RT_QUEUE_STRIDE, (unsigned long long)cnt);
+                    b = shfl_u64(b, leader);
+                    const bool got = b < qe - qb;
+                    if (got) {
+                        base = qb + b;
+                        end = qe;
+                    }
+                    if (!got || b + cnt >= qe - qb) {
+                        // queue q is drained: move on, stop after all of them
+                        q = q + 1 == nq ? 0 : q + 1;
+                        if (++drained >= nq) exhausted = true;
+                    }
+                    if (got || exhausted) break;
+                }
+                if (!active && end > 0) {
                     unsigned long long my = base + (unsigned long long)__popcll(need & lt);
-                    if (my < (unsigned long long)a.n_work) {
+                    if (my < end) {
                         rid = (int64_t)my;
                         int64_t n;
                         TxDesc td;
@@ -498,11 +536,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     }
 }
 
-// Zero the map (unless accumulating) and reset the work counter.  A kernel,
+// Zero the map (unless accumulating) and reset the work-queue heads (the grid
+// always has at least RT_QUEUES threads).  A kernel,
 // not a memset, so that the whole call can be captured in a HIP graph.
 __global__ void k_prepare(float* __restrict__ map, int64_t n, unsigned long long* __restrict__ counter) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *counter = 0ull;
+    if (i < RT_QUEUES) counter[i * RT_QUEUE_STRIDE] = 0ull;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) map[i] = 0.0f;
 }
 
@@ -557,7 +596,12 @@ static rt_status size_spill(FwdArgs& a, const rt_scene* s, int block, int* block
 }
 
 template <int MODE>
-static void launch_mode(const FwdArgs& a, int accel, bool wide, int blocks, int block, hipStream_t st) {
+static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, int block, hipStream_t st) {
+    FwdArgs a = args;
+    // about 4096 work items per queue, at most RT_QUEUES queues
+    a.nq = (int)std::max<int64_t>(1, std::min<int64_t>(RT_QUEUES, a.n_work / 4096));
+    if (const char* env = getenv("RTMAP_QUEUES"))
+        a.nq = std::max(1, std::min(RT_QUEUES, atoi(env)));
     size_t lds = 2 * sizeof(int) * RT_STACK_LDS * block;   // node ids + entry distances
     if (accel == RT_ACCEL_BRUTE)
         hipLaunchKernelGGL((k_forward<true, MODE, false>), dim3(blocks), dim3(block), lds, st, a);
