@@ -56,6 +56,9 @@ struct FwdArgs {
     unsigned long long* stats;
     unsigned long long* counter;   // RT_QUEUES heads, RT_QUEUE_STRIDE apart
     int nq;                        // queues in use (1..RT_QUEUES)
+    int qrem;                      // queues q < qrem hold qper + 1 work indices, the others qper
+    unsigned long long qper;
+    int claim;                     // work indices claimed per queue atomic (>= 64)
     int* spill;
     int64_t spill_stride;
     int spill_depth;
@@ -90,6 +93,13 @@ __device__ __forceinline__ int find_tx(const int64_t* __restrict__ prefix, int n
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Value of lane 0 (the caller runs with every lane active), in scalar registers.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+    unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(v & 0xffffffffu));
+    unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
 
 __device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src) {
     unsigned lo = __shfl((unsigned)(v & 0xffffffffu), src);
@@ -308,10 +318,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
 
     bool active = false;
     bool exhausted = false;
-    const unsigned long long nw = (unsigned long long)a.n_work;
-    const int nq = a.nq;
-    int q = (int)((gtid >> 6) % nq);   // this wavefront's first queue
+    // this wavefront's first queue (held in scalar registers)
+    int q = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % a.nq));
     int drained = 0;                   // queues found drained so far
+    const unsigned long long claim = (unsigned long long)a.claim;   // work indices per atomic
+    unsigned long long res_b = 0, res_e = 0;                         // claimed, not yet started
     int64_t rid = 0;          // ray index relative to ray_begin
     int l = 0;
     int last = -1;
@@ -322,35 +333,47 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     float* mapb = a.map;      // map of the lane's transmitter
 
     while (true) {
-        // ---- refill lanes without a ray from the work queues
-        if (!exhausted) {
+        // ---- refill lanes without a ray: from this wavefront's reservoir of
+        // claimed work indices, claiming a new batch from the queues when the
+        // reservoir cannot cover every idle lane
+        if (!exhausted || res_b < res_e) {
             unsigned long long need = __ballot(!active);
             if (need && (__popcll(need) >= a.refill || need == ~0ull)) {
-                int leader = __ffsll((long long)need) - 1;
-                unsigned cnt = (unsigned)__popcll(need);
-                unsigned long long base = 0, end = 0;
+                const unsigned cnt = (unsigned)__popcll(need);
                 // wave-uniform: every value below is the same on all lanes
-                while (true) {
-                    const unsigned long long qb = (unsigned long long)q * nw / nq;
-                    const unsigned long long qe = (unsigned long long)(q + 1) * nw / nq;
-                    unsigned long long b = 0;
-                    if (lane == leader) b = atomicAdd(a.counter + q * RT_QUEUE_STRIDE, (unsigned long long)cnt);
-                    b = shfl_u64(b, leader);
-                    const bool got = b < qe - qb;
-                    if (got) {
-                        base = qb + b;
-                        end = qe;
+                unsigned long long b1 = res_b, e1 = res_e, b2 = 0, e2 = 0;
+                if (e1 - b1 < cnt && !exhausted) {
+                    while (true) {
+                        // queue q holds work indices [qb, qe): per or per + 1 of them
+                        const unsigned long long qb = (unsigned long long)q * a.qper + (unsigned)min(q, a.qrem);
+                        const unsigned long long qn = a.qper + (q < a.qrem ? 1ull : 0ull);
+                        unsigned long long b = 0;
+                        if (lane == 0) b = atomicAdd(a.counter + q * RT_QUEUE_STRIDE, claim);
+                        b = uniform_u64(b);
+                        const bool got = b < qn;
+                        if (got) {
+                            b2 = qb + b;
+                            e2 = qb + min(qn, b + claim);
+                        }
+                        if (!got || b + claim >= qn) {
+                            // queue q is drained: move on, stop after all of them
+                            q = q + 1 == a.nq ? 0 : q + 1;
+                            if (++drained >= a.nq) exhausted = true;
+                        }
+                        if (got || exhausted) break;
                     }
-                    if (!got || b + cnt >= qe - qb) {
-                        // queue q is drained: move on, stop after all of them
-                        q = q + 1 == nq ? 0 : q + 1;
-                        if (++drained >= nq) exhausted = true;
-                    }
-                    if (got || exhausted) break;
                 }
-                if (!active && end > 0) {
-                    unsigned long long my = base + (unsigned long long)__popcll(need & lt);
-                    if (my < end) {
+                // idle lanes take the reservoir first, then the new batch
+                const unsigned long long n1 = e1 - b1;
+                const unsigned long long take1 = min((unsigned long long)cnt, n1);
+                const unsigned long long take2 = min((unsigned long long)cnt - take1, e2 - b2);
+                res_b = take1 < n1 ? b1 + take1 : b2 + take2;
+                res_e = take1 < n1 ? e1 : e2;
+                if (!active) {
+                    const unsigned long long rank = (unsigned long long)__popcll(need & lt);
+                    const bool mine = rank < take1 + take2;
+                    const unsigned long long my = rank < take1 ? b1 + rank : b2 + (rank - take1);
+                    if (mine) {
                         rid = (int64_t)my;
                         int64_t n;
                         TxDesc td;
@@ -602,6 +625,11 @@ static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, i
     a.nq = (int)std::max<int64_t>(1, std::min<int64_t>(RT_QUEUES, a.n_work / 4096));
     if (const char* env = getenv("RTMAP_QUEUES"))
         a.nq = std::max(1, std::min(RT_QUEUES, atoi(env)));
+    a.qper = (unsigned long long)a.n_work / (unsigned long long)a.nq;
+    a.qrem = (int)((unsigned long long)a.n_work % (unsigned long long)a.nq);
+    a.claim = 256;
+    if (const char* env = getenv("RTMAP_CLAIM"))
+        a.claim = std::max(64, std::min(4096, atoi(env)));
     size_t lds = 2 * sizeof(int) * RT_STACK_LDS * block;   // node ids + entry distances
     if (accel == RT_ACCEL_BRUTE)
         hipLaunchKernelGGL((k_forward<true, MODE, false>), dim3(blocks), dim3(block), lds, st, a);
