@@ -56,7 +56,7 @@ extern "C" rt_status rt_build_scene(const float* vertices, int64_t n_vertices, c
     }
     s->n_tri = n_triangles;
     s->n_mat = n_materials;
-    e = hipMalloc(&s->counters, sizeof(unsigned long long) * RT_QUEUES * RT_QUEUE_STRIDE);
+    e = hipMalloc(&s->counters, sizeof(unsigned long long) * (RT_QUEUES + 1) * RT_QUEUE_STRIDE);
     if (e != hipSuccess) {
         delete s;
         return rt_hip_fail(e, "hipMalloc(counters)");
@@ -640,7 +640,7 @@ extern "C" rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_t
     // of the traversal stack is fixed at compile time and spills beyond it
     const int blocks[] = {128, 256, 512};
     const int deps[] = {RT_DEPOSIT_ATOMIC, RT_DEPOSIT_WAVE};
-    const int refills[] = {32, 56};
+    const int refills[] = {32, 48, 56};
     const int orders[] = {1, 2};
     const int widths[] = {4, 2};
     float best = 1e30f;

@@ -23,7 +23,8 @@
 #define RT_WIDE_EMPTY 0x7fffffff
 // Work queues of the persistent kernels: the launch's work indices are split
 // into up to RT_QUEUES contiguous ranges, each with its own counter on its own
-// 256-byte line, so that lane refills do not serialise on one address.
+// 256-byte line, so that lane refills do not serialise on one address.  One
+// more line after them counts the queues drained so far.
 #define RT_QUEUES 256
 #define RT_QUEUE_STRIDE 32
 
@@ -57,7 +58,8 @@ struct rt_scene {
     size_t bytes = 0;
     double build_ms = 0.0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    // per-scene workspace: RT_QUEUES work-queue heads, RT_QUEUE_STRIDE apart
+    // per-scene workspace: RT_QUEUES work-queue heads and the drained-queue
+    // count, RT_QUEUE_STRIDE apart
     unsigned long long* counters = nullptr;
     int* spill = nullptr;     // traversal stack spill
     size_t spill_entries = 0; // ints available in `spill`

@@ -355,11 +355,20 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                             b2 = qb + b;
                             e2 = qb + min(qn, b + claim);
                         }
-                        if (!got || b + claim >= qn) {
-                            // queue q is drained: move on, stop after all of them
-                            q = q + 1 == a.nq ? 0 : q + 1;
-                            if (++drained >= a.nq) exhausted = true;
+                        if (got && b + claim >= qn) {
+                            // this claim drained queue q (exactly one claim per queue does)
+                            if (lane == 0) atomicAdd(a.counter + RT_QUEUES * RT_QUEUE_STRIDE, 1ull);
                         }
+                        if (!got) {
+                            // drained earlier: stop once every queue is, else try the next
+                            unsigned long long nd = 0;
+                            if (lane == 0)
+                                nd = __hip_atomic_load(a.counter + RT_QUEUES * RT_QUEUE_STRIDE, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                            nd = uniform_u64(nd);
+                            if (nd >= (unsigned long long)a.nq || ++drained >= a.nq) exhausted = true;
+                        }
+                        if (!got || b + claim >= qn) q = q + 1 == a.nq ? 0 : q + 1;
                         if (got || exhausted) break;
                     }
                 }
@@ -559,12 +568,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     }
 }
 
-// Zero the map (unless accumulating) and reset the work-queue heads (the grid
-// always has at least RT_QUEUES threads).  A kernel,
+// Zero the map (unless accumulating) and reset the work-queue heads and the
+// drained count (launched with at least two 256-thread blocks, so that the
+// grid has more than RT_QUEUES threads).  A kernel,
 // not a memset, so that the whole call can be captured in a HIP graph.
 __global__ void k_prepare(float* __restrict__ map, int64_t n, unsigned long long* __restrict__ counter) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < RT_QUEUES) counter[i * RT_QUEUE_STRIDE] = 0ull;
+    if (i <= RT_QUEUES) counter[i * RT_QUEUE_STRIDE] = 0ull;
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) map[i] = 0.0f;
 }
 
@@ -606,7 +616,9 @@ static void base_args(FwdArgs& a, const rt_scene* s, int block, const float* eps
 }
 
 static rt_status size_spill(FwdArgs& a, const rt_scene* s, int block, int* blocks_out) {
+    // persistent grid, but no more workgroups than give each lane about four rays
     int blocks = rt_persistent_blocks(block, s->device);
+    blocks = (int)std::min<int64_t>(blocks, std::max<int64_t>(256, (a.n_work + 4LL * block - 1) / (4LL * block)));
     int64_t threads = (int64_t)blocks * block;
     // a wide traversal pushes up to 3 entries per wide level (= 2 binary levels)
     int64_t need_depth = std::max<int64_t>(0, rt_stack_need(s) - RT_STACK_LDS);
@@ -627,7 +639,12 @@ static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, i
         a.nq = std::max(1, std::min(RT_QUEUES, atoi(env)));
     a.qper = (unsigned long long)a.n_work / (unsigned long long)a.nq;
     a.qrem = (int)((unsigned long long)a.n_work % (unsigned long long)a.nq);
-    a.claim = 256;
+    // claims small enough that every wavefront makes about 16 of them (a
+    // wavefront runs its claimed rays one after another, so large claims
+    // lengthen the tail), large enough to keep queue atomics rare; whole
+    // multiples of the wavefront, so that a refill stays on one stretch of the
+    // launch order
+    a.claim = 64 * (int)std::max<int64_t>(1, std::min<int64_t>(4, a.n_work / ((int64_t)blocks * block * 16)));
     if (const char* env = getenv("RTMAP_CLAIM"))
         a.claim = std::max(64, std::min(4096, atoi(env)));
     size_t lds = 2 * sizeof(int) * RT_STACK_LDS * block;   // node ids + entry distances
@@ -678,7 +695,7 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
     int64_t map_n = a.map_stride * a.npol;
     {
         int64_t zn = f.zero_map ? map_n : 0;
-        int g = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (zn + 255) / 256));
+        int g = (int)std::min<int64_t>(2048, std::max<int64_t>(2, (zn + 255) / 256));
         hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, f.map, zn, s->counters);
     }
     if (f.order) rt_order_shifts_single(f.order, f.tx.n_rays, s->shifts, st);
@@ -724,7 +741,7 @@ rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const f
     int blocks = 0;
     rt_status r = size_spill(a, s, block, &blocks);
     if (r != RT_OK) return r;
-    int g = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (zero_floats + 255) / 256));
+    int g = (int)std::min<int64_t>(4096, std::max<int64_t>(2, (zero_floats + 255) / 256));
     hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, maps, zero_floats, s->counters);
     if (order) rt_order_shifts_multi(order, txs, n_tx, max_chunks, s->shifts, st);
     if (total_rays > 0) {
