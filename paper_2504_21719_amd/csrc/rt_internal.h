@@ -49,9 +49,12 @@ struct rt_scene {
     float4* tris = nullptr;
     float4* normals = nullptr;
     // 4-wide BVH collapsed from the binary one: 8 x float4 (128 B) per node,
-    //   w0..w1 = x (lo, hi) of children 0..3, w2..w3 = y, w4..w5 = z,
-    //   w6 = child refs (>= 0 wide node, < 0 leaf slot ~r, RT_WIDE_EMPTY);
-    // node 0 is the root.  Built when n_tri >= 2.
+    //   w0 = x_lo of children 0..3, w1 = x_hi, w2 = y_lo, w3 = y_hi,
+    //   w4 = z_lo, w5 = z_hi, w6 = child refs (>= 0 wide node, < 0 leaf
+    //   slot ~r, RT_WIDE_EMPTY), w7 unused;
+    // node 0 is the root.  Built when n_tri >= 2.  A ray reads, per axis, the
+    // near plane first (lo for a positive direction component, else hi) and
+    // the far one at the byte offset XOR 16.
     float4* wide = nullptr;
     int64_t n_wide = 0;
     int tuned_width = 0;      // 2 binary, 4 wide (0 = default)

@@ -164,6 +164,7 @@ struct Ray {
     float ix, iy, iz;          // guarded reciprocal direction (slab test)
     float sx, sy, sz;          // watertight shear constants
     int kx, ky, kz;            // watertight axis permutation
+    unsigned nx, ny, nz;       // byte offsets of the near planes in a 4-wide node
 };
 
 __device__ __forceinline__ float pick(float a, float b, float c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
@@ -193,6 +194,9 @@ __device__ __forceinline__ void ray_setup(Ray& r) {
     r.ix = safe_inv(r.dx);
     r.iy = safe_inv(r.dy);
     r.iz = safe_inv(r.dz);
+    r.nx = r.ix < 0.0f ? 16u : 0u;
+    r.ny = r.iy < 0.0f ? 48u : 32u;
+    r.nz = r.iz < 0.0f ? 80u : 64u;
 }
 
 // Watertight ray/triangle test.  Returns t (> t_min) or a negative value.
@@ -251,23 +255,32 @@ __device__ __forceinline__ void box2(const Ray& r, float4 q0, float4 q1, float4 
     tR = aR;
 }
 
-// Slab test of the four children of a wide node (same arithmetic as box2).
-__device__ __forceinline__ void box4(const Ray& r, const float4* __restrict__ w, float tmin, float tmax, bool hit[4],
-                                     float tent[4]) {
-    float4 x01 = w[0], x23 = w[1], y01 = w[2], y23 = w[3], z01 = w[4], z23 = w[5];
-    const float xl[4] = {x01.x, x01.z, x23.x, x23.z}, xh[4] = {x01.y, x01.w, x23.y, x23.w};
-    const float yl[4] = {y01.x, y01.z, y23.x, y23.z}, yh[4] = {y01.y, y01.w, y23.y, y23.w};
-    const float zl[4] = {z01.x, z01.z, z23.x, z23.z}, zh[4] = {z01.y, z01.w, z23.y, z23.w};
+// Slab test of the four children of a wide node at byte offset `base` of
+// `wb`.  Per axis the ray reads its near planes (lo for a positive direction
+// component, else hi) and its far planes, so that no min/max per axis is
+// needed: entry = max(near distances, tmin), exit = min(far distances) times
+// the slack.  Also returns the four child references.
+__device__ __forceinline__ void box4(const Ray& r, const char* __restrict__ wb, unsigned base, float tmin,
+                                     float tmax, bool hit[4], float tent[4], int ref[4]) {
+    const unsigned bx = base | r.nx, by = base | r.ny, bz = base | r.nz;
+    const float4 nx = *(const float4*)(wb + bx), fx = *(const float4*)(wb + (bx ^ 16u));
+    const float4 ny = *(const float4*)(wb + by), fy = *(const float4*)(wb + (by ^ 16u));
+    const float4 nz = *(const float4*)(wb + bz), fz = *(const float4*)(wb + (bz ^ 16u));
+    const float4 rf = *(const float4*)(wb + (base | 96u));
+    const float nxa[4] = {nx.x, nx.y, nx.z, nx.w}, fxa[4] = {fx.x, fx.y, fx.z, fx.w};
+    const float nya[4] = {ny.x, ny.y, ny.z, ny.w}, fya[4] = {fy.x, fy.y, fy.z, fy.w};
+    const float nza[4] = {nz.x, nz.y, nz.z, nz.w}, fza[4] = {fz.x, fz.y, fz.z, fz.w};
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-        float tx0 = (xl[c] - r.ox) * r.ix, tx1 = (xh[c] - r.ox) * r.ix;
-        float ty0 = (yl[c] - r.oy) * r.iy, ty1 = (yh[c] - r.oy) * r.iy;
-        float tz0 = (zl[c] - r.oz) * r.iz, tz1 = (zh[c] - r.oz) * r.iz;
-        float a = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
-        float b = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * kBoxSlack;
+        float a = fmaxf(fmaxf((nxa[c] - r.ox) * r.ix, (nya[c] - r.oy) * r.iy), fmaxf((nza[c] - r.oz) * r.iz, tmin));
+        float b = fminf(fminf((fxa[c] - r.ox) * r.ix, (fya[c] - r.oy) * r.iy), (fza[c] - r.oz) * r.iz) * kBoxSlack;
         hit[c] = a <= fminf(b, tmax);
         tent[c] = a;
     }
+    ref[0] = __float_as_int(rf.x);
+    ref[1] = __float_as_int(rf.y);
+    ref[2] = __float_as_int(rf.z);
+    ref[3] = __float_as_int(rf.w);
 }
 
 // ------------------------------------------------------------ Fresnel

@@ -154,12 +154,10 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
         int node = 0;
         for (int guard = 0; guard < a.n_tri; guard++) {
             n_nodes++;
-            const float4* w = a.wide + 8 * (int64_t)node;
             bool h[4];
             float te[4];
-            box4(r, w, tmin, t_best * kBoxSlack, h, te);
-            float4 rf = w[6];
-            int ref[4] = {__float_as_int(rf.x), __float_as_int(rf.y), __float_as_int(rf.z), __float_as_int(rf.w)};
+            int ref[4];
+            box4(r, (const char*)a.wide, (unsigned)node << 7, tmin, t_best * kBoxSlack, h, te, ref);
             float key[4];
             unsigned leaves = 0;
 #pragma unroll

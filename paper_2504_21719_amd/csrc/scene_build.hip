@@ -382,12 +382,10 @@ __global__ void k_wide_emit(const int4* __restrict__ child, const float4* __rest
         }
     }
     float4* w = wide + 8 * (int64_t)index4[i];
-    w[0] = make_float4(lo[0][0], hi[0][0], lo[1][0], hi[1][0]);
-    w[1] = make_float4(lo[2][0], hi[2][0], lo[3][0], hi[3][0]);
-    w[2] = make_float4(lo[0][1], hi[0][1], lo[1][1], hi[1][1]);
-    w[3] = make_float4(lo[2][1], hi[2][1], lo[3][1], hi[3][1]);
-    w[4] = make_float4(lo[0][2], hi[0][2], lo[1][2], hi[1][2]);
-    w[5] = make_float4(lo[2][2], hi[2][2], lo[3][2], hi[3][2]);
+    for (int a = 0; a < 3; a++) {
+        w[2 * a] = make_float4(lo[0][a], lo[1][a], lo[2][a], lo[3][a]);
+        w[2 * a + 1] = make_float4(hi[0][a], hi[1][a], hi[2][a], hi[3][a]);
+    }
     w[6] = make_float4(__int_as_float(out[0]), __int_as_float(out[1]), __int_as_float(out[2]),
                        __int_as_float(out[3]));
     w[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -719,12 +717,16 @@ rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t*
         HIPCHK(hipMemcpyAsync(&last_index, index4 + n_int - 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         int64_t n4 = (int64_t)last_index + last_flag;
-        HIPCHK(hipMalloc(&s->wide, sizeof(float4) * 8 * n4));
-        s->bytes += sizeof(float4) * 8 * n4;
-        hipLaunchKernelGGL(k_wide_emit, dim3(grid_for(n_int, kBlock)), dim3(kBlock), 0, st, child, s->nodes,
-                           s->tris, is_root, index4, n_int, s->wide);
-        HIPCHK(hipGetLastError());
-        s->n_wide = n4;
+        // the traversal addresses wide nodes with 32-bit byte offsets; larger
+        // trees are traversed as binary trees
+        if (n4 < ((int64_t)1 << 25)) {
+            HIPCHK(hipMalloc(&s->wide, sizeof(float4) * 8 * n4));
+            s->bytes += sizeof(float4) * 8 * n4;
+            hipLaunchKernelGGL(k_wide_emit, dim3(grid_for(n_int, kBlock)), dim3(kBlock), 0, st, child, s->nodes,
+                               s->tris, is_root, index4, n_int, s->wide);
+            HIPCHK(hipGetLastError());
+            s->n_wide = n4;
+        }
     }
     HIPCHK(hipEventRecord(e1, st));
     HIPCHK(hipEventSynchronize(e1));
