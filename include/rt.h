@@ -188,8 +188,10 @@ typedef struct {
  *   cells    int32: plane cell crossed by segment l (j*W + i), or -1
  *   weights  float: weight deposited by segment l (polarisation 0), or 0
  *   stats    uint64[5], accumulated (not reset): traced segments, plane
- *            crossings, BVH node visits, ray-triangle tests, traversal stack
- *            overflows (always 0: the spill area is sized from the tree depth)
+ *            crossings, BVH node visits, ray-triangle tests, traversal
+ *            faults: stack overflows or references outside the tree, each of
+ *            which ends that query (always 0: the spill area is sized from
+ *            the tree depth, and a well-formed tree has no bad references)
  */
 typedef struct {
     int32_t* hits;

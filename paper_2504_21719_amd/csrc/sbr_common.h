@@ -255,18 +255,30 @@ __device__ __forceinline__ void box2(const Ray& r, float4 q0, float4 q1, float4 
     tR = aR;
 }
 
-// Slab test of the four children of a wide node at byte offset `base` of
-// `wb`.  Per axis the ray reads its near planes (lo for a positive direction
+// Buffer resource over the 4-wide node array: loads are range-checked by
+// the hardware against `bytes` (an offset outside reads zeros), so a bad node
+// reference can never read outside the array.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wide_rsrc(const float4* wide, int n_wide) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)wide, (short)0, n_wide * 128, 0x00020000);
+}
+
+__device__ __forceinline__ float4 ld16(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
+}
+
+// Slab test of the four children of the wide node at byte offset `base`.
+// Per axis the ray reads its near planes (lo for a positive direction
 // component, else hi) and its far planes, so that no min/max per axis is
 // needed: entry = max(near distances, tmin), exit = min(far distances) times
 // the slack.  Also returns the four child references.
-__device__ __forceinline__ void box4(const Ray& r, const char* __restrict__ wb, unsigned base, float tmin,
-                                     float tmax, bool hit[4], float tent[4], int ref[4]) {
+__device__ __forceinline__ void box4(const Ray& r, __amdgpu_buffer_rsrc_t rs, unsigned base, float tmin, float tmax,
+                                     bool hit[4], float tent[4], int ref[4]) {
     const unsigned bx = base | r.nx, by = base | r.ny, bz = base | r.nz;
-    const float4 nx = *(const float4*)(wb + bx), fx = *(const float4*)(wb + (bx ^ 16u));
-    const float4 ny = *(const float4*)(wb + by), fy = *(const float4*)(wb + (by ^ 16u));
-    const float4 nz = *(const float4*)(wb + bz), fz = *(const float4*)(wb + (bz ^ 16u));
-    const float4 rf = *(const float4*)(wb + (base | 96u));
+    const float4 nx = ld16(rs, bx), fx = ld16(rs, bx ^ 16u);
+    const float4 ny = ld16(rs, by), fy = ld16(rs, by ^ 16u);
+    const float4 nz = ld16(rs, bz), fz = ld16(rs, bz ^ 16u);
+    const float4 rf = ld16(rs, base | 96u);
     const float nxa[4] = {nx.x, nx.y, nx.z, nx.w}, fxa[4] = {fx.x, fx.y, fx.z, fx.w};
     const float nya[4] = {ny.x, ny.y, ny.z, ny.w}, fya[4] = {fy.x, fy.y, fy.z, fy.w};
     const float nza[4] = {nz.x, nz.y, nz.z, nz.w}, fza[4] = {fz.x, fz.y, fz.z, fz.w};

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cstring>
 
 #include "sbr_common.h"
@@ -35,6 +36,7 @@ struct FwdArgs {
     const float4* normals;
     int root;
     int n_tri;
+    int n_wide;              // 4-wide nodes (0 when the tree is binary only)
     const float* eps_r;
     const float* sigma;
     TxDesc tx;
@@ -112,12 +114,55 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Per-lane traversal stack: the first RT_STACK_LDS entries {node, entry
+// distance} live in LDS, laid out [entry][lane] (8 bytes each, so a
+// wavefront's pushes are contiguous); deeper entries (node only) go to a
+// per-lane global spill area.  `top` is the LDS slot of entry sp while
+// sp <= RT_STACK_LDS.
+struct TravStack {
+    int2* top;
+    int stride;   // lanes per workgroup
+    int sp;
+};
+
+__device__ __forceinline__ void push_entry(const FwdArgs& a, TravStack& st, int64_t gtid, int ref, float key,
+                                           unsigned& overflow) {
+    if (st.sp < RT_STACK_LDS) {
+        *st.top = make_int2(ref, __float_as_int(key));
+        st.top += st.stride;
+    } else if (st.sp - RT_STACK_LDS < a.spill_depth) {
+        a.spill[(st.sp - RT_STACK_LDS) * a.spill_stride + gtid] = ref;
+    } else {
+        overflow++;   // cannot happen: the spill area is sized from the tree depth
+        return;
+    }
+    st.sp++;
+}
+
+// Pop until an entry whose box may still hold a hit closer than `lim`.
+__device__ __forceinline__ bool pop_entry(const FwdArgs& a, TravStack& st, int64_t gtid, float lim, int& node) {
+    while (st.sp > 0) {
+        st.sp--;
+        if (st.sp < RT_STACK_LDS) {
+            st.top -= st.stride;
+            const int2 e = *st.top;
+            if (__int_as_float(e.y) <= lim) {
+                node = e.x;
+                return true;
+            }
+        } else {
+            node = a.spill[(st.sp - RT_STACK_LDS) * a.spill_stride + gtid];
+            return true;
+        }
+    }
+    return false;
+}
+
 // Closest hit of ray r among all triangles but `last` (a slot).  Ties in t go
 // to the smallest original triangle id.  Returns the slot or -1.
 template <bool BRUTE, bool WIDE>
 __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int last, float& t_best, int& id_best,
-                                           int* __restrict__ lstack, float* __restrict__ tstack, int lstride,
-                                           int64_t gtid,
+                                           int2* __restrict__ stk, int lstride, int64_t gtid,
                                            unsigned& n_nodes, unsigned& n_tris, unsigned& overflow) {
     t_best = INFINITY;
     id_best = 0x7fffffff;
@@ -146,28 +191,26 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
         test(~a.root);
         return slot_best;
     }
+    TravStack st{stk, lstride, 0};
     if (WIDE) {
-        // 4-wide traversal: four slab tests per node fetch; leaf children are
-        // tested at once, internal hits are sorted by entry distance, the
-        // nearest is descended and the others are pushed farthest first
-        int sp = 0;
+        // 4-wide traversal: four slab tests per node fetch (empty child slots
+        // hold inverted boxes and never hit); leaf children are tested at once,
+        // internal hits are sorted by entry distance, the nearest is descended
+        // and the others are pushed farthest first
         int node = 0;
+        const __amdgpu_buffer_rsrc_t rs = wide_rsrc(a.wide, a.n_wide);
         for (int guard = 0; guard < a.n_tri; guard++) {
             n_nodes++;
             bool h[4];
             float te[4];
             int ref[4];
-            box4(r, (const char*)a.wide, (unsigned)node << 7, tmin, t_best * kBoxSlack, h, te, ref);
+            box4(r, rs, (unsigned)node << 7, tmin, t_best * kBoxSlack, h, te, ref);
             float key[4];
             unsigned leaves = 0;
 #pragma unroll
             for (int c = 0; c < 4; c++) {
-                bool hc = h[c] && ref[c] != RT_WIDE_EMPTY;
-                if (hc && ref[c] < 0) {
-                    leaves |= 1u << c;
-                    hc = false;
-                }
-                key[c] = hc ? te[c] : INFINITY;
+                key[c] = (h[c] && ref[c] >= 0) ? te[c] : INFINITY;
+                leaves |= (h[c] && ref[c] < 0) ? 1u << c : 0u;
             }
             // one triangle-test body for the whole wavefront: it runs as many
             // times as the lane with the most leaf hits needs
@@ -176,17 +219,7 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
                 leaves &= leaves - 1u;
                 test(~(c == 0 ? ref[0] : c == 1 ? ref[1] : c == 2 ? ref[2] : ref[3]));
             }
-            // children whose entry lies beyond the closest hit found so far
-            // are dropped (the same outcome as a box test with the new bound)
-            const float lim = t_best * kBoxSlack;
-            int nint = 0;
-#pragma unroll
-            for (int c = 0; c < 4; c++) {
-                if (key[c] > lim) key[c] = INFINITY;
-                nint += key[c] < INFINITY ? 1 : 0;
-            }
-            if (nint > 0) {
-                // sort the four (key, ref) pairs by key (misses sort last)
+            // sort the four (key, ref) pairs by key (misses sort last)
 #define RT_CSWAP(i, j)                                  \
     if (key[j] < key[i]) {                              \
         float tk = key[i];                              \
@@ -196,50 +229,32 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
         ref[i] = ref[j];                                \
         ref[j] = tr;                                    \
     }
-                RT_CSWAP(0, 1) RT_CSWAP(2, 3) RT_CSWAP(0, 2) RT_CSWAP(1, 3) RT_CSWAP(1, 2)
+            RT_CSWAP(0, 1) RT_CSWAP(2, 3) RT_CSWAP(0, 2) RT_CSWAP(1, 3) RT_CSWAP(1, 2)
 #undef RT_CSWAP
+            // children entered beyond the closest hit so far are dropped (the
+            // same outcome as a box test with the new bound); the limit stays
+            // finite so that the INFINITY keys of missed, leaf and empty slots
+            // never pass it, also before the first hit
+            const float lim = fminf(t_best * kBoxSlack, FLT_MAX);
+            if (key[0] <= lim) {
 #pragma unroll
-                for (int c = 3; c >= 1; c--) {
-                    if (c < nint) {
-                        if (sp < RT_STACK_LDS) {
-                            lstack[sp * lstride] = ref[c];
-                            tstack[sp * lstride] = key[c];
-                            sp++;
-                        } else if (sp - RT_STACK_LDS < a.spill_depth) {
-                            a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid] = ref[c];
-                            sp++;
-                        } else {
-                            overflow++;
-                        }
-                    }
-                }
+                for (int c = 3; c >= 1; c--)
+                    if (key[c] <= lim) push_entry(a, st, gtid, ref[c], key[c], overflow);
                 node = ref[0];
-            } else {
-                bool found = false;
-                while (sp > 0) {
-                    sp--;
-                    if (sp < RT_STACK_LDS) {
-                        if (tstack[sp * lstride] <= t_best * kBoxSlack) {
-                            node = lstack[sp * lstride];
-                            found = true;
-                            break;
-                        }
-                    } else {
-                        node = a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid];
-                        found = true;
-                        break;
-                    }
-                }
-                if (!found) break;
+            } else if (!pop_entry(a, st, gtid, lim, node)) {
+                break;
             }
         }
         return slot_best;
     }
-    int sp = 0;
     int node = a.root;
     // every internal node is visited at most once per query; the bound only
     // guards against a malformed tree
     for (int guard = 0; guard < a.n_tri; guard++) {
+        if ((unsigned)node >= (unsigned)(a.n_tri - 1)) {
+            overflow++;
+            break;
+        }
         n_nodes++;
         const float4* q = a.nodes + 4 * (int64_t)node;
         float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
@@ -256,44 +271,17 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
             hR = false;
         }
         if (hL && hR) {
-            int nearc = tL <= tR ? cl : cr;
-            int farc = tL <= tR ? cr : cl;
-            float tfar = tL <= tR ? tR : tL;
             // the far child's entry distance goes with it, so that it can be
             // dropped at pop time without fetching its node
-            if (sp < RT_STACK_LDS) {
-                lstack[sp * lstride] = farc;
-                tstack[sp * lstride] = tfar;
-                sp++;
-            } else if (sp - RT_STACK_LDS < a.spill_depth) {
-                a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid] = farc;
-                sp++;
-            } else {
-                overflow++;   // cannot happen when the spill is sized from the tree depth
-            }
-            node = nearc;
+            const bool lnear = tL <= tR;
+            push_entry(a, st, gtid, lnear ? cr : cl, lnear ? tR : tL, overflow);
+            node = lnear ? cl : cr;
         } else if (hL) {
             node = cl;
         } else if (hR) {
             node = cr;
-        } else {
-            // pop until a node whose box may still hold a closer hit
-            bool found = false;
-            while (sp > 0) {
-                sp--;
-                if (sp < RT_STACK_LDS) {
-                    if (tstack[sp * lstride] <= t_best * kBoxSlack) {
-                        node = lstack[sp * lstride];
-                        found = true;
-                        break;
-                    }
-                } else {
-                    node = a.spill[(sp - RT_STACK_LDS) * a.spill_stride + gtid];
-                    found = true;
-                    break;
-                }
-            }
-            if (!found) break;
+        } else if (!pop_entry(a, st, gtid, t_best * kBoxSlack, node)) {
+            break;
         }
     }
     return slot_best;
@@ -301,10 +289,9 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
 
 template <bool BRUTE, int MODE, bool WIDE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_forward(const FwdArgs a) {
-    extern __shared__ int s_stack[];
+    extern __shared__ int2 s_stack[];
     const int lstride = blockDim.x;
-    int* lstack = s_stack + threadIdx.x;
-    float* tstack = (float*)(s_stack + RT_STACK_LDS * blockDim.x) + threadIdx.x;
+    int2* stk = s_stack + threadIdx.x;
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
     const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -451,7 +438,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
             r.dz = k.z;
             ray_setup(r);
             int idb;
-            slot = closest_hit<BRUTE, WIDE>(a, r, last, t_hit, idb, lstack, tstack, lstride, gtid, st_nodes,
+            slot = closest_hit<BRUTE, WIDE>(a, r, last, t_hit, idb, stk, lstride, gtid, st_nodes,
                                             st_tris, st_over);
             hit_id = slot >= 0 ? idb : -1;
             st_seg++;
@@ -597,6 +584,7 @@ static void base_args(FwdArgs& a, const rt_scene* s, int block, const float* eps
     memset(&a, 0, sizeof(a));
     a.nodes = s->nodes;
     a.wide = s->wide;
+    a.n_wide = (int)s->n_wide;
     a.tris = s->tris;
     a.normals = s->normals;
     a.root = s->root;
@@ -645,7 +633,7 @@ static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, i
     a.claim = 64 * (int)std::max<int64_t>(1, std::min<int64_t>(4, a.n_work / ((int64_t)blocks * block * 16)));
     if (const char* env = getenv("RTMAP_CLAIM"))
         a.claim = std::max(64, std::min(4096, atoi(env)));
-    size_t lds = 2 * sizeof(int) * RT_STACK_LDS * block;   // node ids + entry distances
+    size_t lds = sizeof(int2) * RT_STACK_LDS * block;   // {node, entry distance} per entry
     if (accel == RT_ACCEL_BRUTE)
         hipLaunchKernelGGL((k_forward<true, MODE, false>), dim3(blocks), dim3(block), lds, st, a);
     else if (wide)

@@ -361,9 +361,10 @@ __global__ void k_wide_emit(const int4* __restrict__ child, const float4* __rest
     int out[4];
     for (int j = 0; j < 4; j++) {
         if (j >= cnt) {
+            // inverted box: no ray ever enters it
             for (int a = 0; a < 3; a++) {
-                lo[j][a] = 0.0f;
-                hi[j][a] = 0.0f;
+                lo[j][a] = INFINITY;
+                hi[j][a] = -INFINITY;
             }
             out[j] = RT_WIDE_EMPTY;
         } else if (refs[j] < 0) {

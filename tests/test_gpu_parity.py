@@ -81,6 +81,7 @@ def test_tree_widths_match_brute_force(scene_kind):
         ref = None
         for accel in accels:
             g = gpu_radio_map(cfg, scene_handle=s, ray_begin=b, ray_end=e, accel=accel)
+            assert int(g.stats[4]) == 0, (accel, b)
             if ref is None:
                 ref = g
             else:
@@ -186,6 +187,7 @@ def test_manhattan_full_size_sampled():
     np.testing.assert_allclose(g.map[0][big], acc[big], rtol=1e-4)
     np.testing.assert_allclose(bench.map[0][big], acc[big], rtol=1e-4)
     assert int(g.stats[0]) == int((g.hits != -2).sum())
+    assert int(g.stats[4]) == 0          # no stack overflow, no reference outside the tree
     ids = np.arange(7, N, N // 1500, dtype=np.int64)
     o = oracle.radio_map(cfg.scene, cfg.tx, cfg.plane, cfg.params, ray_ids=ids, want_records=True)
     rep, bad = compare_hits(g.hits[ids], o.hits, o.flags, ids.size, max_frac=1.0)
