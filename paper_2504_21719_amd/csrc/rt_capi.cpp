@@ -266,8 +266,8 @@ static int pick_block(const rt_scene* s, const rt_sbr_params* p) {
 }
 
 // Untuned defaults (from a sweep on the Manhattan workload): same-cell
-// summation across the wavefront, refill once 48 lanes are idle, coherent
-// launch order, 4-wide tree.
+// summation across the wavefront, refill once the whole wavefront is idle,
+// coherent launch order, 4-wide tree.
 static int pick_deposit(const rt_scene* s, const rt_sbr_params* p) {
     if (p->deposit) return p->deposit;
     if (s->tuned_deposit) return s->tuned_deposit;
@@ -275,7 +275,7 @@ static int pick_deposit(const rt_scene* s, const rt_sbr_params* p) {
 }
 
 static int pick_refill(const rt_scene* s) {
-    int r = s->tuned_refill ? s->tuned_refill : 48;
+    int r = s->tuned_refill ? s->tuned_refill : 64;
     if (const char* env = getenv("RTMAP_REFILL")) r = atoi(env);
     return std::max(1, std::min(64, r));
 }
@@ -640,7 +640,7 @@ extern "C" rt_status rt_tune(rt_scene* scene, rt_materials materials, const rt_t
     // of the traversal stack is fixed at compile time and spills beyond it
     const int blocks[] = {128, 256, 512};
     const int deps[] = {RT_DEPOSIT_ATOMIC, RT_DEPOSIT_WAVE};
-    const int refills[] = {32, 48, 56};
+    const int refills[] = {48, 56, 64};
     const int orders[] = {1, 2};
     const int widths[] = {4, 2};
     float best = 1e30f;

@@ -28,25 +28,27 @@ __device__ __forceinline__ cf cmulc(cf a, cf b) {
     return cf{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 // a / b: multiply by conj(b) / |b|^2.  Magnitudes in this library stay far
-// inside the FP32 range (|eta| <= ~1e8), so no rescaling is needed.
+// inside the FP32 range (|eta| <= ~1e8), so no rescaling is needed.  The
+// reciprocal is the hardware one (about 1 ulp).
 __device__ __forceinline__ cf cdiv(cf a, cf b) {
-    float inv = 1.0f / cabs2(b);
+    float inv = __builtin_amdgcn_rcpf(cabs2(b));
     return cf{(a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv};
 }
 // Principal square root (Re >= 0).  With m = |z|:
 //   Re >= 0 branch:  t = sqrt((m + x)/2),  sqrt(z) = t + j y/(2t)
 //   x < 0:           t = sqrt((m - x)/2),  sqrt(z) = |y|/(2t) + j sign(y) t
-// choosing the branch that avoids cancellation in m +- x.
+// choosing the branch that avoids cancellation in m +- x.  Hardware square
+// root and reciprocal (about 1 ulp each).
 __device__ __forceinline__ cf csqrt_principal(cf z) {
     float x = z.re, y = z.im;
-    float m = sqrtf(x * x + y * y);
+    float m = __builtin_amdgcn_sqrtf(x * x + y * y);
     if (m == 0.0f) return cf{0.0f, 0.0f};
     if (x >= 0.0f) {
-        float t = sqrtf(0.5f * (m + x));
-        return cf{t, y / (2.0f * t)};
+        float t = __builtin_amdgcn_sqrtf(0.5f * (m + x));
+        return cf{t, y * __builtin_amdgcn_rcpf(2.0f * t)};
     }
-    float t = sqrtf(0.5f * (m - x));
-    return cf{fabsf(y) / (2.0f * t), copysignf(t, y)};
+    float t = __builtin_amdgcn_sqrtf(0.5f * (m - x));
+    return cf{fabsf(y) * __builtin_amdgcn_rcpf(2.0f * t), copysignf(t, y)};
 }
 
 __device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
@@ -57,7 +59,7 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a
 __device__ __forceinline__ float3 cross3(float3 a, float3 b) {
     return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
-__device__ __forceinline__ float3 unit3(float3 a) { return a * (1.0f / sqrtf(dot3(a, a))); }
+__device__ __forceinline__ float3 unit3(float3 a) { return a * __builtin_amdgcn_rsqf(dot3(a, a)); }
 
 // 2x2 complex matrix, row-major: [a b; c d]
 struct cm2 {

@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 if (cell >= 0) {
                     float g = G[cell];
                     if (g != 0.0f) {
-                        float al = g * a.tx.kappa / fabsf(s0.z);
+                        float al = g * a.tx.kappa * __builtin_amdgcn_rcpf(fabsf(s0.z));
                         // E_l = T_l C
                         cf e0 = cadd(cscale(cf{s2.x, s2.y}, ct), cscale(cf{s2.z, s2.w}, cp));
                         cf e1 = cadd(cscale(cf{s3.x, s3.y}, ct), cscale(cf{s3.z, s3.w}, cp));

@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                 const float4* sp = a.geom + (int64_t)l * 2 * T + g;
                 float4 s0 = sp[0], s1 = sp[T];
                 cell[l] = __float_as_int(s1.w);
-                gk[l] = td.kappa / fabsf(s0.z);
+                gk[l] = td.kappa * __builtin_amdgcn_rcpf(fabsf(s0.z));
                 if (l + 1 < ns) {
                     float4 nm = a.normals[__float_as_int(s0.w)];
                     matl[l] = __float_as_int(nm.w);
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(kSampBlock) k_samples_deep(const SampArgs a) {
             const float4* sp = a.geom + (int64_t)l * 2 * T + g;
             float4 s0 = sp[0], s1 = sp[T];
             int cell = __float_as_int(s1.w);
-            if (cell >= 0) unsafeAtomicAdd(map + cell, td.kappa / fabsf(s0.z) * (cabs2(e0) + cabs2(e1)));
+            if (cell >= 0) unsafeAtomicAdd(map + cell, td.kappa * __builtin_amdgcn_rcpf(fabsf(s0.z)) * (cabs2(e0) + cabs2(e1)));
             if (l + 1 < ns) {
                 float4 nm = a.normals[__float_as_int(s0.w)];
                 int m = __float_as_int(nm.w);

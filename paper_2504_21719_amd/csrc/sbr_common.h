@@ -169,9 +169,12 @@ struct Ray {
 
 __device__ __forceinline__ float pick(float a, float b, float c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
 
+// Hardware reciprocal (about 1 ulp): the slab test has a relative slack far
+// above that, and the shear constants below only need to be the same for
+// every triangle a ray is tested against, which keeps the test watertight.
 __device__ __forceinline__ float safe_inv(float d) {
     float a = fabsf(d) < 1e-20f ? copysignf(1e-20f, d) : d;
-    return 1.0f / a;
+    return __builtin_amdgcn_rcpf(a);
 }
 
 __device__ __forceinline__ void ray_setup(Ray& r) {
@@ -188,9 +191,9 @@ __device__ __forceinline__ void ray_setup(Ray& r) {
     r.kx = kx;
     r.ky = ky;
     r.kz = kz;
-    r.sx = pick(r.dx, r.dy, r.dz, kx) / dkz;
-    r.sy = pick(r.dx, r.dy, r.dz, ky) / dkz;
-    r.sz = 1.0f / dkz;
+    r.sz = __builtin_amdgcn_rcpf(dkz);
+    r.sx = pick(r.dx, r.dy, r.dz, kx) * r.sz;
+    r.sy = pick(r.dx, r.dy, r.dz, ky) * r.sz;
     r.ix = safe_inv(r.dx);
     r.iy = safe_inv(r.dy);
     r.iz = safe_inv(r.dz);
@@ -337,7 +340,7 @@ __device__ __forceinline__ float3 te_direction(float3 k, float3 n) {
         e = cross3(k, a);
         l2 = dot3(e, e);
     }
-    return e * (1.0f / sqrtf(l2));
+    return e * __builtin_amdgcn_rsqf(l2);
 }
 
 // Reflection geometry at a hit.  The field of a segment is stored as complex

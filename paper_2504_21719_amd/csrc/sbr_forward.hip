@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
             st_seg++;
             // ---- plane crossing of this segment
             if (k.z != 0.0f) {
-                float tm = (a.pl.z - o.z) / k.z;
+                float tm = (a.pl.z - o.z) * __builtin_amdgcn_rcpf(k.z);
                 if (tm > 0.0f && tm < t_hit) {
                     float x = o.x + tm * k.x, y = o.y + tm * k.y;
                     float fx = (x - a.pl.x0) * a.pl.inv_dx, fy = (y - a.pl.y0) * a.pl.inv_dy;
@@ -455,7 +455,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                     }
                 }
                 if (MODE != MODE_GEOM && cell >= 0) {
-                        float g = kap / fabsf(k.z);
+                        float g = kap * __builtin_amdgcn_rcpf(fabsf(k.z));
                         cf e0 = cadd(cscale(Ta, c0t), cscale(Tb, c0p));
                         cf e1 = cadd(cscale(Tc, c0t), cscale(Td, c0p));
                         w0 = g * (cabs2(e0) + cabs2(e1));
