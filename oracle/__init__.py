@@ -44,7 +44,8 @@ def build(force: bool = True) -> str:
 class _Tx(C.Structure):
     _fields_ = [("pos", C.c_double * 3), ("yaw", C.c_double), ("pitch", C.c_double),
                 ("roll", C.c_double), ("pattern", C.c_int32), ("q", C.c_double),
-                ("pol", C.c_int32)]
+                ("pol", C.c_int32), ("n_ant", C.c_int32), ("ant_pos", C.c_void_p),
+                ("precoding", C.c_void_p)]
 
 
 class _Plane(C.Structure):
@@ -99,6 +100,16 @@ def _tx(tx) -> _Tx:
     t.pos[:] = [float(v) for v in tx.pos]
     t.yaw, t.pitch, t.roll = float(tx.yaw), float(tx.pitch), float(tx.roll)
     t.pattern, t.q, t.pol = int(tx.pattern), float(tx.pattern_q), int(tx.pol)
+    ant = getattr(tx, "array", None)
+    if ant is not None:
+        pos = np.ascontiguousarray(ant.positions, dtype=np.float64).reshape(-1, 3)
+        u = np.asarray(ant.precoding).astype(np.complex128).reshape(-1)
+        if u.shape[0] != pos.shape[0]:
+            raise ValueError("one precoding weight per array element")
+        prec = np.ascontiguousarray(np.stack([u.real, u.imag], axis=1))
+        t.n_ant = pos.shape[0]
+        t.ant_pos, t.precoding = pos.ctypes.data, prec.ctypes.data
+        t._keep = (pos, prec)          # the arrays live as long as the struct
     return t
 
 

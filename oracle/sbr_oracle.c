@@ -24,6 +24,9 @@
  *     eq. reflected_refracted_vectors), TE/TM bases (eq. fresnel_in_vectors,
  *     eq. fresnel_out_vectors), vacuum Fresnel coefficients (eq. fresnel_vac)
  *     with the complex relative permittivity of eq. eta;
+ *   - an optional synthetic transmit array with a precoding vector
+ *     (Sec. "Handling Multiple Transmit Antennas"): the launch field of a ray
+ *     is multiplied by alpha = a_tx^T u_P of its departure direction;
  *   - the Monte-Carlo radio-map estimator eq. radio-map-solver-ci-all-2-
  *     estimator for specular chains only (no diffuse reflection, so n_S = 0 and
  *     the interaction probability is 1), in which the squared ray-tube length
@@ -97,6 +100,7 @@ static cplx cv_dot_real(vec3 e, cvec3 E) { return e.x * E.x + e.y * E.y + e.z * 
 static cvec3 cv_axpy(cvec3 acc, cplx a, vec3 e) {
     acc.x += a * e.x; acc.y += a * e.y; acc.z += a * e.z; return acc;
 }
+static cvec3 cv_scale(cvec3 E, cplx a) { cvec3 r = {a * E.x, a * E.y, a * E.z}; return r; }
 static double cv_norm2(cvec3 E) {
     return creal(E.x * conj(E.x) + E.y * conj(E.y) + E.z * conj(E.z));
 }
@@ -142,6 +146,9 @@ typedef struct {
     int32_t pattern;     /* 0 isotropic, 1 directional (q) */
     double q;
     int32_t pol;         /* 0 V, 1 H, 2 dual (V and H) */
+    int32_t n_ant;       /* synthetic transmit array: number of elements, 0 = none */
+    const double* ant_pos;   /* [n_ant][3] element offsets from pos (m, global frame) */
+    const double* precoding; /* [n_ant][2] complex precoding vector u_P (re, im) */
 } or_tx;
 
 typedef struct {
@@ -176,6 +183,25 @@ typedef struct {
     int64_t tri_tests;    /* out: number of ray-triangle tests */
     int64_t segments;     /* out: number of traced segments */
 } or_out;
+
+/* ------------------------------------------------- synthetic transmit array */
+/* Sec. "Handling Multiple Transmit Antennas": paths start at the array centre;
+ * element i adds the phase of the array response vector
+ * (eq. path-solver-array-response-vector), exp(j 2 pi/lambda k^T d_i), and
+ * the precoded array radiates alpha = a_tx^T u_P times the single-element
+ * field, so a path contributes ||E alpha||^2 to the map. */
+static cplx array_alpha(const or_tx* tx, vec3 k, double lam)
+{
+    if (tx->n_ant <= 0) return 1.0;
+    cplx alpha = 0.0;
+    for (int32_t i = 0; i < tx->n_ant; i++) {
+        const double* d = tx->ant_pos + 3 * (int64_t)i;
+        double phase = 2.0 * OR_PI / lam * (k.x * d[0] + k.y * d[1] + k.z * d[2]);
+        cplx u = tx->precoding[2 * (int64_t)i] + I * tx->precoding[2 * (int64_t)i + 1];
+        alpha += u * cexp(I * phase);
+    }
+    return alpha;
+}
 
 /* ------------------------------------------------------ lattice and launch */
 /* Spherical Fibonacci lattice (Sec. "Sampling Initial Ray Directions"). */
@@ -380,6 +406,7 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
         int64_t n = ray_ids ? ray_ids[r] : ray_begin + r;
         if (n < 0 || n >= N) return 1;
         vec3 k = lattice_dir(n, N);
+        const cplx alpha = array_alpha(tx, k, lam);   /* 1 without an array */
         for (int p = 0; p < npol; p++) {
             dual Ed[3];
             launch_field(k, tx, tx->pol == 1 ? 1 : p, Ed);
@@ -389,6 +416,11 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                 dE[p][2 * n_mat + a].x = Ed[0].d[a];
                 dE[p][2 * n_mat + a].y = Ed[1].d[a];
                 dE[p][2 * n_mat + a].z = Ed[2].d[a];
+            }
+            /* the element offsets are global, so alpha depends on no parameter */
+            if (tx->n_ant > 0) {
+                E[p] = cv_scale(E[p], alpha);
+                for (int q = 0; q < P; q++) dE[p][q] = cv_scale(dE[p][q], alpha);
             }
         }
         vec3 o = mk(tx->pos[0], tx->pos[1], tx->pos[2]);

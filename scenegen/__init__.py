@@ -63,6 +63,35 @@ class Scene:
 
 
 @dataclasses.dataclass
+class TxArray:
+    """Synthetic transmit array: element offsets from the transmitter position
+    (metres, global frame) and one complex precoding weight per element.  The
+    weights are stored in float32 (the precision the library takes)."""
+    positions: np.ndarray         # [n][3] float64
+    precoding: np.ndarray         # [n] complex64
+
+
+def linear_array(n: int, spacing: float, axis=(1.0, 0.0, 0.0), precoding=None) -> TxArray:
+    """n elements spaced `spacing` metres along `axis`, centred on the
+    transmitter; equal weights 1/sqrt(n) unless `precoding` is given."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    off = (np.arange(n, dtype=np.float64) - 0.5 * (n - 1)) * spacing
+    u = np.full(n, 1.0 / math.sqrt(n), dtype=np.complex64) if precoding is None else np.asarray(precoding)
+    return TxArray(off[:, None] * a[None, :], u.astype(np.complex64))
+
+
+def random_array(n: int, extent: float, seed: int) -> TxArray:
+    """n elements at seeded random offsets in a cube of side `extent` metres,
+    with seeded random complex weights of unit total power."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(-0.5 * extent, 0.5 * extent, size=(n, 3))
+    u = rng.normal(size=n) + 1j * rng.normal(size=n)
+    u = u / np.linalg.norm(u)
+    return TxArray(pos, u.astype(np.complex64))
+
+
+@dataclasses.dataclass
 class Tx:
     pos: tuple                    # metres
     yaw: float = 0.0              # radians
@@ -71,6 +100,7 @@ class Tx:
     pattern: int = PATTERN_ISO
     pattern_q: float = 2.0
     pol: int = POL_V
+    array: Optional[TxArray] = None
 
 
 @dataclasses.dataclass

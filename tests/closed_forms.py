@@ -132,3 +132,27 @@ def fibonacci_phase_exact(n: int) -> float:
     phi = (Decimal(1) + Decimal(5).sqrt()) / 2
     x = Decimal(n) / phi
     return float(x - int(x))
+
+
+def lattice_directions(ns, N: int) -> np.ndarray:
+    """Unit directions of lattice points `ns` of an N-point spherical
+    Fibonacci lattice (float64; fine for n below about 1e7)."""
+    ns = np.asarray(ns, dtype=np.float64)
+    golden = (1.0 + math.sqrt(5.0)) / 2.0
+    z = 1.0 - 2.0 * ns / (N - 1)
+    phi = 2.0 * math.pi * np.mod(ns * (golden - 1.0), 1.0)
+    s = np.sqrt(np.maximum(0.0, (1.0 - z) * (1.0 + z)))
+    return np.stack([s * np.cos(phi), s * np.sin(phi), z], axis=1)
+
+
+def dirichlet_gain(n: int, spacing_wl: float, c, c0: float) -> np.ndarray:
+    """|alpha|^2 of an n-element uniform linear array, element spacing
+    `spacing_wl` wavelengths, weights exp(-j 2 pi s i c0)/sqrt(n): the
+    Dirichlet kernel sin^2(n pi s (c - c0)) / (n sin^2(pi s (c - c0))), with
+    c the direction cosine along the array axis (limit n where the
+    denominator vanishes)."""
+    x = math.pi * spacing_wl * (np.asarray(c, dtype=np.float64) - c0)
+    den = n * np.sin(x) ** 2
+    num = np.sin(n * x) ** 2
+    small = np.abs(np.sin(x)) < 1e-12
+    return np.where(small, float(n), num / np.where(small, 1.0, den))

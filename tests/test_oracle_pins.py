@@ -416,3 +416,67 @@ def test_degenerate_inputs(oracle_lib):
     bad.tri_material[3] = 7
     with pytest.raises(ValueError):
         oracle_lib.radio_map(bad, sg.Tx((0, 0, 10)), pl, sg.Params(FREQ, 10, 1))
+
+
+# ------------------------------------------------- synthetic transmit array
+def _steered_ula(n, spacing, c0):
+    """Uniform linear array along x, weights steering toward x-cosine c0."""
+    base = sg.linear_array(n, spacing)
+    d = base.positions[:, 0]
+    u = np.exp(-2j * math.pi * d / LAM * c0) / math.sqrt(n)
+    return sg.TxArray(base.positions, u.astype(np.complex64))
+
+
+def test_array_single_element_is_identity(oracle_lib):
+    """One element at the array centre with a unit-modulus weight leaves the
+    map unchanged (alpha = u, |alpha| = 1)."""
+    cfg = sg.tiny_config(n_rays=20_000)
+    base = _run(oracle_lib, cfg.scene, cfg.tx, cfg.plane, 20_000, 3)
+    one = sg.TxArray(np.zeros((1, 3)), np.ones(1, np.complex64))
+    r1 = _run(oracle_lib, cfg.scene, sg.Tx(cfg.tx.pos, array=one), cfg.plane, 20_000, 3)
+    assert np.array_equal(r1.map, base.map)
+    ph = sg.TxArray(np.zeros((1, 3)), np.array([np.exp(0.7j)], np.complex64))
+    r2 = _run(oracle_lib, cfg.scene, sg.Tx(cfg.tx.pos, array=ph), cfg.plane, 20_000, 3)
+    np.testing.assert_allclose(r2.map, base.map, rtol=1e-6)
+
+
+def test_array_ula_dirichlet(oracle_lib):
+    """Empty scene: every crossing's weight is the single-element weight times
+    the Dirichlet kernel of a steered 8-element half-wavelength ULA evaluated
+    at the ray's launch direction (closed form of eq. path-solver-array-
+    response-vector with a steering precoding vector)."""
+    N = 30_000
+    n, c0 = 8, 0.3
+    pl = sg.Plane(1.5, -40.0, -40.0, 1.0, 1.0, 80, 80)
+    tx0 = sg.Tx((0.0, 0.0, 10.0))
+    tx1 = sg.Tx((0.0, 0.0, 10.0), array=_steered_ula(n, 0.5 * LAM, c0))
+    r0 = _run(oracle_lib, sg.empty_scene(), tx0, pl, N, 0, want_records=True)
+    r1 = _run(oracle_lib, sg.empty_scene(), tx1, pl, N, 0, want_records=True)
+    assert np.array_equal(r0.records["ray"], r1.records["ray"])
+    assert r0.records["ray"].size > 5_000
+    k = cf.lattice_directions(r0.records["ray"], N)
+    ref = cf.dirichlet_gain(n, 0.5, k[:, 0], c0)
+    ratio = r1.records["w"] / r0.records["w"]
+    # weights are stored in float32: allow their rounding
+    np.testing.assert_allclose(ratio, ref, rtol=2e-6, atol=2e-6 * n)
+    assert ratio.max() > 0.9 * n and ratio.min() < 1e-2      # main lobe and nulls both sampled
+
+
+def test_array_gain_applies_per_ray_at_every_depth(oracle_lib):
+    """Ground-only scene: alpha depends only on the departure direction, so
+    the direct and the ground-reflected crossing of one ray are scaled alike."""
+    N = 40_000
+    pl = sg.Plane(1.5, -30.0, -30.0, 2.0, 2.0, 30, 30)
+    ant = sg.random_array(6, 0.2, seed=11)
+    r0 = _run(oracle_lib, sg.ground_quad(100.0), sg.Tx((0.0, 0.0, 10.0)), pl, N, 2, want_records=True)
+    r1 = _run(oracle_lib, sg.ground_quad(100.0), sg.Tx((0.0, 0.0, 10.0), array=ant), pl, N, 2,
+              want_records=True)
+    assert np.array_equal(r0.records["ray"], r1.records["ray"])
+    assert np.array_equal(r0.records["depth"], r1.records["depth"])
+    ratio = r1.records["w"] / r0.records["w"]
+    rays = r0.records["ray"]
+    both = [n for n in np.unique(rays) if (rays == n).sum() == 2]
+    assert len(both) > 1_000
+    for n in both[:2000]:
+        a, b = ratio[rays == n]
+        assert abs(a - b) <= 1e-9 * max(a, b, 1e-12)
