@@ -231,6 +231,11 @@ def main():
             result.update(extra_legs(rt, sg, cfg, scene, eps, sig, dev))
         except rt.RtError as e:
             result["extras_error"] = str(e)
+    if not args.no_extras:
+        try:
+            result["array"] = array_leg(rt, sg, cfg, scene, eps, sig, out)
+        except rt.RtError as e:
+            result["array_error"] = str(e)
     if not args.no_large:
         try:
             result["large"] = large_leg(rt, sg, dev, args)
@@ -412,6 +417,31 @@ def extra_legs(rt, sg, cfg, scene, eps, sig, dev, reps=5):
     out["batched_samples_ms"] = round(t_bs, 3)
     out["plain_samples_loop_ms"] = round(t_ps, 3)
     return out
+
+
+def array_leg(rt, sg, cfg, scene, eps, sig, out, sizes=(1, 16, 64, 256, 1024)):
+    """Synthetic transmit arrays (the paper's radio-map timing sweep over the
+    number of transmit antennas): the Manhattan workload with a half-wavelength
+    uniform linear array along x, steered to x-cosine 0.5, for several sizes."""
+    import math
+    import numpy as np
+    lam = 299792458.0 / cfg.params.freq_hz
+    res = {"workload": "manhattan, 1e7 rays, L = 5, ULA along x, half-wavelength spacing, steered to x-cosine 0.5",
+           "ms": {}, "M ray-bounces/s": {}}
+    st = None
+    for n in sizes:
+        base = sg.linear_array(n, 0.5 * lam)
+        u = np.exp(-2j * math.pi * base.positions[:, 0] / lam * 0.5) / math.sqrt(n)
+        tx = sg.Tx(cfg.tx.pos, array=sg.TxArray(base.positions, u.astype(np.complex64)))
+        t = _time(lambda: rt.rt_radio_map(scene, eps, sig, tx, cfg.plane, cfg.params, out), 3, 1)
+        if st is None:
+            import torch
+            stats = torch.zeros(8, dtype=torch.int64, device=out.device)
+            rt.rt_radio_map(scene, eps, sig, tx, cfg.plane, cfg.params, out, stats=stats)
+            st = int(stats[0])
+        res["ms"][str(n)] = round(t, 3)
+        res["M ray-bounces/s"][str(n)] = round(st / (t * 1e-3) / 1e6, 1)
+    return res
 
 
 def _time(fn, reps=10, warm=2):

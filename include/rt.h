@@ -131,6 +131,20 @@ typedef struct {
     int32_t pattern;
     float pattern_q;
     int32_t pol;
+    /* Optional synthetic transmit array with a precoding vector (Sec.
+     * "Handling Multiple Transmit Antennas"): rays start at `pos`; a ray of
+     * departure direction k carries alpha = sum_i u_i exp(j 2 pi/lambda k.d_i)
+     * (the array response vector, eq. path-solver-array-response-vector,
+     * times the precoding vector) and its map weight is scaled by |alpha|^2.
+     *   n_ant      number of elements; 0 = a single element at `pos`
+     *   ant_pos    device float64 [n_ant][3]: element offsets d_i from `pos`
+     *              in metres, global frame (not rotated with the antenna)
+     *   precoding  device float32 [n_ant][2]: u_i as (re, im)
+     * Both arrays are read by the kernels of the call and must stay valid
+     * until it completes.  Not supported by rt_radio_map_batched. */
+    int32_t n_ant;
+    const double* ant_pos;
+    const float* precoding;
 } rt_tx;
 
 /*

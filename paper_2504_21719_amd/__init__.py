@@ -48,7 +48,8 @@ class rt_materials(C.Structure):
 
 class rt_tx(C.Structure):
     _fields_ = [("pos", C.c_double * 3), ("yaw", C.c_double), ("pitch", C.c_double), ("roll", C.c_double),
-                ("pattern", C.c_int32), ("pattern_q", C.c_float), ("pol", C.c_int32)]
+                ("pattern", C.c_int32), ("pattern_q", C.c_float), ("pol", C.c_int32),
+                ("n_ant", C.c_int32), ("ant_pos", C.c_void_p), ("precoding", C.c_void_p)]
 
 
 class rt_plane(C.Structure):
@@ -136,11 +137,34 @@ def _ptr(t):
 
 
 # ----------------------------------------------------------------- structs
+def device_array(arr):
+    """Device copies of a synthetic transmit array (float64 offsets [n][3],
+    float32 (re, im) weights [n][2]), made once and kept on the array object."""
+    dev = getattr(arr, "_rt_device", None)
+    if dev is None:
+        import numpy as np
+        import torch
+        pos = np.ascontiguousarray(arr.positions, dtype=np.float64).reshape(-1, 3)
+        u = np.asarray(arr.precoding).astype(np.complex64).reshape(-1)
+        if u.shape[0] != pos.shape[0]:
+            raise ValueError("one precoding weight per array element")
+        w = np.ascontiguousarray(np.stack([u.real, u.imag], axis=1).astype(np.float32))
+        dev = (torch.from_numpy(pos).cuda(), torch.from_numpy(w).cuda())
+        arr._rt_device = dev
+    return dev
+
+
 def make_tx(tx) -> rt_tx:
     t = rt_tx()
     t.pos[:] = [float(v) for v in tx.pos]
     t.yaw, t.pitch, t.roll = float(tx.yaw), float(tx.pitch), float(tx.roll)
     t.pattern, t.pattern_q, t.pol = int(tx.pattern), float(tx.pattern_q), int(tx.pol)
+    arr = getattr(tx, "array", None)
+    if arr is not None:
+        pos, w = device_array(arr)
+        t.n_ant = int(pos.shape[0])
+        t.ant_pos, t.precoding = pos.data_ptr(), w.data_ptr()
+        t._keep = (pos, w)
     return t
 
 

@@ -156,6 +156,9 @@ static rt_status check_tx(const rt_tx* tx, bool allow_dual) {
     CHECK_ARG(std::isfinite(tx->pattern_q) && tx->pattern_q >= 0.0f, "tx pattern_q must be finite and >= 0");
     CHECK_ARG(tx->pol == RT_POL_V || tx->pol == RT_POL_H || (allow_dual && tx->pol == RT_POL_DUAL),
               allow_dual ? "tx pol must be 0 (V), 1 (H) or 2 (dual)" : "tx pol must be 0 (V) or 1 (H) here");
+    CHECK_ARG(tx->n_ant >= 0 && tx->n_ant <= 65536, "tx n_ant must be in [0, 65536]");
+    CHECK_ARG(tx->n_ant == 0 || (tx->ant_pos != nullptr && tx->precoding != nullptr),
+              "tx ant_pos and precoding must be set when n_ant > 0");
     return RT_OK;
 }
 
@@ -233,7 +236,10 @@ static void fill_tx(const rt_tx* t, int64_t n_rays, const rt_plane* p, double fr
     d->n_rays = n_rays;
     double lam = RT_C0 / freq;
     d->kappa = (float)(lam * lam / (4.0 * RT_PI * (double)n_rays * p->dx * p->dy));
-    d->pad = 0;
+    d->n_ant = t->n_ant;
+    d->ant_pos = t->ant_pos;
+    d->precoding = t->precoding;
+    d->four_inv_lambda = 4.0 / lam;
 }
 
 static uint64_t mix(uint64_t h, const void* p, size_t n) {
@@ -449,6 +455,8 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     rt_status r;
     for (int i = 0; i < n_tx; i++) {
         if ((r = check_tx(&txs[i], false)) != RT_OK) return r;
+        if (txs[i].n_ant != 0)
+            return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: transmit arrays are not supported here");
         CHECK_ARG(rays_per_tx[i] >= 1 && rays_per_tx[i] <= ((int64_t)1 << 40),
                   "rt_radio_map_batched: rays_per_tx must be in [1, 2^40]");
     }

@@ -132,7 +132,10 @@ struct TxDesc {
     int64_t shift0;          // first entry of this lattice's chunks in the shift table
     int64_t n_chunks;        // full chunks of the launch order (0 = lattice order)
     float kappa;             // lambda^2 / (4 pi N_S dx dy)
-    int32_t pad;
+    int32_t n_ant;           // synthetic transmit array (0 = single element)
+    const double* ant_pos;   // [n_ant][3] element offsets, metres, global frame
+    const float* precoding;  // [n_ant][2] complex weights
+    double four_inv_lambda;  // 4 / lambda: phase in quarter turns per metre
 };
 
 // Plane + physics constants for one call.

@@ -81,6 +81,9 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
         const int ns = a.nseg[r];
         const int64_t ray = a.ray_begin + r;
         Launch Lr = fib_launch(ray, a.tx.n_rays);
+        // transmit array: |alpha|^2 of the departure direction scales every
+        // crossing of the ray and depends on none of the parameters
+        const float kap = a.tx.n_ant > 0 ? a.tx.kappa * array_gain(Lr, a.tx) : a.tx.kappa;
         for (int p = 0; p < a.npol; p++) {
             int pol_index = (a.npol == 2) ? p : (a.tx.pol == 1 ? 1 : 0);
             d3f cth, cph;
@@ -95,7 +98,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 if (cell >= 0) {
                     float g = G[cell];
                     if (g != 0.0f) {
-                        float al = g * a.tx.kappa * __builtin_amdgcn_rcpf(fabsf(s0.z));
+                        float al = g * kap * __builtin_amdgcn_rcpf(fabsf(s0.z));
                         // E_l = T_l C
                         cf e0 = cadd(cscale(cf{s2.x, s2.y}, ct), cscale(cf{s2.z, s2.w}, cp));
                         cf e1 = cadd(cscale(cf{s3.x, s3.y}, ct), cscale(cf{s3.z, s3.w}, cp));

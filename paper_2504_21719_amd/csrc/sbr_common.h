@@ -103,6 +103,43 @@ __device__ __forceinline__ Launch fib_launch(int64_t n, int64_t N) {
     return L;
 }
 
+// sin and cos of the angle (pi/2) v for v in quarter turns: v is split at
+// the nearest integer q (exact in FP64), the remainder y = (pi/2)(v - q),
+// |y| <= pi/4, is taken to FP32, sin y and cos y come from their Taylor
+// series to y^9 and y^10 (truncation below 2e-9 on |y| <= pi/4), and the
+// quadrant q mod 4 rotates the pair.
+__device__ __forceinline__ void sincos_quarter_turns(double v, float& s, float& c) {
+    const double q = rint(v);
+    const float y = (float)((v - q) * (0.5 * RT_PI));
+    const float y2 = y * y;
+    const float sy =
+        y * (1.0f + y2 * (-1.0f / 6.0f + y2 * (1.0f / 120.0f + y2 * (-1.0f / 5040.0f + y2 * (1.0f / 362880.0f)))));
+    const float cy = 1.0f + y2 * (-0.5f + y2 * (1.0f / 24.0f + y2 * (-1.0f / 720.0f +
+                                                                     y2 * (1.0f / 40320.0f - y2 / 3628800.0f))));
+    const int quad = (int)((long long)q & 3);
+    s = quad == 0 ? sy : quad == 1 ? cy : quad == 2 ? -sy : -cy;
+    c = quad == 0 ? cy : quad == 1 ? -sy : quad == 2 ? -cy : sy;
+}
+
+// |alpha|^2 of a synthetic transmit array for launch direction k
+// (Sec. "Handling Multiple Transmit Antennas"): alpha = a_tx^T u_P with the
+// array response a_tx[i] = exp(j 2 pi/lambda k.d_i) of
+// eq. path-solver-array-response-vector.  The phase is formed in FP64 in
+// quarter turns; the element data are the same for every lane.
+__device__ __forceinline__ float array_gain(const Launch& L, const TxDesc& t) {
+    float are = 0.0f, aim = 0.0f;
+    for (int i = 0; i < t.n_ant; i++) {
+        const double* d = t.ant_pos + 3 * (int64_t)i;
+        const double v = (L.kx * d[0] + L.ky * d[1] + L.kz * d[2]) * t.four_inv_lambda;
+        float s, c;
+        sincos_quarter_turns(v, s, c);
+        const float ur = t.precoding[2 * (int64_t)i], ui = t.precoding[2 * (int64_t)i + 1];
+        are += ur * c - ui * s;
+        aim += ur * s + ui * c;
+    }
+    return are * are + aim * aim;
+}
+
 // Transmit pattern components (C_theta, C_phi) on the launch basis
 // (theta_hat, phi_hat) of direction k, for one polarisation (pol_index 0:
 // C' = sqrt(G) theta_hat', 1: C' = sqrt(G) phi_hat').  The local direction is

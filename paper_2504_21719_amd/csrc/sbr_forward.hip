@@ -398,6 +398,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                         if (MODE != MODE_GEOM) {
                             tx_pattern<float>(Lr, td, td.pol == 1 ? 1 : 0, c0t, c0p);
                             if (a.npol == 2) tx_pattern<float>(Lr, td, 1, c1t, c1p);
+                            // a transmit array scales the ray's field by alpha
+                            // and its weights by |alpha|^2
+                            kap = td.kappa;
+                            if (td.n_ant > 0) kap *= array_gain(Lr, td);
                         }
                         k = f3((float)Lr.kx, (float)Lr.ky, (float)Lr.kz);
                         es = f3((float)Lr.tx, (float)Lr.ty, (float)Lr.tz);

@@ -83,7 +83,8 @@ def test_invalid_params_rejected_on_host(bad):
     assert L.rt_last_error().decode()
 
 
-@pytest.mark.parametrize("field,val", [("pattern", 5), ("pol", 3), ("pattern_q", -1.0), ("yaw", float("nan"))])
+@pytest.mark.parametrize("field,val", [("pattern", 5), ("pol", 3), ("pattern_q", -1.0), ("yaw", float("nan")),
+                                       ("n_ant", -1), ("n_ant", 3), ("n_ant", 70000)])
 def test_invalid_tx_rejected_on_host(field, val):
     import paper_2504_21719_amd as rt
     L = rt.lib()
@@ -155,6 +156,13 @@ def test_batched_argument_checks():
     st = L.rt_radio_map_batched(C.cast(dummy, C.c_void_p), m, 1, txs, C.cast(budgets, C.c_void_p), 2, C.byref(pl),
                                 C.byref(_params()), C.cast(out, C.c_void_p), None, None, None)
     assert st == rt.RT_EINVAL        # dual pol not allowed here
+    txs[0].pol = 0
+    txs[0].n_ant = 2
+    txs[0].ant_pos = C.cast(out, C.c_void_p)
+    txs[0].precoding = C.cast(out, C.c_void_p)
+    st = L.rt_radio_map_batched(C.cast(dummy, C.c_void_p), m, 1, txs, C.cast(budgets, C.c_void_p), 2, C.byref(pl),
+                                C.byref(_params()), C.cast(out, C.c_void_p), None, None, None)
+    assert st == rt.RT_EUNSUPPORTED  # transmit arrays only in single-transmitter calls
 
 
 def test_binding_refuses_host_tensors():
