@@ -27,7 +27,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-FLAG_EDGE, FLAG_TIE, FLAG_GRAZING, FLAG_NEAR, FLAG_POLAR = 1, 2, 4, 8, 16
+FLAG_EDGE, FLAG_TIE, FLAG_GRAZING, FLAG_NEAR, FLAG_POLAR, FLAG_TERM = 1, 2, 4, 8, 16, 32
 
 
 def build(force: bool = True) -> str:
@@ -55,7 +55,8 @@ class _Plane(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("freq", C.c_double), ("n_rays", C.c_int64), ("max_depth", C.c_int32),
-                ("t_min", C.c_double)]
+                ("t_min", C.c_double), ("rr_depth", C.c_int32), ("rr_p_max", C.c_double),
+                ("gain_threshold", C.c_double), ("seed", C.c_uint32)]
 
 
 class _Out(C.Structure):
@@ -85,6 +86,8 @@ def lib():
             L.or_launch_field.argtypes = [C.c_double] * 3 + [C.POINTER(_Tx), C.c_int, C.c_void_p, C.c_void_p]
             L.or_lattice_dir.restype = None
             L.or_lattice_dir.argtypes = [C.c_int64, C.c_int64, C.c_void_p]
+            L.or_philox4x32.restype = None
+            L.or_philox4x32.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
             L.or_fibonacci.restype = None
             L.or_fibonacci.argtypes = [C.c_int64, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
             _lib = L
@@ -111,6 +114,15 @@ def _tx(tx) -> _Tx:
         t.ant_pos, t.precoding = pos.ctypes.data, prec.ctypes.data
         t._keep = (pos, prec)          # the arrays live as long as the struct
     return t
+
+
+def philox4x32(ctr, key):
+    """Philox4x32-10 block (four 32-bit counter words, two key words)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().or_philox4x32(c.ctypes.data, k.ctypes.data, o.ctypes.data)
+    return o
 
 
 def _plane(p) -> _Plane:
@@ -182,7 +194,9 @@ def radio_map(scene, tx, plane, params, *, ray_ids=None, ray_begin=None, ray_end
         rh = np.ascontiguousarray(replay_hits, dtype=np.int32)
         assert rh.shape == (n_run, Lmax + 1)
         out.replay_hits = rh.ctypes.data
-    prm = _Params(float(params.freq_hz), int(params.n_rays), Lmax, float(params.t_min))
+    prm = _Params(float(params.freq_hz), int(params.n_rays), Lmax, float(params.t_min),
+                  int(getattr(params, "rr_depth", 1)), float(getattr(params, "rr_p_max", 0.0)),
+                  float(getattr(params, "gain_threshold", 0.0)), int(getattr(params, "seed", 0)) & 0xffffffff)
     txs, pls = _tx(tx), _plane(plane)
     rc = L.or_radio_map(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], M.ctypes.data, n_mat,
                         eps.ctypes.data, sig.ctypes.data, C.byref(txs), C.byref(pls), C.byref(prm),

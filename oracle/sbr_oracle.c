@@ -76,6 +76,7 @@ typedef double complex cplx;
 #define OR_FLAG_GRAZING 4u
 #define OR_FLAG_NEAR 8u
 #define OR_FLAG_POLAR 16u
+#define OR_FLAG_TERM 32u     /* early-termination decision within 1e-5 of its threshold */
 
 #define OR_MAX_PARAMS 64
 #define OR_MAX_DEPTH 64
@@ -161,6 +162,10 @@ typedef struct {
     int64_t n_rays;
     int32_t max_depth;
     double t_min;
+    int32_t rr_depth;       /* early termination before every segment l >= rr_depth */
+    double rr_p_max;        /* Russian roulette: maximum keep probability, 0 = off */
+    double gain_threshold;  /* gain thresholding: path-gain floor, 0 = off */
+    uint32_t seed;          /* key of the random stream */
 } or_params;
 
 typedef struct {
@@ -183,6 +188,42 @@ typedef struct {
     int64_t tri_tests;    /* out: number of ray-triangle tests */
     int64_t segments;     /* out: number of traced segments */
 } or_out;
+
+/* ------------------------------------------------------- random numbers */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): a counter-based generator.  Each of the ten
+ * rounds multiplies words 0 and 2 by two fixed odd constants, keeps the low
+ * halves, and XORs the high halves with the other two words and the round
+ * key; the key is advanced by two Weyl constants between rounds. */
+void or_philox4x32(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; round++) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in [0, 1) for ray n before segment l: the top 24 bits of the
+ * first output word of Philox4x32-10 at counter (n_lo, n_hi, l, 0) with key
+ * (seed, 0), exactly representable in single precision. */
+static double rr_uniform(uint32_t seed, int64_t n, int l)
+{
+    uint32_t ctr[4] = {(uint32_t)((uint64_t)n & 0xffffffffu), (uint32_t)((uint64_t)n >> 32), (uint32_t)l, 0u};
+    uint32_t key[2] = {seed, 0u};
+    uint32_t out[4];
+    or_philox4x32(ctr, key, out);
+    return (double)(out[0] >> 8) * (1.0 / 16777216.0);
+}
 
 /* ------------------------------------------------- synthetic transmit array */
 /* Sec. "Handling Multiple Transmit Antennas": paths start at the array centre;
@@ -559,6 +600,36 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             run_len += h.t;
             k = kr;
             last = h.prim;
+
+            /* Early termination before segment l + 1 (Sec. "Practical Notes",
+             * eq. radio-map-solver-rr-prob), from depth rr_depth on.  The
+             * distance-normalised gain r^2 ||E||^2 is ||E||^2 here (E carries
+             * no spreading); polarisation 0 decides for both.  Gain
+             * thresholding drops the path when its path gain at the current
+             * ray-tube length, (lambda / (4 pi r))^2 ||E||^2, is below the
+             * threshold; Russian roulette keeps it with probability
+             * p = min(||E||^2, p_max) and then divides the field by sqrt(p). */
+            const int next = l + 1;
+            if (next >= prm->rr_depth && (prm->gain_threshold > 0.0 || prm->rr_p_max > 0.0)) {
+                const double gn = cv_norm2(E[0]);
+                if (prm->gain_threshold > 0.0) {
+                    const double thr = prm->gain_threshold;
+                    const double gain = lam * lam / (16.0 * OR_PI * OR_PI * run_len * run_len) * gn;
+                    if (frow && fabs(gain - thr) <= 1e-5 * thr) frow[next] |= OR_FLAG_TERM;
+                    if (gain < thr) break;
+                }
+                if (prm->rr_p_max > 0.0) {
+                    const double p = fmin(gn, prm->rr_p_max);
+                    const double u = rr_uniform(prm->seed, n, next);
+                    if (frow && fabs(u - p) <= 1e-5 * p) frow[next] |= OR_FLAG_TERM;
+                    if (!(u < p)) break;
+                    const double sc = 1.0 / sqrt(p);     /* p is held constant for gradients */
+                    for (int p2 = 0; p2 < npol; p2++) {
+                        E[p2] = cv_scale(E[p2], sc);
+                        for (int q = 0; q < P; q++) dE[p2][q] = cv_scale(dE[p2][q], sc);
+                    }
+                }
+            }
         }
     }
     return 0;

@@ -122,6 +122,13 @@ class Params:
     ray_begin: int = 0
     ray_end: Optional[int] = None  # None -> n_rays
     t_min: float = 1e-4
+    # early termination (both off by default): applied before tracing every
+    # segment l >= rr_depth; Russian roulette with maximum keep probability
+    # rr_p_max, gain thresholding below gain_threshold; draws seeded by seed
+    rr_depth: int = 1
+    rr_p_max: float = 0.0
+    gain_threshold: float = 0.0
+    seed: int = 0
 
     def end(self) -> int:
         return self.n_rays if self.ray_end is None else int(self.ray_end)

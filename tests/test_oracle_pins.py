@@ -480,3 +480,113 @@ def test_array_gain_applies_per_ray_at_every_depth(oracle_lib):
     for n in both[:2000]:
         a, b = ratio[rays == n]
         assert abs(a - b) <= 1e-9 * max(a, b, 1e-12)
+
+
+# ---------------------------------------- early termination (Russian roulette)
+def test_philox_known_answers(oracle_lib):
+    """The generator that drives Russian roulette reproduces the published
+    Philox4x32-10 known-answer vectors (tests/golden/philox4x32_10_kat.txt)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    n = 0
+    for line in open(path):
+        if not line.strip() or line.startswith("#"):
+            continue
+        w = [int(x, 16) for x in line.split()]
+        out = oracle_lib.philox4x32(w[0:4], w[4:6])
+        assert [int(v) for v in out] == w[6:10]
+        n += 1
+    assert n == 3
+
+
+def _rr_params(N, L, **kw):
+    return sg.Params(FREQ, N, L, **kw)
+
+
+def test_roulette_depth_gating_and_threshold_limits(oracle_lib):
+    """Termination from a depth beyond L changes nothing; a vanishing gain
+    threshold changes nothing; an infinite one leaves only the direct (depth-0)
+    contributions."""
+    cfg = sg.tiny_config(n_rays=30_000)
+    base = oracle_lib.radio_map(cfg.scene, cfg.tx, cfg.plane, _rr_params(30_000, 3))
+    off = oracle_lib.radio_map(cfg.scene, cfg.tx, cfg.plane,
+                               _rr_params(30_000, 3, rr_depth=4, rr_p_max=0.5, gain_threshold=1.0))
+    assert np.array_equal(off.map, base.map)
+    tiny = oracle_lib.radio_map(cfg.scene, cfg.tx, cfg.plane, _rr_params(30_000, 3, gain_threshold=1e-300))
+    assert np.array_equal(tiny.map, base.map)
+    d0 = oracle_lib.radio_map(cfg.scene, cfg.tx, cfg.plane, _rr_params(30_000, 0))
+    inf = oracle_lib.radio_map(cfg.scene, cfg.tx, cfg.plane, _rr_params(30_000, 3, gain_threshold=1e300))
+    assert np.array_equal(inf.map, d0.map)
+
+
+def test_roulette_reweights_survivors_by_one_over_p(oracle_lib):
+    """With p_max below every path's distance-normalised gain, p = p_max for
+    all paths: a ray survives its roulette iff its uniform is below p_max, and
+    each surviving crossing weighs exactly 1/p_max times the unterminated one."""
+    N, pmax = 20_000, 0.02
+    pl = sg.Plane(1.5, -30.0, -30.0, 2.0, 2.0, 30, 30)
+    tx = sg.Tx((0.0, 0.0, 10.0), pol=sg.POL_H)     # |r_perp|^2 >= 0.155 on concrete: never below p_max
+    scene = sg.ground_quad(100.0)
+    r0 = oracle_lib.radio_map(scene, tx, pl, _rr_params(N, 1), want_records=True, want_hits=True)
+    r1 = oracle_lib.radio_map(scene, tx, pl, _rr_params(N, 1, rr_p_max=pmax, seed=77), want_records=True,
+                              want_hits=True)
+    traced1 = r0.hits[:, 1] != -2            # rays that reach a second segment without roulette
+    surv = r1.hits[:, 1] != -2
+    assert np.all(surv <= traced1)
+    # the decision follows the counter-based stream: uniform of (ray, depth 1)
+    u = np.array([(int(oracle_lib.philox4x32([n & 0xffffffff, n >> 32, 1, 0], [77, 0])[0]) >> 8) / 2.0 ** 24
+                  for n in np.nonzero(traced1)[0]])
+    assert np.array_equal(surv[traced1], u < pmax)
+    assert 0.5 * pmax < surv[traced1].mean() < 2.0 * pmax
+    w0 = {(int(a), int(b)): w for a, b, w in zip(r0.records["ray"], r0.records["depth"], r0.records["w"])}
+    n1 = 0
+    for a, b, w in zip(r1.records["ray"], r1.records["depth"], r1.records["w"]):
+        ref = w0[(int(a), int(b))]
+        if b == 0:
+            assert w == ref
+        else:
+            assert abs(w * pmax - ref) <= 1e-12 * ref
+            n1 += 1
+    assert n1 > 20
+
+
+def test_roulette_is_unbiased(oracle_lib):
+    """Russian roulette with p = min(||E||^2, p_max) keeps the estimator
+    unbiased: the total reflected power with roulette matches the one without
+    within four standard errors (seeded, so the outcome is fixed)."""
+    N = 200_000
+    cfg = sg.tiny_config(n_rays=N)
+    r0 = oracle_lib.radio_map(cfg.scene, cfg.tx, cfg.plane, _rr_params(N, 3), want_records=True)
+    r1 = oracle_lib.radio_map(cfg.scene, cfg.tx, cfg.plane, _rr_params(N, 3, rr_p_max=0.9, seed=5),
+                              want_records=True)
+    def reflected_per_ray(r):
+        m = r.records["depth"] >= 1
+        return np.bincount(r.records["ray"][m], weights=r.records["w"][m], minlength=N)
+    a, b = reflected_per_ray(r0), reflected_per_ray(r1)
+    assert np.count_nonzero(b) < 0.9 * np.count_nonzero(a)      # roulette did remove paths
+    se = np.std(b - a) * math.sqrt(N)
+    assert abs(b.sum() - a.sum()) <= 4.0 * se
+    assert abs(b.sum() / a.sum() - 1.0) < 0.05
+
+
+def test_roulette_probability_is_the_normalised_gain(oracle_lib):
+    """H-pol over a horizontal ground: after the bounce ||E||^2 = |r_perp|^2
+    (textbook Fresnel via Snell's law at cos(theta_i) = |k_z|), so with
+    p_max = 1 a ray survives its roulette iff its uniform is below that."""
+    N = 20_000
+    pl = sg.Plane(1.5, -30.0, -30.0, 2.0, 2.0, 30, 30)
+    tx = sg.Tx((0.0, 0.0, 10.0), pol=sg.POL_H)
+    scene = sg.ground_quad(100.0)
+    r0 = oracle_lib.radio_map(scene, tx, pl, _rr_params(N, 1), want_hits=True)
+    r1 = oracle_lib.radio_map(scene, tx, pl, _rr_params(N, 1, rr_p_max=1.0, seed=3), want_hits=True)
+    rays = np.nonzero(r0.hits[:, 1] != -2)[0]
+    k = cf.lattice_directions(rays, N)
+    rp, _ = cf.fresnel_general(cf.eta(5.24, 0.12, FREQ), np.abs(k[:, 2]))
+    p = np.abs(rp) ** 2
+    u = np.array([(int(oracle_lib.philox4x32([int(n) & 0xffffffff, int(n) >> 32, 1, 0], [3, 0])[0]) >> 8) / 2.0 ** 24
+                  for n in rays])
+    clear = np.abs(u - p) > 1e-9
+    surv = r1.hits[rays, 1] != -2
+    assert clear.sum() > 0.99 * rays.size
+    assert np.array_equal(surv[clear], (u < p)[clear])
+    assert 0.1 < surv.mean() < 0.9
