@@ -192,6 +192,23 @@ typedef struct {
     int32_t accel;
     int32_t deposit;
     int32_t block_size;   /* 0 = tuned default; else 64, 128, 256 or 512 */
+    /* Early termination (Sec. "Practical Notes", eq. radio-map-solver-rr-prob),
+     * applied before tracing every segment l >= max(rr_depth, 1):
+     *   gain_threshold  > 0: drop the path when its path gain at the current
+     *                   ray-tube length r, (lambda/(4 pi r))^2 ||E||^2, is
+     *                   below it (biased); 0 = off
+     *   rr_p_max        in (0, 1]: Russian roulette, keep the path with
+     *                   p = min(||E||^2, rr_p_max) and divide its field by
+     *                   sqrt(p) (unbiased); 0 = off
+     *   seed            key of the per-ray random stream (Philox4x32-10 at
+     *                   counter (ray index, l))
+     * ||E||^2 is the distance-normalised gain of polarisation 0 (times
+     * |alpha|^2 with a transmit array).  Not available with a tape or in
+     * rt_radio_map_batched (RT_EUNSUPPORTED). */
+    int32_t rr_depth;
+    float rr_p_max;
+    float gain_threshold;
+    uint32_t seed;
 } rt_sbr_params;
 
 /*

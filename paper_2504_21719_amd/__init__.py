@@ -60,7 +60,9 @@ class rt_plane(C.Structure):
 class rt_sbr_params(C.Structure):
     _fields_ = [("freq_hz", C.c_double), ("n_rays", C.c_int64), ("ray_begin", C.c_int64),
                 ("ray_end", C.c_int64), ("max_depth", C.c_int32), ("accumulate", C.c_int32),
-                ("t_min", C.c_float), ("accel", C.c_int32), ("deposit", C.c_int32), ("block_size", C.c_int32)]
+                ("t_min", C.c_float), ("accel", C.c_int32), ("deposit", C.c_int32), ("block_size", C.c_int32),
+                ("rr_depth", C.c_int32), ("rr_p_max", C.c_float), ("gain_threshold", C.c_float),
+                ("seed", C.c_uint32)]
 
 
 class rt_records(C.Structure):
@@ -178,7 +180,9 @@ def make_params(p, *, ray_begin=None, ray_end=None, accumulate=0, accel=RT_ACCEL
     re_ = ray_end if ray_end is not None else getattr(p, "ray_end", None)
     re_ = 0 if re_ is None else int(re_)
     return rt_sbr_params(float(p.freq_hz), int(p.n_rays), rb, re_, int(p.max_depth), int(accumulate),
-                         float(p.t_min), int(accel), int(deposit), int(block_size))
+                         float(p.t_min), int(accel), int(deposit), int(block_size),
+                         int(getattr(p, "rr_depth", 1)), float(getattr(p, "rr_p_max", 0.0)),
+                         float(getattr(p, "gain_threshold", 0.0)), int(getattr(p, "seed", 0)) & 0xffffffff)
 
 
 # ------------------------------------------------------------------ scene

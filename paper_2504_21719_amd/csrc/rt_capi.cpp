@@ -183,6 +183,9 @@ static rt_status check_params(const rt_sbr_params* p, int64_t* b, int64_t* e) {
                   p->block_size == 512,
               "block_size must be 0, 64, 128, 256 or 512");
     CHECK_ARG(p->accumulate == 0 || p->accumulate == 1, "accumulate must be 0 or 1");
+    CHECK_ARG(std::isfinite(p->rr_p_max) && p->rr_p_max >= 0.0f && p->rr_p_max <= 1.0f,
+              "rr_p_max must be in [0, 1]");
+    CHECK_ARG(std::isfinite(p->gain_threshold) && p->gain_threshold >= 0.0f, "gain_threshold must be >= 0");
     int64_t begin = p->ray_begin, end = p->ray_end <= 0 ? p->n_rays : p->ray_end;
     CHECK_ARG(begin >= 0 && begin <= end && end <= p->n_rays, "ray range must satisfy 0 <= begin <= end <= n_rays");
     *b = begin;
@@ -351,6 +354,16 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
     f.zero_map = params->accumulate == 0;
     f.map = out_map;
     f.tape = tape;
+    f.rr_depth = std::max(1, params->rr_depth);
+    f.rr_p_max = params->rr_p_max;
+    f.gain_threshold = params->gain_threshold;
+    f.seed = params->seed;
+    {
+        const double lam = RT_C0 / params->freq_hz;
+        f.gain_scale = (float)(lam * lam / (16.0 * RT_PI * RT_PI));
+    }
+    if (tape && (f.rr_p_max > 0.0f || f.gain_threshold > 0.0f))
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map: early termination cannot be recorded on a tape");
     if (records) {
         f.hits = records->hits;
         f.cells = records->cells;
@@ -467,6 +480,8 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     p.ray_begin = 0;
     p.ray_end = 0;
     if ((r = check_params(&p, &b, &e)) != RT_OK) return r;
+    if (p.rr_p_max > 0.0f || p.gain_threshold > 0.0f)
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: early termination is not supported here");
     if ((r = check_device(scene)) != RT_OK) return r;
     rt_scene* s = const_cast<rt_scene*>(scene);
     hipStream_t hs = (hipStream_t)stream;

@@ -175,6 +175,11 @@ struct FwdLaunch {
     int32_t* cells;
     float* weights;
     unsigned long long* stats;
+    int32_t rr_depth;        // early termination before segments l >= rr_depth (>= 1)
+    float rr_p_max;          // Russian roulette (0 = off)
+    float gain_threshold;    // gain thresholding (0 = off)
+    uint32_t seed;
+    float gain_scale;        // lambda^2 / (16 pi^2)
 };
 rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st);
 

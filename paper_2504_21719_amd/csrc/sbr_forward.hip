@@ -61,6 +61,13 @@ struct FwdArgs {
     int qrem;                      // queues q < qrem hold qper + 1 work indices, the others qper
     unsigned long long qper;
     int claim;                     // work indices claimed per queue atomic (>= 64)
+    // early termination (kernel variant TERM): before segments l >= rr_depth
+    int rr_depth;
+    float rr_p_max;                // Russian roulette, 0 = off
+    float gain_threshold;          // gain thresholding, 0 = off
+    unsigned seed;
+    float gain_scale;              // lambda^2 / (16 pi^2): path gain = gain_scale ||E||^2 / r^2
+    float inv_kappa;               // 1 / tx.kappa: |alpha|^2 = kap * inv_kappa
     int* spill;
     int64_t spill_stride;
     int spill_depth;
@@ -112,6 +119,29 @@ __device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int
 __device__ __forceinline__ float wave_sum(float v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
     return v;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011), written from its
+// definition: ten rounds, each multiplying words 0 and 2 by two odd constants,
+// keeping the low halves and XORing the high halves with words 1, 3 and the
+// round key, which advances by two Weyl constants.  Uniform in [0, 1) from
+// the top 24 bits of word 0 at counter (n_lo, n_hi, l, 0), key (seed, 0).
+__device__ __forceinline__ float philox_uniform(unsigned seed, int64_t n, int l) {
+    unsigned c0 = (unsigned)((uint64_t)n & 0xffffffffu), c1 = (unsigned)((uint64_t)n >> 32), c2 = (unsigned)l,
+             c3 = 0u;
+    unsigned k0 = seed, k1 = 0u;
+#pragma unroll
+    for (int round = 0; round < 10; round++) {
+        const unsigned lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const unsigned lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return (float)(c0 >> 8) * (1.0f / 16777216.0f);
 }
 
 // Per-lane traversal stack: the first RT_STACK_LDS entries {node, entry
@@ -287,7 +317,7 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
     return slot_best;
 }
 
-template <bool BRUTE, int MODE, bool WIDE>
+template <bool BRUTE, int MODE, bool WIDE, bool TERM>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_forward(const FwdArgs a) {
     extern __shared__ int2 s_stack[];
     const int lstride = blockDim.x;
@@ -315,6 +345,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     cf Ta = {1, 0}, Tb = {0, 0}, Tc = {0, 0}, Td = {1, 0};
     float c0t = 0.f, c0p = 0.f, c1t = 0.f, c1p = 0.f;   // C_T per polarisation
     float kap = a.tx.kappa;   // lambda^2 / (4 pi N_S |M|) of the lane's transmitter
+    float rlen = 0.0f;        // unfolded length to the last interaction (early termination only)
     float* mapb = a.map;      // map of the lane's transmitter
 
     while (true) {
@@ -411,6 +442,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                         Tc = cf{0, 0};
                         Td = cf{1, 0};
                         l = 0;
+                        rlen = 0.0f;
                         last = -1;
                         active = true;
                         if (a.hits) {
@@ -539,6 +571,32 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                 es = b.es_new;
                 last = slot;
                 l++;
+                if (TERM && l >= a.rr_depth) {
+                    // early termination before segment l: the distance-normalised
+                    // gain ||T C||^2 of polarisation 0 (times |alpha|^2)
+                    rlen += t_hit;
+                    const cf e0 = cadd(cscale(Ta, c0t), cscale(Tb, c0p));
+                    const cf e1 = cadd(cscale(Tc, c0t), cscale(Td, c0p));
+                    const float gn = (cabs2(e0) + cabs2(e1)) * (kap * a.inv_kappa);
+                    bool drop = false;
+                    if (a.gain_threshold > 0.0f)
+                        drop = a.gain_scale * gn * __builtin_amdgcn_rcpf(rlen * rlen) < a.gain_threshold;
+                    if (!drop && a.rr_p_max > 0.0f) {
+                        const float p = fminf(gn, a.rr_p_max);
+                        if (philox_uniform(a.seed, a.ray_begin + rid, l) < p) {
+                            const float sc = __builtin_amdgcn_rsqf(p);   // survivors carry 1/sqrt(p)
+                            Ta = cscale(Ta, sc);
+                            Tb = cscale(Tb, sc);
+                            Tc = cscale(Tc, sc);
+                            Td = cscale(Td, sc);
+                        } else {
+                            drop = true;
+                        }
+                    }
+                    if (drop) active = false;
+                } else if (TERM) {
+                    rlen += t_hit;
+                }
             }
         }
     }
@@ -621,7 +679,8 @@ static rt_status size_spill(FwdArgs& a, const rt_scene* s, int block, int* block
 }
 
 template <int MODE>
-static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, int block, hipStream_t st) {
+static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, int block, hipStream_t st,
+                        bool term = false) {
     FwdArgs a = args;
     // about 4096 work items per queue, at most RT_QUEUES queues
     a.nq = (int)std::max<int64_t>(1, std::min<int64_t>(RT_QUEUES, a.n_work / 4096));
@@ -638,12 +697,23 @@ static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, i
     if (const char* env = getenv("RTMAP_CLAIM"))
         a.claim = std::max(64, std::min(4096, atoi(env)));
     size_t lds = sizeof(int2) * RT_STACK_LDS * block;   // {node, entry distance} per entry
+    if constexpr (MODE == MODE_SINGLE) {
+        if (term) {
+            if (accel == RT_ACCEL_BRUTE)
+                hipLaunchKernelGGL((k_forward<true, MODE, false, true>), dim3(blocks), dim3(block), lds, st, a);
+            else if (wide)
+                hipLaunchKernelGGL((k_forward<false, MODE, true, true>), dim3(blocks), dim3(block), lds, st, a);
+            else
+                hipLaunchKernelGGL((k_forward<false, MODE, false, true>), dim3(blocks), dim3(block), lds, st, a);
+            return;
+        }
+    }
     if (accel == RT_ACCEL_BRUTE)
-        hipLaunchKernelGGL((k_forward<true, MODE, false>), dim3(blocks), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((k_forward<true, MODE, false, false>), dim3(blocks), dim3(block), lds, st, a);
     else if (wide)
-        hipLaunchKernelGGL((k_forward<false, MODE, true>), dim3(blocks), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((k_forward<false, MODE, true, false>), dim3(blocks), dim3(block), lds, st, a);
     else
-        hipLaunchKernelGGL((k_forward<false, MODE, false>), dim3(blocks), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((k_forward<false, MODE, false, false>), dim3(blocks), dim3(block), lds, st, a);
 }
 
 // Tree width: forced by accel, else tuned (or overridden), default 4-wide.
@@ -689,7 +759,14 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
         hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, f.map, zn, s->counters);
     }
     if (f.order) rt_order_shifts_single(f.order, f.tx.n_rays, s->shifts, st);
-    if (a.n_work > 0) launch_mode<MODE_SINGLE>(a, f.accel, use_wide(s, f.accel), blocks, f.block, st);
+    a.rr_depth = f.rr_depth;
+    a.rr_p_max = f.rr_p_max;
+    a.gain_threshold = f.gain_threshold;
+    a.seed = f.seed;
+    a.gain_scale = f.gain_scale;
+    a.inv_kappa = 1.0f / f.tx.kappa;
+    const bool term = f.rr_p_max > 0.0f || f.gain_threshold > 0.0f;
+    if (a.n_work > 0) launch_mode<MODE_SINGLE>(a, f.accel, use_wide(s, f.accel), blocks, f.block, st, term);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rt_hip_fail(e, "forward launch");
     return RT_OK;

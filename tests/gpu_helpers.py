@@ -16,7 +16,8 @@ import numpy as np
 import oracle
 import scenegen as sg
 
-EXEMPT_FLAGS = (oracle.FLAG_EDGE | oracle.FLAG_TIE | oracle.FLAG_GRAZING | oracle.FLAG_NEAR | oracle.FLAG_POLAR)
+EXEMPT_FLAGS = (oracle.FLAG_EDGE | oracle.FLAG_TIE | oracle.FLAG_GRAZING | oracle.FLAG_NEAR | oracle.FLAG_POLAR
+                | oracle.FLAG_TERM)
 
 
 @dataclasses.dataclass
