@@ -320,11 +320,22 @@ def large_leg(rt, sg, dev, args, reps=3):
     r = rooflines(int(st[0]), int(st[1]), int(st[2]), int(st[3]), width, t, None,
                   note="tree + triangles about %d MB: larger than L2, partly held in the 256 MB MALL"
                   % (info.device_bytes >> 20))
+    # early termination from depth 2: Russian roulette with p_max = 0.5
+    import dataclasses
+    prr = dataclasses.replace(cfg.params, rr_depth=2, rr_p_max=0.5, seed=1)
+    stats.zero_()
+    rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, prr, out, stats=stats)
+    torch.cuda.synchronize()
+    seg_rr = int(stats[0])
+    t_rr = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, prr, out), reps, 1)
     return {"workload": "large: 1,021,074 triangles, 1e8 rays, max depth 8, 1000x1000 cells of 2 m",
             "value": round(int(st[0]) / (t * 1e-3) / 1e6, 3), "unit": "M ray-bounces/s", "ms_per_step": round(t, 3),
             "segments_per_step": int(st[0]), "build_ms": round(info.build_ms, 3), "bvh_depth": info.bvh_depth,
             "tuned_width": width, "roofline_hbm_model": r["hbm_model"],
-            "roofline_alu": {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac")}}
+            "roofline_alu": {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac")},
+            "roulette": {"setting": "Russian roulette from depth 2, p_max 0.5",
+                         "ms_per_step": round(t_rr, 3), "segments_per_step": seg_rr,
+                         "speedup": round(t / t_rr, 3)}}
 
 
 def extra_legs(rt, sg, cfg, scene, eps, sig, dev, reps=5):
