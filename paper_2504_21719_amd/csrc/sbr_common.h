@@ -77,20 +77,49 @@ struct Launch {
     double px, py;          // phi_hat = (px, py, 0)
 };
 
+// sin and cos of 2 pi u, u = m 2^-53 turns (m < 2^53), in FP64: 4u quarter
+// turns are split in integers at the nearest quarter turn q (exact), the
+// remainder y = (pi/2)(4u - q) has |y| <= pi/4, sin y and cos y come from
+// their Taylor series to y^13 and y^14 (truncation below 3e-14 relative), and
+// q mod 4 rotates the pair.
+__device__ __forceinline__ void sincos_turns53(uint64_t m, double& s, double& c) {
+    const uint64_t q = (m + (1ull << 50)) >> 51;
+    const double y = (double)((int64_t)m - (int64_t)(q << 51)) * (0.5 * RT_PI * 0x1.0p-51);
+    const double y2 = y * y;
+    double ps = 1.0 / 6227020800.0;
+    ps = fma(ps, y2, -1.0 / 39916800.0);
+    ps = fma(ps, y2, 1.0 / 362880.0);
+    ps = fma(ps, y2, -1.0 / 5040.0);
+    ps = fma(ps, y2, 1.0 / 120.0);
+    ps = fma(ps, y2, -1.0 / 6.0);
+    const double sy = fma(y * y2, ps, y);
+    double pc = -1.0 / 87178291200.0;
+    pc = fma(pc, y2, 1.0 / 479001600.0);
+    pc = fma(pc, y2, -1.0 / 3628800.0);
+    pc = fma(pc, y2, 1.0 / 40320.0);
+    pc = fma(pc, y2, -1.0 / 720.0);
+    pc = fma(pc, y2, 1.0 / 24.0);
+    pc = fma(pc, y2, -0.5);
+    const double cy = fma(y2, pc, 1.0);
+    const int quad = (int)(q & 3);
+    s = quad == 0 ? sy : quad == 1 ? cy : quad == 2 ? -sy : -cy;
+    c = quad == 0 ? cy : quad == 1 ? -sy : quad == 2 ? -cy : sy;
+}
+
 // Lattice point n of an N-point spherical Fibonacci lattice, in FP64.
 __device__ __forceinline__ Launch fib_launch(int64_t n, int64_t N) {
-    double z, ph;
+    double z;
+    uint64_t m;                                               // azimuth in turns, times 2^53
     if (N == 1) {
         z = 0.0;
-        ph = RT_PI;
+        m = 1ull << 52;                                       // half a turn
     } else {
-        z = 1.0 - 2.0 * (double)n / (double)(N - 1);
-        uint64_t f = (uint64_t)n * kPhiFrac;                 // wraps mod 2^64
-        ph = 2.0 * RT_PI * ((double)(f >> 11) * 0x1.0p-53);
+        z = 1.0 - (double)n * (2.0 / (double)(N - 1));         // the quotient is hoisted per lattice
+        m = ((uint64_t)n * kPhiFrac) >> 11;                   // product wraps mod 2^64
     }
     double st = sqrt(fmax(0.0, (1.0 - z) * (1.0 + z)));
     double sp, cp;
-    sincos(ph, &sp, &cp);
+    sincos_turns53(m, sp, cp);
     Launch L;
     L.kx = st * cp;
     L.ky = st * sp;
