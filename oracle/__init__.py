@@ -27,7 +27,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-FLAG_EDGE, FLAG_TIE, FLAG_GRAZING, FLAG_NEAR, FLAG_POLAR, FLAG_TERM = 1, 2, 4, 8, 16, 32
+FLAG_EDGE, FLAG_TIE, FLAG_GRAZING, FLAG_NEAR, FLAG_POLAR, FLAG_TERM, FLAG_CHOICE = 1, 2, 4, 8, 16, 32, 64
 
 
 def build(force: bool = True) -> str:
@@ -56,7 +56,7 @@ class _Plane(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("freq", C.c_double), ("n_rays", C.c_int64), ("max_depth", C.c_int32),
                 ("t_min", C.c_double), ("rr_depth", C.c_int32), ("rr_p_max", C.c_double),
-                ("gain_threshold", C.c_double), ("seed", C.c_uint32)]
+                ("gain_threshold", C.c_double), ("seed", C.c_uint32), ("refraction", C.c_int32)]
 
 
 class _Out(C.Structure):
@@ -77,11 +77,15 @@ def lib():
             L = C.CDLL(_LIB)
             L.or_radio_map.restype = C.c_int
             L.or_radio_map.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
-                                       C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(_Tx),
+                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_Tx),
                                        C.POINTER(_Plane), C.POINTER(_Params), C.c_void_p, C.c_int64,
                                        C.c_int64, C.c_int64, C.POINTER(_Out)]
             L.or_fresnel.restype = None
             L.or_fresnel.argtypes = [C.c_double] * 4 + [C.POINTER(C.c_double)] * 4
+            L.or_fresnel_slab.restype = None
+            L.or_fresnel_slab.argtypes = [C.c_double] * 5 + [C.c_void_p]
+            L.or_uniform.restype = C.c_double
+            L.or_uniform.argtypes = [C.c_uint32, C.c_int64, C.c_int, C.c_uint32]
             L.or_launch_field.restype = None
             L.or_launch_field.argtypes = [C.c_double] * 3 + [C.POINTER(_Tx), C.c_int, C.c_void_p, C.c_void_p]
             L.or_lattice_dir.restype = None
@@ -142,15 +146,22 @@ class OracleResult:
 
 
 def radio_map(scene, tx, plane, params, *, ray_ids=None, ray_begin=None, ray_end=None,
-              eps_r=None, sigma=None, want_hits=False, want_records=False, rec_cap=None,
+              eps_r=None, sigma=None, thickness=None, want_hits=False, want_records=False, rec_cap=None,
               grad_map=None, replay_hits=None) -> OracleResult:
-    """Run the oracle over a ray range (default: the params' range) or an explicit list."""
+    """Run the oracle over a ray range (default: the params' range) or an explicit list.
+
+    ``thickness`` (metres per material; default ``scene.thickness``, None =
+    half-space walls) switches to the slab coefficients; ``params.refraction``
+    samples reflection or transmission at every hit and needs a thickness."""
     L = lib()
     V = np.ascontiguousarray(scene.vertices, dtype=np.float32)
     F = np.ascontiguousarray(scene.triangles, dtype=np.int32)
     M = np.ascontiguousarray(scene.tri_material, dtype=np.int32)
     eps = np.ascontiguousarray(scene.eps_r if eps_r is None else eps_r, dtype=np.float64)
     sig = np.ascontiguousarray(scene.sigma if sigma is None else sigma, dtype=np.float64)
+    if thickness is None:
+        thickness = getattr(scene, "thickness", None)
+    thk = None if thickness is None else np.ascontiguousarray(thickness, dtype=np.float64)
     n_mat = int(eps.shape[0])
     npol = 2 if int(tx.pol) == 2 else 1
     Lmax = int(params.max_depth)
@@ -196,10 +207,11 @@ def radio_map(scene, tx, plane, params, *, ray_ids=None, ray_begin=None, ray_end
         out.replay_hits = rh.ctypes.data
     prm = _Params(float(params.freq_hz), int(params.n_rays), Lmax, float(params.t_min),
                   int(getattr(params, "rr_depth", 1)), float(getattr(params, "rr_p_max", 0.0)),
-                  float(getattr(params, "gain_threshold", 0.0)), int(getattr(params, "seed", 0)) & 0xffffffff)
+                  float(getattr(params, "gain_threshold", 0.0)), int(getattr(params, "seed", 0)) & 0xffffffff,
+                  int(getattr(params, "refraction", 0)))
     txs, pls = _tx(tx), _plane(plane)
     rc = L.or_radio_map(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], M.ctypes.data, n_mat,
-                        eps.ctypes.data, sig.ctypes.data, C.byref(txs), C.byref(pls), C.byref(prm),
+                        eps.ctypes.data, sig.ctypes.data, _ptr(thk), C.byref(txs), C.byref(pls), C.byref(prm),
                         _ptr(ids), n_run if ids is not None else 0, b, e, C.byref(out))
     if rc != 0:
         raise ValueError("oracle rejected its arguments (code %d)" % rc)
@@ -217,6 +229,18 @@ def fresnel(eps_r, sigma, freq, cos_theta):
     a, b, c, d = (C.c_double(), C.c_double(), C.c_double(), C.c_double())
     L.or_fresnel(eps_r, sigma, freq, cos_theta, C.byref(a), C.byref(b), C.byref(c), C.byref(d))
     return complex(a.value, b.value), complex(c.value, d.value)
+
+
+def fresnel_slab(eps_r, sigma, freq, cos_theta, d):
+    """(r_perp, r_par, t_perp, t_par) of a slab of thickness d, eq. fresnel_slab."""
+    o = np.zeros(8)
+    lib().or_fresnel_slab(eps_r, sigma, freq, cos_theta, d, o.ctypes.data)
+    return complex(o[0], o[1]), complex(o[2], o[3]), complex(o[4], o[5]), complex(o[6], o[7])
+
+
+def uniform(seed, n, l, stream):
+    """The oracle's uniform draw for ray n, index l and stream (0 termination, 1 interaction type)."""
+    return float(lib().or_uniform(int(seed) & 0xffffffff, int(n), int(l), int(stream)))
 
 
 def launch_field(k, tx, pol_index=0):

@@ -24,6 +24,14 @@
  *     eq. reflected_refracted_vectors), TE/TM bases (eq. fresnel_in_vectors,
  *     eq. fresnel_out_vectors), vacuum Fresnel coefficients (eq. fresnel_vac)
  *     with the complex relative permittivity of eq. eta;
+ *   - optional finite-thickness walls: the single-layer slab coefficients
+ *     eq. fresnel_slab with eq. q_fresnel_slab (Sec. "Single-Layer Slab")
+ *     replace the half-space ones, and optional refraction: at every hit one
+ *     interaction type, reflection or transmission, is sampled with the
+ *     probabilities of eq. path-solver-used-dist-event and the field is
+ *     divided by the square root of the probability (the Pr(chi)^-1 factor of
+ *     the estimator); transmitted rays keep their direction (Sec.
+ *     "Interactions with Scene Objects");
  *   - an optional synthetic transmit array with a precoding vector
  *     (Sec. "Handling Multiple Transmit Antennas"): the launch field of a ray
  *     is multiplied by alpha = a_tx^T u_P of its departure direction;
@@ -44,8 +52,15 @@
  * derivatives use dual numbers through eq. rotation and eq. theta_phi_prime.
  *
  * Readings where the paper is silent (stated once here, used throughout):
- *   - only specular reflection is enabled, so q(R) = 1 and Pr(chi) = 1;
- *   - half-space (vacuum-incidence) Fresnel coefficients, no slab thickness;
+ *   - by default only specular reflection is enabled, so q(R) = 1 and
+ *     Pr(chi) = 1; with refraction, diffuse reflection and diffraction stay
+ *     off (S = 0, R = 1, q(D) = 0), so q(T) = 1 - q(R);
+ *   - half-space (vacuum-incidence) Fresnel coefficients unless a slab
+ *     thickness is given; a transmitted ray keeps the TE/TM basis of the
+ *     incident side (k_t = k_i gives e_t,par = e_i,par in
+ *     eq. fresnel_out_vectors);
+ *   - the interaction at the end of segment l of ray n reflects iff the
+ *     uniform draw at Philox counter (n, l, 1) is below q(R);
  *   - c0 = 299792458 m/s, eps0 = 8.8541878128e-12 F/m, phi_g = (1+sqrt 5)/2;
  *   - the plane is two-sided and non-occluding; a segment contributes iff
  *     0 < t_plane < t_hit (t_hit = inf on a miss); cells are half-open;
@@ -77,6 +92,7 @@ typedef double complex cplx;
 #define OR_FLAG_NEAR 8u
 #define OR_FLAG_POLAR 16u
 #define OR_FLAG_TERM 32u     /* early-termination decision within 1e-5 of its threshold */
+#define OR_FLAG_CHOICE 64u   /* reflection/transmission draw within 1e-5 of q(R) */
 
 #define OR_MAX_PARAMS 64
 #define OR_MAX_DEPTH 64
@@ -166,6 +182,7 @@ typedef struct {
     double rr_p_max;        /* Russian roulette: maximum keep probability, 0 = off */
     double gain_threshold;  /* gain thresholding: path-gain floor, 0 = off */
     uint32_t seed;          /* key of the random stream */
+    int32_t refraction;     /* 1: sample reflection or transmission at every hit */
 } or_params;
 
 typedef struct {
@@ -213,12 +230,14 @@ void or_philox4x32(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t 
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Uniform in [0, 1) for ray n before segment l: the top 24 bits of the
- * first output word of Philox4x32-10 at counter (n_lo, n_hi, l, 0) with key
- * (seed, 0), exactly representable in single precision. */
-static double rr_uniform(uint32_t seed, int64_t n, int l)
+/* Uniform in [0, 1) for ray n, index l and stream s: the top 24 bits of the
+ * first output word of Philox4x32-10 at counter (n_lo, n_hi, l, s) with key
+ * (seed, 0), exactly representable in single precision.  Stream 0 is early
+ * termination before segment l, stream 1 the interaction type at the end of
+ * segment l. */
+static double rr_uniform(uint32_t seed, int64_t n, int l, uint32_t stream)
 {
-    uint32_t ctr[4] = {(uint32_t)((uint64_t)n & 0xffffffffu), (uint32_t)((uint64_t)n >> 32), (uint32_t)l, 0u};
+    uint32_t ctr[4] = {(uint32_t)((uint64_t)n & 0xffffffffu), (uint32_t)((uint64_t)n >> 32), (uint32_t)l, stream};
     uint32_t key[2] = {seed, 0u};
     uint32_t out[4];
     or_philox4x32(ctr, key, out);
@@ -242,6 +261,23 @@ static cplx array_alpha(const or_tx* tx, vec3 k, double lam)
         alpha += u * cexp(I * phase);
     }
     return alpha;
+}
+
+/* ------------------------------------------------------------- slab */
+/* Single-layer slab (Sec. "Single-Layer Slab", eq. fresnel_slab): with
+ * x = exp(-j q) and q = (2 pi d / lambda) s, s = sqrt(eta - sin^2 theta_1)
+ * (eq. q_fresnel_slab), each half-space coefficient r' of eq. fresnel_vac
+ * becomes r = r' (1 - x^2) / (1 - r'^2 x^2), and the slab passes
+ * t = (1 - r'^2) x / (1 - r'^2 x^2).  k_d = 2 pi d / lambda.  The r's are
+ * replaced in place. */
+static void slab(cplx s, double k_d, cplx* r_perp, cplx* r_par, cplx* t_perp, cplx* t_par)
+{
+    cplx x1 = cexp(-I * (k_d * s)), x2 = x1 * x1;
+    cplx rp2 = *r_perp * *r_perp, rl2 = *r_par * *r_par;
+    *t_perp = (1.0 - rp2) * x1 / (1.0 - rp2 * x2);
+    *t_par = (1.0 - rl2) * x1 / (1.0 - rl2 * x2);
+    *r_perp = *r_perp * (1.0 - x2) / (1.0 - rp2 * x2);
+    *r_par = *r_par * (1.0 - x2) / (1.0 - rl2 * x2);
 }
 
 /* ------------------------------------------------------ lattice and launch */
@@ -410,7 +446,7 @@ static hit_info closest_hit(const or_mesh* m, vec3 o, vec3 k, int64_t last, doub
  */
 int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                  const int32_t* tri_mat, int32_t n_mat,
-                 const double* eps_r, const double* sigma,
+                 const double* eps_r, const double* sigma, const double* thickness,
                  const or_tx* tx, const or_plane* pl, const or_params* prm,
                  const int64_t* ray_ids, int64_t n_ids, int64_t ray_begin, int64_t ray_end,
                  or_out* out)
@@ -418,6 +454,12 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
     if (prm->n_rays < 1 || prm->max_depth < 0 || prm->max_depth >= OR_MAX_DEPTH) return 1;
     if (pl->W < 1 || pl->H < 1 || !(pl->dx > 0) || !(pl->dy > 0)) return 1;
     if (n_mat < 1 || 2 * n_mat + 3 > OR_MAX_PARAMS) return 1;
+    if (prm->refraction && !thickness) return 1;
+    if (thickness) {
+        for (int32_t i = 0; i < n_mat; i++)
+            if (!(thickness[i] >= 0.0)) return 1;
+        if (out->grad_map && out->grad) return 1;   /* no slab derivatives */
+    }
     for (int64_t i = 0; i < n_tri; i++) {
         for (int j = 0; j < 3; j++)
             if (F[3 * i + j] < 0 || F[3 * i + j] >= n_v) return 1;
@@ -543,7 +585,7 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             }
             if (h.prim < 0 || l == L) break;
 
-            /* specular reflection at primitive h.prim */
+            /* interaction at primitive h.prim */
             int m = tri_mat[h.prim];
             cplx eta = eps_r[m] - I * sigma[m] / (OR_EPS0 * omega);
             double c = -vdot(nrm, k);                 /* cos(theta_1) >= 0 */
@@ -556,6 +598,9 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             cplx ds = 1.0 / (2.0 * s);
             cplx dr_perp = ((-ds) * den_p - (c - s) * ds) / (den_p * den_p);
             cplx dr_par = ((c - ds) * den_l - (eta * c - s) * (c + ds)) / (den_l * den_l);
+
+            cplx t_perp = 0.0, t_par = 0.0;
+            if (thickness) slab(s, 2.0 * OR_PI * thickness[m] / lam, &r_perp, &r_par, &t_perp, &t_par);
 
             vec3 kn = vcross(k, nrm);
             vec3 e_perp;
@@ -570,6 +615,27 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             vec3 kr = vsub(k, vscale(nrm, 2.0 * vdot(k, nrm)));
             kr = vunit(kr);
             vec3 er_par = vunit(vcross(e_perp, kr));
+
+            /* interaction type (eq. path-solver-used-dist-event with S = 0,
+             * R = 1, q(D) = 0): reflection with q(R) = (|r_perp|^2 +
+             * |r_par|^2) / (|r_perp|^2 + |r_par|^2 + |t_perp|^2 + |t_par|^2),
+             * else transmission; the field of the sampled branch is divided
+             * by sqrt(q) so that ||E||^2 carries the Pr(chi)^-1 factor of
+             * eq. radio-map-solver-ci-all-2-estimator */
+            int transmit = 0;
+            double inv_sqrt_q = 1.0;
+            if (prm->refraction) {
+                double ar = creal(r_perp * conj(r_perp)) + creal(r_par * conj(r_par));
+                double at = creal(t_perp * conj(t_perp)) + creal(t_par * conj(t_par));
+                double qr = (ar + at > 0.0) ? ar / (ar + at) : 1.0;
+                double u = rr_uniform(prm->seed, n, l, 1u);
+                if (frow && fabs(u - qr) <= 1e-5) frow[l] |= OR_FLAG_CHOICE;
+                transmit = !(u < qr);
+                inv_sqrt_q = 1.0 / sqrt(transmit ? 1.0 - qr : qr);
+            }
+            cplx c_perp = transmit ? t_perp : r_perp;
+            cplx c_par = transmit ? t_par : r_par;
+            vec3 out_par = transmit ? e_par : er_par;
 
             for (int p = 0; p < npol; p++) {
                 cplx a_perp = cv_dot_real(e_perp, E[p]);
@@ -592,13 +658,13 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                     }
                 }
                 cvec3 En = cv_zero();
-                En = cv_axpy(En, r_perp * a_perp, e_perp);
-                En = cv_axpy(En, r_par * a_par, er_par);
+                En = cv_axpy(En, c_perp * a_perp * inv_sqrt_q, e_perp);
+                En = cv_axpy(En, c_par * a_par * inv_sqrt_q, out_par);
                 E[p] = En;
             }
             o = vadd(o, vscale(k, h.t));
             run_len += h.t;
-            k = kr;
+            if (!transmit) k = kr;
             last = h.prim;
 
             /* Early termination before segment l + 1 (Sec. "Practical Notes",
@@ -620,7 +686,7 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                 }
                 if (prm->rr_p_max > 0.0) {
                     const double p = fmin(gn, prm->rr_p_max);
-                    const double u = rr_uniform(prm->seed, n, next);
+                    const double u = rr_uniform(prm->seed, n, next, 0u);
                     if (frow && fabs(u - p) <= 1e-5 * p) frow[next] |= OR_FLAG_TERM;
                     if (!(u < p)) break;
                     const double sc = 1.0 / sqrt(p);     /* p is held constant for gradients */
@@ -645,6 +711,26 @@ void or_fresnel(double eps_r, double sigma, double freq, double c,
     cplx a = (c - s) / (c + s), b = (eta * c - s) / (eta * c + s);
     *rperp_re = creal(a); *rperp_im = cimag(a);
     *rpar_re = creal(b); *rpar_im = cimag(b);
+}
+
+/* Slab coefficients for tests: eq. fresnel_slab at incidence cos(theta_1) = c
+ * for a slab of thickness d (metres); out = (r_perp, r_par, t_perp, t_par) as
+ * (re, im) pairs. */
+void or_fresnel_slab(double eps_r, double sigma, double freq, double c, double d, double* out8)
+{
+    double omega = 2.0 * OR_PI * freq;
+    cplx eta = eps_r - I * sigma / (OR_EPS0 * omega);
+    cplx s = csqrt(eta - (1.0 - c * c));
+    cplx rp = (c - s) / (c + s), rl = (eta * c - s) / (eta * c + s), tp, tl;
+    slab(s, 2.0 * OR_PI * d * freq / OR_C0, &rp, &rl, &tp, &tl);
+    out8[0] = creal(rp); out8[1] = cimag(rp); out8[2] = creal(rl); out8[3] = cimag(rl);
+    out8[4] = creal(tp); out8[5] = cimag(tp); out8[6] = creal(tl); out8[7] = cimag(tl);
+}
+
+/* Uniform draw of the random stream, for tests. */
+double or_uniform(uint32_t seed, int64_t n, int l, uint32_t stream)
+{
+    return rr_uniform(seed, n, l, stream);
 }
 
 /* Transmitted field (value only) for tests: E[3 complex as re,im pairs]. */

@@ -32,6 +32,18 @@ import numpy as np
 CONCRETE = (5.24, 0.12)
 GLASS = (6.31, 0.05)
 METAL = (1.0, 1.0e7)
+# Slab thickness per material (m) for finite-thickness walls: a 20 cm
+# concrete wall, a 10 mm glass pane, a 5 mm metal sheet.  The paper prints
+# none; these are round values of the usual construction.
+THICKNESS = {CONCRETE: 0.2, GLASS: 0.01, METAL: 0.005}
+
+
+def with_thickness(scene: "Scene", thickness=None) -> "Scene":
+    """Copy of ``scene`` with slab thickness per material (default THICKNESS
+    looked up by (eps_r, sigma))."""
+    if thickness is None:
+        thickness = [THICKNESS[(float(e), float(s))] for e, s in zip(scene.eps_r, scene.sigma)]
+    return dataclasses.replace(scene, thickness=np.asarray(thickness, dtype=np.float64))
 
 PATTERN_ISO = 0          # isotropic, G = 1
 PATTERN_DIRECTIONAL = 1  # G(alpha) = (q+1) ((1+cos alpha)/2)^q about local +x
@@ -46,6 +58,7 @@ class Scene:
     eps_r: np.ndarray             # float64 [n_mat]
     sigma: np.ndarray             # float64 [n_mat], S/m
     name: str = ""
+    thickness: Optional[np.ndarray] = None   # float64 [n_mat] slab thickness (m); None = half-space
 
     @property
     def n_triangles(self) -> int:
@@ -129,6 +142,8 @@ class Params:
     rr_p_max: float = 0.0
     gain_threshold: float = 0.0
     seed: int = 0
+    # 1: sample reflection or transmission at every hit (needs slab thickness)
+    refraction: int = 0
 
     def end(self) -> int:
         return self.n_rays if self.ray_end is None else int(self.ray_end)

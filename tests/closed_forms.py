@@ -39,6 +39,30 @@ def fresnel_general(eta2, cos_t1):
     return r_perp, r_par
 
 
+def slab_characteristic(eta2, cos_t1, d, lam):
+    """(r_s, r_p, t_s, t_p) of a homogeneous layer in vacuum by the optical
+    characteristic-matrix method (Born and Wolf, Principles of Optics,
+    Sec. 1.6): the layer of index n = sqrt(eta2) and phase thickness
+    delta = (2 pi / lambda) n d cos(theta_2) has the matrix
+    [[cos delta, j sin delta / Y], [j Y sin delta, cos delta]], with the
+    tilted admittance Y = n cos(theta_2) (TE) or n / cos(theta_2) (TM) and
+    Y_0 = cos(theta_1) or 1 / cos(theta_1) in vacuum; with (B, C) = M (1, Y_0),
+    r = (Y_0 B - C) / (Y_0 B + C) and t = 2 Y_0 / (Y_0 B + C).  r_p refers to
+    the tangential field, so r_p = -r_par of eq. fresnel at one interface.
+    The matrix is even in n cos(theta_2), so no square-root branch enters."""
+    c = np.asarray(cos_t1, dtype=np.complex128)
+    n2 = np.sqrt(eta2 + 0j)
+    cos_t2 = np.sqrt(1.0 - (1.0 - c ** 2) / eta2)
+    delta = 2 * math.pi / lam * d * n2 * cos_t2
+    out = []
+    for y0, y1 in ((c, n2 * cos_t2), (1.0 / c, n2 / cos_t2)):
+        B = np.cos(delta) + 1j * np.sin(delta) / y1 * y0
+        C = 1j * y1 * np.sin(delta) + np.cos(delta) * y0
+        out.append(((y0 * B - C) / (y0 * B + C), 2 * y0 / (y0 * B + C)))
+    (rs, ts), (rp, tp) = out
+    return rs, rp, ts, tp
+
+
 def normal_incidence_r(eta2):
     """Textbook normal-incidence reflection coefficient (1 - n)/(1 + n), n = sqrt(eta)."""
     n = np.sqrt(eta2 + 0j)
