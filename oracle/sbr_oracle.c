@@ -431,7 +431,7 @@ static hit_info closest_hit(const or_mesh* m, vec3 o, vec3 k, int64_t last, doub
             h.t2 = t;
         }
     }
-    if (t_edge <= h.t * (1.0 + 1e-6)) h.flags |= OR_FLAG_EDGE;
+    if (isfinite(t_edge) && t_edge <= h.t * (1.0 + 1e-6)) h.flags |= OR_FLAG_EDGE;
     if (h.prim >= 0 && h.t2 <= h.t * (1.0 + 1e-5)) h.flags |= OR_FLAG_TIE;
     if (t_any < 1e-2) h.flags |= OR_FLAG_NEAR;
     return h;
