@@ -107,10 +107,18 @@ rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
  * Radio materials, device float32 arrays.  eps_r and sigma are the real
  * relative permittivity and the conductivity of eq. eta, indexed by material
  * (and, for batched calls, [n_samples][n_materials]).
+ * thickness (optional, NULL = half-space walls): slab thickness d >= 0 in
+ * metres per material.  Every interaction then uses the single-layer slab
+ * coefficients of eq. fresnel_slab with eq. q_fresnel_slab (Sec.
+ * "Single-Layer Slab") instead of the half-space ones of eq. fresnel_vac.
+ * The array is read by the kernels of the call and must stay valid until it
+ * completes; a negative or non-finite entry gives undefined results.  Not
+ * supported with a tape or by rt_radio_map_batched (RT_EUNSUPPORTED).
  */
 typedef struct {
     const float* eps_r;
     const float* sigma;
+    const float* thickness;
 } rt_materials;
 
 enum { RT_PATTERN_ISO = 0, RT_PATTERN_DIRECTIONAL = 1 };
@@ -209,6 +217,19 @@ typedef struct {
     float rr_p_max;
     float gain_threshold;
     uint32_t seed;
+    /* Refraction (Sec. "Sampling Interaction Types"): 0 = specular
+     * reflection only (q(R) = 1); 1 = at the end of every segment l that
+     * hits a triangle one interaction is sampled, reflection with
+     * q(R) = (|r_perp|^2 + |r_par|^2) / (|r_perp|^2 + |r_par|^2 + |t_perp|^2
+     * + |t_par|^2), else transmission (eq. path-solver-used-dist-event with
+     * no diffuse reflection or diffraction), from the draw at Philox4x32-10
+     * counter (ray index, l, 1) with key (seed, 0); the field of the
+     * sampled branch is divided by sqrt(q), the Pr(chi)^-1 factor of the
+     * estimator.  A transmitted ray keeps its direction (Sec. "Interactions
+     * with Scene Objects") and its TE/TM basis.  Needs materials.thickness
+     * (RT_EINVAL otherwise); not available with a tape or in
+     * rt_radio_map_batched (RT_EUNSUPPORTED). */
+    int32_t refraction;
 } rt_sbr_params;
 
 /*

@@ -43,7 +43,7 @@ class rt_scene_info(C.Structure):
 
 
 class rt_materials(C.Structure):
-    _fields_ = [("eps_r", C.c_void_p), ("sigma", C.c_void_p)]
+    _fields_ = [("eps_r", C.c_void_p), ("sigma", C.c_void_p), ("thickness", C.c_void_p)]
 
 
 class rt_tx(C.Structure):
@@ -62,7 +62,7 @@ class rt_sbr_params(C.Structure):
                 ("ray_end", C.c_int64), ("max_depth", C.c_int32), ("accumulate", C.c_int32),
                 ("t_min", C.c_float), ("accel", C.c_int32), ("deposit", C.c_int32), ("block_size", C.c_int32),
                 ("rr_depth", C.c_int32), ("rr_p_max", C.c_float), ("gain_threshold", C.c_float),
-                ("seed", C.c_uint32)]
+                ("seed", C.c_uint32), ("refraction", C.c_int32)]
 
 
 class rt_records(C.Structure):
@@ -182,7 +182,8 @@ def make_params(p, *, ray_begin=None, ray_end=None, accumulate=0, accel=RT_ACCEL
     return rt_sbr_params(float(p.freq_hz), int(p.n_rays), rb, re_, int(p.max_depth), int(accumulate),
                          float(p.t_min), int(accel), int(deposit), int(block_size),
                          int(getattr(p, "rr_depth", 1)), float(getattr(p, "rr_p_max", 0.0)),
-                         float(getattr(p, "gain_threshold", 0.0)), int(getattr(p, "seed", 0)) & 0xffffffff)
+                         float(getattr(p, "gain_threshold", 0.0)), int(getattr(p, "seed", 0)) & 0xffffffff,
+                         int(getattr(p, "refraction", 0)))
 
 
 # ------------------------------------------------------------------ scene
@@ -229,19 +230,22 @@ def scene_from_mesh(scene, device="cuda") -> RtScene:
     return rt_build_scene(V, F, M, len(scene.eps_r))
 
 
-def materials(eps_r, sigma) -> rt_materials:
-    return rt_materials(_ptr(eps_r), _ptr(sigma))
+def materials(eps_r, sigma, thickness=None) -> rt_materials:
+    return rt_materials(_ptr(eps_r), _ptr(sigma), _ptr(thickness))
 
 
 # ----------------------------------------------------------------- forward
 def rt_radio_map(scene: RtScene, eps_r, sigma, tx, plane, params, out_map, *, tape=None, hits=None,
-                 cells=None, weights=None, stats=None, stream=None, **pkw):
-    """Queue the SBR radio map into ``out_map`` (device f32 [H][W] or [2][H][W])."""
+                 cells=None, weights=None, stats=None, stream=None, thickness=None, **pkw):
+    """Queue the SBR radio map into ``out_map`` (device f32 [H][W] or [2][H][W]).
+
+    ``thickness`` (device f32 [n_mat], metres) selects slab walls; with
+    ``params.refraction`` every hit samples reflection or transmission."""
     rec = rt_records(_ptr(hits), _ptr(cells), _ptr(weights), _ptr(stats))
     p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
     t = tx if isinstance(tx, rt_tx) else make_tx(tx)
     pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
-    _check(lib().rt_radio_map(scene.handle, materials(eps_r, sigma), C.byref(t), C.byref(pl), C.byref(p),
+    _check(lib().rt_radio_map(scene.handle, materials(eps_r, sigma, thickness), C.byref(t), C.byref(pl), C.byref(p),
                               _ptr(out_map), tape.handle if tape is not None else None, C.byref(rec),
                               _stream(stream)))
     return out_map

@@ -186,6 +186,7 @@ static rt_status check_params(const rt_sbr_params* p, int64_t* b, int64_t* e) {
     CHECK_ARG(std::isfinite(p->rr_p_max) && p->rr_p_max >= 0.0f && p->rr_p_max <= 1.0f,
               "rr_p_max must be in [0, 1]");
     CHECK_ARG(std::isfinite(p->gain_threshold) && p->gain_threshold >= 0.0f, "gain_threshold must be >= 0");
+    CHECK_ARG(p->refraction == 0 || p->refraction == 1, "refraction must be 0 or 1");
     int64_t begin = p->ray_begin, end = p->ray_end <= 0 ? p->n_rays : p->ray_end;
     CHECK_ARG(begin >= 0 && begin <= end && end <= p->n_rays, "ray range must satisfy 0 <= begin <= end <= n_rays");
     *b = begin;
@@ -330,6 +331,10 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
         CHECK_ARG(tape->n_rays == e - b && tape->max_depth == params->max_depth,
                   "rt_radio_map: tape was created for another ray range or depth");
     }
+    CHECK_ARG(!params->refraction || materials.thickness,
+              "rt_radio_map: refraction needs the slab thickness of every material");
+    if (tape && materials.thickness)
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map: slab walls and refraction cannot be recorded on a tape");
     if ((r = check_device(scene)) != RT_OK) return r;
     FwdLaunch f{};
     f.scene = scene;
@@ -364,6 +369,9 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
     }
     if (tape && (f.rr_p_max > 0.0f || f.gain_threshold > 0.0f))
         return rt_fail(RT_EUNSUPPORTED, "rt_radio_map: early termination cannot be recorded on a tape");
+    f.thickness = materials.thickness;
+    f.refraction = params->refraction;
+    f.k0 = (float)(2.0 * RT_PI * params->freq_hz / RT_C0);
     if (records) {
         f.hits = records->hits;
         f.cells = records->cells;
@@ -425,6 +433,8 @@ extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials m
                                            float* grad_sigma, float* grad_orient, void* stream) {
     CHECK_ARG(scene != nullptr, "rt_radio_map_backward: scene is NULL");
     CHECK_ARG(tape != nullptr, "rt_radio_map_backward: tape is NULL");
+    if (materials.thickness || (params && params->refraction))
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_backward: slab walls and refraction have no adjoint here");
     CHECK_ARG(grad_map != nullptr, "rt_radio_map_backward: grad_map is NULL");
     CHECK_ARG(materials.eps_r && materials.sigma, "rt_radio_map_backward: material pointers are NULL");
     rt_status r;
@@ -482,6 +492,8 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     if ((r = check_params(&p, &b, &e)) != RT_OK) return r;
     if (p.rr_p_max > 0.0f || p.gain_threshold > 0.0f)
         return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: early termination is not supported here");
+    if (p.refraction || materials.thickness)
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: slab walls and refraction are not supported here");
     if ((r = check_device(scene)) != RT_OK) return r;
     rt_scene* s = const_cast<rt_scene*>(scene);
     hipStream_t hs = (hipStream_t)stream;

@@ -180,6 +180,9 @@ struct FwdLaunch {
     float gain_threshold;    // gain thresholding (0 = off)
     uint32_t seed;
     float gain_scale;        // lambda^2 / (16 pi^2)
+    const float* thickness;  // slab thickness per material (m), or null (half-space)
+    int32_t refraction;      // sample reflection or transmission at every hit
+    float k0;                // 2 pi / lambda
 };
 rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st);
 

@@ -368,6 +368,7 @@ __device__ __forceinline__ void box4(const Ray& r, __amdgpu_buffer_rsrc_t rs, un
 struct Fresnel {
     cf rperp, rpar;       // eq. fresnel_vac
     cf drperp, drpar;     // d/d eta
+    cf s;                 // sqrt(eta - sin^2 theta_1), principal branch
 };
 
 // c = cos(theta_1) >= 0, eta = eps_r - j sigma/(eps0 omega)  (eq. eta)
@@ -381,6 +382,7 @@ __device__ __forceinline__ Fresnel fresnel(float c, cf eta) {
     cf lp = cadd(ec, s), lm = csub(ec, s);
     F.rperp = cdiv(cm, cp);
     F.rpar = cdiv(lm, lp);
+    F.s = s;
     if (DERIV) {
         // r_perp = (c - s)/(c + s), s = sqrt(eta - sin^2): d r_perp/d eta = -c / (s (c + s)^2)
         // r_par = (eta c - s)/(eta c + s): d r_par/d eta = c (eta - 2 sin^2) / (s (eta c + s)^2)
@@ -393,6 +395,27 @@ __device__ __forceinline__ Fresnel fresnel(float c, cf eta) {
         F.drpar = cf{0, 0};
     }
     return F;
+}
+
+// Single-layer slab (eq. fresnel_slab, eq. q_fresnel_slab) of phase constant
+// k_d = 2 pi d / lambda: with x = exp(-j k_d s), each half-space r' held in F
+// becomes r' (1 - x^2) / (1 - r'^2 x^2) in place, and the slab passes
+// t = (1 - r'^2) x / (1 - r'^2 x^2).  Im s <= 0, so |x| <= 1.
+__device__ __forceinline__ void slab(Fresnel& F, float k_d, cf& tperp, cf& tpar) {
+    const float qre = k_d * F.s.re, qim = k_d * F.s.im;
+    float sn, cs;
+    sincosf(qre, &sn, &cs);
+    const float m = __expf(qim);
+    const cf x = cf{m * cs, -m * sn};
+    const cf x2 = cmul(x, x);
+    const cf one = cf{1.0f, 0.0f};
+    const cf rp2 = cmul(F.rperp, F.rperp), rl2 = cmul(F.rpar, F.rpar);
+    const cf dp = csub(one, cmul(rp2, x2)), dl = csub(one, cmul(rl2, x2));
+    const cf omx2 = csub(one, x2);
+    tperp = cdiv(cmul(csub(one, rp2), x), dp);
+    tpar = cdiv(cmul(csub(one, rl2), x), dl);
+    F.rperp = cdiv(cmul(F.rperp, omx2), dp);
+    F.rpar = cdiv(cmul(F.rpar, omx2), dl);
 }
 
 // Orthonormal TE direction e_perp = (k x n)/|k x n|; at normal incidence any

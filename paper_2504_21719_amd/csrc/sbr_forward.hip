@@ -61,13 +61,17 @@ struct FwdArgs {
     int qrem;                      // queues q < qrem hold qper + 1 work indices, the others qper
     unsigned long long qper;
     int claim;                     // work indices claimed per queue atomic (>= 64)
-    // early termination (kernel variant TERM): before segments l >= rr_depth
+    // early termination (kernel variant EXT): before segments l >= rr_depth
     int rr_depth;
     float rr_p_max;                // Russian roulette, 0 = off
     float gain_threshold;          // gain thresholding, 0 = off
     unsigned seed;
     float gain_scale;              // lambda^2 / (16 pi^2): path gain = gain_scale ||E||^2 / r^2
     float inv_kappa;               // 1 / tx.kappa: |alpha|^2 = kap * inv_kappa
+    // finite-thickness walls and refraction (kernel variant EXT)
+    const float* thickness;        // slab thickness per material (m), or null
+    int refraction;                // 1: sample reflection or transmission at every hit
+    float k0;                      // 2 pi / lambda
     int* spill;
     int64_t spill_stride;
     int spill_depth;
@@ -125,10 +129,12 @@ __device__ __forceinline__ float wave_sum(float v) {
 // definition: ten rounds, each multiplying words 0 and 2 by two odd constants,
 // keeping the low halves and XORing the high halves with words 1, 3 and the
 // round key, which advances by two Weyl constants.  Uniform in [0, 1) from
-// the top 24 bits of word 0 at counter (n_lo, n_hi, l, 0), key (seed, 0).
-__device__ __forceinline__ float philox_uniform(unsigned seed, int64_t n, int l) {
+// the top 24 bits of word 0 at counter (n_lo, n_hi, l, stream), key
+// (seed, 0); stream 0 decides early termination before segment l, stream 1
+// the interaction type at the end of segment l.
+__device__ __forceinline__ float philox_uniform(unsigned seed, int64_t n, int l, unsigned stream) {
     unsigned c0 = (unsigned)((uint64_t)n & 0xffffffffu), c1 = (unsigned)((uint64_t)n >> 32), c2 = (unsigned)l,
-             c3 = 0u;
+             c3 = stream;
     unsigned k0 = seed, k1 = 0u;
 #pragma unroll
     for (int round = 0; round < 10; round++) {
@@ -317,7 +323,7 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
     return slot_best;
 }
 
-template <bool BRUTE, int MODE, bool WIDE, bool TERM>
+template <bool BRUTE, int MODE, bool WIDE, bool EXT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_forward(const FwdArgs a) {
     extern __shared__ int2 s_stack[];
     const int lstride = blockDim.x;
@@ -552,26 +558,49 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                 float4 nm = a.normals[slot];
                 int mat = __float_as_int(nm.w);
                 Bounce b = bounce_geometry(k, es, f3(nm.x, nm.y, nm.z));
+                bool transmit = false;
                 if (MODE != MODE_GEOM) {
                     cf eta = cf{a.eps_r[mat], -a.sigma[mat] * a.pl.inv_eps0_omega};
                     Fresnel F = fresnel<false>(b.c, eta);
-                    // T <- diag(r_perp, -r_par) W T
+                    cf cperp = F.rperp, cpar = F.rpar;
+                    if (EXT && a.thickness) {
+                        // single-layer slab: r and t from r' and x = exp(-j q)
+                        cf tperp, tpar;
+                        slab(F, a.k0 * a.thickness[mat], tperp, tpar);
+                        cperp = F.rperp;
+                        cpar = F.rpar;
+                        if (a.refraction) {
+                            // reflect with q(R), else transmit with q(T); the
+                            // sampled branch carries 1/sqrt(q)
+                            const float ar = cabs2(F.rperp) + cabs2(F.rpar);
+                            const float at = cabs2(tperp) + cabs2(tpar);
+                            const float tot = ar + at;
+                            const float qr = tot > 0.0f ? ar / tot : 1.0f;
+                            transmit = !(philox_uniform(a.seed, a.ray_begin + rid, l, 1u) < qr);
+                            const float sc = __builtin_amdgcn_rsqf(transmit ? at / tot : qr);
+                            cperp = cscale(transmit ? tperp : F.rperp, sc);
+                            cpar = cscale(transmit ? tpar : F.rpar, sc);
+                        }
+                    }
+                    // T <- diag(c_perp, -c_par) W T: the new basis is (e_perp,
+                    // k' x e_perp), whose second vector is -e_par of the
+                    // outgoing wave for both k' = k_r and k' = k
                     cf na = cadd(cscale(Ta, b.w00), cscale(Tc, b.w01));
                     cf nb = cadd(cscale(Tb, b.w00), cscale(Td, b.w01));
                     cf nc = cadd(cscale(Ta, b.w10), cscale(Tc, b.w11));
                     cf nd = cadd(cscale(Tb, b.w10), cscale(Td, b.w11));
-                    Ta = cmul(F.rperp, na);
-                    Tb = cmul(F.rperp, nb);
-                    cf mr = cf{-F.rpar.re, -F.rpar.im};
+                    Ta = cmul(cperp, na);
+                    Tb = cmul(cperp, nb);
+                    cf mr = cf{-cpar.re, -cpar.im};
                     Tc = cmul(mr, nc);
                     Td = cmul(mr, nd);
                 }
                 o = o + k * t_hit;
-                k = b.kr;
+                if (!transmit) k = b.kr;
                 es = b.es_new;
                 last = slot;
                 l++;
-                if (TERM && l >= a.rr_depth) {
+                if (EXT && l >= a.rr_depth && (a.rr_p_max > 0.0f || a.gain_threshold > 0.0f)) {
                     // early termination before segment l: the distance-normalised
                     // gain ||T C||^2 of polarisation 0 (times |alpha|^2)
                     rlen += t_hit;
@@ -583,7 +612,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                         drop = a.gain_scale * gn * __builtin_amdgcn_rcpf(rlen * rlen) < a.gain_threshold;
                     if (!drop && a.rr_p_max > 0.0f) {
                         const float p = fminf(gn, a.rr_p_max);
-                        if (philox_uniform(a.seed, a.ray_begin + rid, l) < p) {
+                        if (philox_uniform(a.seed, a.ray_begin + rid, l, 0u) < p) {
                             const float sc = __builtin_amdgcn_rsqf(p);   // survivors carry 1/sqrt(p)
                             Ta = cscale(Ta, sc);
                             Tb = cscale(Tb, sc);
@@ -594,7 +623,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                         }
                     }
                     if (drop) active = false;
-                } else if (TERM) {
+                } else if (EXT) {
                     rlen += t_hit;
                 }
             }
@@ -680,7 +709,7 @@ static rt_status size_spill(FwdArgs& a, const rt_scene* s, int block, int* block
 
 template <int MODE>
 static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, int block, hipStream_t st,
-                        bool term = false) {
+                        bool ext = false) {
     FwdArgs a = args;
     // about 4096 work items per queue, at most RT_QUEUES queues
     a.nq = (int)std::max<int64_t>(1, std::min<int64_t>(RT_QUEUES, a.n_work / 4096));
@@ -698,7 +727,7 @@ static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, i
         a.claim = std::max(64, std::min(4096, atoi(env)));
     size_t lds = sizeof(int2) * RT_STACK_LDS * block;   // {node, entry distance} per entry
     if constexpr (MODE == MODE_SINGLE) {
-        if (term) {
+        if (ext) {
             if (accel == RT_ACCEL_BRUTE)
                 hipLaunchKernelGGL((k_forward<true, MODE, false, true>), dim3(blocks), dim3(block), lds, st, a);
             else if (wide)
@@ -765,8 +794,11 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
     a.seed = f.seed;
     a.gain_scale = f.gain_scale;
     a.inv_kappa = 1.0f / f.tx.kappa;
-    const bool term = f.rr_p_max > 0.0f || f.gain_threshold > 0.0f;
-    if (a.n_work > 0) launch_mode<MODE_SINGLE>(a, f.accel, use_wide(s, f.accel), blocks, f.block, st, term);
+    a.thickness = f.thickness;
+    a.refraction = f.refraction;
+    a.k0 = f.k0;
+    const bool ext = f.rr_p_max > 0.0f || f.gain_threshold > 0.0f || f.thickness != nullptr;
+    if (a.n_work > 0) launch_mode<MODE_SINGLE>(a, f.accel, use_wide(s, f.accel), blocks, f.block, st, ext);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rt_hip_fail(e, "forward launch");
     return RT_OK;

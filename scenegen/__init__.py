@@ -236,11 +236,12 @@ def empty_scene() -> Scene:
                  np.zeros((0,), np.int32), np.array([CONCRETE[0]]), np.array([CONCRETE[1]]), "empty")
 
 
-def tiny_scene() -> Scene:
-    """Ground quad 200x200 m at z=0 plus a 20x20x30 m box centred at (40, 0)."""
+def tiny_scene(bottom=True) -> Scene:
+    """Ground quad 200x200 m at z=0 plus a 20x20x30 m box centred at (40, 0)
+    (bottom=False: without the box's bottom face, which lies on the ground)."""
     mb = _MeshBuilder()
     mb.quad((-100.0, -100.0, 0.0), (100.0, -100.0, 0.0), (100.0, 100.0, 0.0), (-100.0, 100.0, 0.0), 0)
-    mb.box((30.0, -10.0, 0.0), (50.0, 10.0, 30.0), 0, bottom=True)
+    mb.box((30.0, -10.0, 0.0), (50.0, 10.0, 30.0), 0, bottom=bottom)
     return mb.build([CONCRETE], "tiny")
 
 
@@ -250,12 +251,14 @@ def tiny_config(n_rays=100_000, max_depth=3) -> Config:
                   Params(3.5e9, n_rays, max_depth), "tiny")
 
 
-def manhattan_scene(seed=2) -> Scene:
+def manhattan_scene(seed=2, bottoms=True) -> Scene:
     """10x10 blocks on a 100 m pitch over [-500,500]^2 with 20 m streets.
 
     Streets are centred on x, y = -500 + 100 i; one box per block, centred in
     the block, footprint U(20,60) m per side, height U(10,80) m, concrete or
     glass with p = 0.5.  Draws are row-major over (i, j): w_x, w_y, h, material.
+    bottoms=False leaves out the bottom faces, which coincide with the ground
+    (for transmitted rays, which can reach them).
     """
     rng = np.random.default_rng(seed)
     mb = _MeshBuilder()
@@ -268,7 +271,7 @@ def manhattan_scene(seed=2) -> Scene:
             mat = int(rng.uniform() < 0.5)      # 0 concrete, 1 glass
             cx = -450.0 + 100.0 * i
             cy = -450.0 + 100.0 * j
-            mb.box((cx - wx / 2, cy - wy / 2, 0.0), (cx + wx / 2, cy + wy / 2, h), mat, bottom=True)
+            mb.box((cx - wx / 2, cy - wy / 2, 0.0), (cx + wx / 2, cy + wy / 2, h), mat, bottom=bottoms)
     return mb.build([CONCRETE, GLASS], "manhattan")
 
 

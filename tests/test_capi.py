@@ -66,7 +66,8 @@ def _params(**kw):
 
 @pytest.mark.parametrize("bad", [dict(n_rays=0), dict(max_depth=-1), dict(max_depth=65), dict(freq_hz=0.0),
                                  dict(ray_begin=5, ray_end=3), dict(ray_end=2000), dict(accel=4), dict(deposit=7),
-                                 dict(block_size=100), dict(accumulate=2), dict(t_min=-1.0)])
+                                 dict(block_size=100), dict(accumulate=2), dict(t_min=-1.0), dict(refraction=2),
+                                 dict(refraction=1)])
 def test_invalid_params_rejected_on_host(bad):
     import paper_2504_21719_amd as rt
     L = rt.lib()
@@ -157,6 +158,10 @@ def test_batched_argument_checks():
                                 C.byref(_params()), C.cast(out, C.c_void_p), None, None, None)
     assert st == rt.RT_EINVAL        # dual pol not allowed here
     txs[0].pol = 0
+    mt = rt.rt_materials(C.cast(out, C.c_void_p), C.cast(out, C.c_void_p), C.cast(out, C.c_void_p))
+    st = L.rt_radio_map_batched(C.cast(dummy, C.c_void_p), mt, 1, txs, C.cast(budgets, C.c_void_p), 2, C.byref(pl),
+                                C.byref(_params()), C.cast(out, C.c_void_p), None, None, None)
+    assert st == rt.RT_EUNSUPPORTED  # slab walls only in single-transmitter calls
     txs[0].n_ant = 2
     txs[0].ant_pos = C.cast(out, C.c_void_p)
     txs[0].precoding = C.cast(out, C.c_void_p)

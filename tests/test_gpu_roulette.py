@@ -46,7 +46,8 @@ def test_termination_after_last_depth_changes_nothing():
     cfg.params.rr_p_max, cfg.params.rr_depth = 0.3, cfg.params.max_depth + 1
     b = gpu_radio_map(cfg, scene_handle=s)
     assert np.array_equal(a.hits, b.hits) and np.array_equal(a.cells, b.cells)
-    assert np.array_equal(a.weights, b.weights)
+    # the two kernel variants may contract multiply-adds differently: a few ulp
+    np.testing.assert_allclose(b.weights, a.weights, rtol=4e-7, atol=0)
 
 
 def test_termination_rejected_with_tape_and_batched():
