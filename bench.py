@@ -236,6 +236,10 @@ def main():
             result["array"] = array_leg(rt, sg, cfg, scene, eps, sig, out)
         except rt.RtError as e:
             result["array_error"] = str(e)
+        try:
+            result["refraction"] = refraction_leg(rt, sg, cfg, dev, out, args.launch)
+        except rt.RtError as e:
+            result["refraction_error"] = str(e)
     if not args.no_large:
         try:
             result["large"] = large_leg(rt, sg, dev, args)
@@ -452,6 +456,38 @@ def array_leg(rt, sg, cfg, scene, eps, sig, out, sizes=(1, 16, 64, 256, 1024)):
             st = int(stats[0])
         res["ms"][str(n)] = round(t, 3)
         res["M ray-bounces/s"][str(n)] = round(st / (t * 1e-3) / 1e6, 1)
+    return res
+
+
+def refraction_leg(rt, sg, cfg, dev, out, launch=""):
+    """Finite-thickness walls and refraction: the Manhattan workload (1e7 rays,
+    L = 5) with 20 cm concrete and 10 mm glass slabs, every hit sampling
+    reflection or transmission, against slab reflection only and the plain
+    half-space path on the same scene.  The buildings' bottom faces are left
+    out (they coincide with the ground, which transmitted rays could reach)."""
+    import torch
+    sc = sg.with_thickness(sg.manhattan_scene(bottoms=False))
+    scene = rt.scene_from_mesh(sc)
+    if launch:
+        rt.rt_set_launch_config(scene, *[int(x) for x in launch.split(",")])
+    else:
+        rt.rt_tune(scene, torch.tensor(sc.eps_r, dtype=torch.float32, device=dev),
+                   torch.tensor(sc.sigma, dtype=torch.float32, device=dev), cfg.tx, cfg.plane, cfg.params,
+                   2_000_000, out)
+    eps = torch.tensor(sc.eps_r, dtype=torch.float32, device=dev)
+    sig = torch.tensor(sc.sigma, dtype=torch.float32, device=dev)
+    thk = torch.tensor(sc.thickness, dtype=torch.float32, device=dev)
+    res = {"workload": "manhattan without building bottoms (%d triangles), 1e7 rays, L = 5, "
+                       "slabs: concrete 0.2 m, glass 0.01 m" % sc.n_triangles}
+    for name, p, t in (("refraction", sg.Params(cfg.params.freq_hz, cfg.params.n_rays, cfg.params.max_depth,
+                                                 refraction=1, seed=1), thk),
+                       ("slab_reflection", cfg.params, thk),
+                       ("half_space", cfg.params, None)):
+        stats = torch.zeros(8, dtype=torch.int64, device=dev)
+        rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, p, out, stats=stats, thickness=t)
+        seg = int(stats[0])
+        ms = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, p, out, thickness=t), 5, 1)
+        res[name] = {"ms": round(ms, 3), "segments": seg, "M ray-bounces/s": round(seg / (ms * 1e-3) / 1e6, 1)}
     return res
 
 
