@@ -77,7 +77,8 @@ def lib():
             L = C.CDLL(_LIB)
             L.or_radio_map.restype = C.c_int
             L.or_radio_map.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
-                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_Tx),
+                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.POINTER(_Tx),
                                        C.POINTER(_Plane), C.POINTER(_Params), C.c_void_p, C.c_int64,
                                        C.c_int64, C.c_int64, C.POINTER(_Out)]
             L.or_fresnel.restype = None
@@ -146,13 +147,16 @@ class OracleResult:
 
 
 def radio_map(scene, tx, plane, params, *, ray_ids=None, ray_begin=None, ray_end=None,
-              eps_r=None, sigma=None, thickness=None, want_hits=False, want_records=False, rec_cap=None,
+              eps_r=None, sigma=None, thickness=None, scattering=None, xpd=None, want_hits=False,
+              want_records=False, rec_cap=None,
               grad_map=None, replay_hits=None) -> OracleResult:
     """Run the oracle over a ray range (default: the params' range) or an explicit list.
 
     ``thickness`` (metres per material; default ``scene.thickness``, None =
     half-space walls) switches to the slab coefficients; ``params.refraction``
-    samples reflection or transmission at every hit and needs a thickness."""
+    samples reflection or transmission at every hit and needs a thickness.
+    ``scattering`` / ``xpd`` (S and K_x per material; default ``scene.scattering``
+    and ``scene.xpd``) enable Lambertian diffuse reflection."""
     L = lib()
     V = np.ascontiguousarray(scene.vertices, dtype=np.float32)
     F = np.ascontiguousarray(scene.triangles, dtype=np.int32)
@@ -162,6 +166,12 @@ def radio_map(scene, tx, plane, params, *, ray_ids=None, ray_begin=None, ray_end
     if thickness is None:
         thickness = getattr(scene, "thickness", None)
     thk = None if thickness is None else np.ascontiguousarray(thickness, dtype=np.float64)
+    if scattering is None:
+        scattering = getattr(scene, "scattering", None)
+    if xpd is None:
+        xpd = getattr(scene, "xpd", None)
+    sca = None if scattering is None else np.ascontiguousarray(scattering, dtype=np.float64)
+    xp = None if xpd is None else np.ascontiguousarray(xpd, dtype=np.float64)
     n_mat = int(eps.shape[0])
     npol = 2 if int(tx.pol) == 2 else 1
     Lmax = int(params.max_depth)
@@ -211,7 +221,7 @@ def radio_map(scene, tx, plane, params, *, ray_ids=None, ray_begin=None, ray_end
                   int(getattr(params, "refraction", 0)))
     txs, pls = _tx(tx), _plane(plane)
     rc = L.or_radio_map(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], M.ctypes.data, n_mat,
-                        eps.ctypes.data, sig.ctypes.data, _ptr(thk), C.byref(txs), C.byref(pls), C.byref(prm),
+                        eps.ctypes.data, sig.ctypes.data, _ptr(thk), _ptr(sca), _ptr(xp), C.byref(txs), C.byref(pls), C.byref(prm),
                         _ptr(ids), n_run if ids is not None else 0, b, e, C.byref(out))
     if rc != 0:
         raise ValueError("oracle rejected its arguments (code %d)" % rc)

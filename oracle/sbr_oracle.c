@@ -32,6 +32,14 @@
  *     divided by the square root of the probability (the Pr(chi)^-1 factor of
  *     the estimator); transmitted rays keep their direction (Sec.
  *     "Interactions with Scene Objects");
+ *   - optional diffuse reflection (Sec. "Definition of Radio Map",
+ *     App. "Diffuse Reflection"): a material with scattering coefficient
+ *     S > 0 scatters with probability q(S) of eq. path-solver-used-dist-event
+ *     into a direction drawn uniformly over the hemisphere of the incident
+ *     side (solid angle 2 pi), with the Lambertian pattern
+ *     (eq. lambertian_model), the reflected power ratio Gamma^2 and the
+ *     cross-polarisation matrix of eq. scattered_field with random phases;
+ *     the specular coefficients are multiplied by R = sqrt(1 - S^2) (eq. R);
  *   - an optional synthetic transmit array with a precoding vector
  *     (Sec. "Handling Multiple Transmit Antennas"): the launch field of a ray
  *     is multiplied by alpha = a_tx^T u_P of its departure direction;
@@ -60,7 +68,20 @@
  *     incident side (k_t = k_i gives e_t,par = e_i,par in
  *     eq. fresnel_out_vectors);
  *   - the interaction at the end of segment l of ray n reflects iff the
- *     uniform draw at Philox counter (n, l, 1) is below q(R);
+ *     uniform draw at Philox counter (n, l, 1) is below q(R), scatters
+ *     diffusely iff it is below q(R) + q(S), and is transmitted otherwise;
+ *     without refraction the transmission share is 0;
+ *   - a diffuse reflection takes its four draws from Philox counter (n, l, 2):
+ *     cos(theta_s) = u0, azimuth 2 pi u1 in the frame (t1, t2, n) with
+ *     t1 = (a x n)/|a x n|, a the coordinate axis least aligned with n, and
+ *     t2 = n x t1; the phases chi_1 = 2 pi u2, chi_2 = 2 pi u3.  The field
+ *     components refer to theta_hat and phi_hat of the incident and the
+ *     scattered direction (phi = 0 on the z axis).  With the change of
+ *     variables of eq. radio-map-solver-ci-all-2 the footprint dA, r^2 and
+ *     cos(theta_i) cancel, so the scattered distance-normalised field is the
+ *     incident one times sqrt(2 pi f_s S^2 Gamma^2 / q(S)) =
+ *     sqrt(2 cos(theta_s) S^2 Gamma^2 / q(S)), and the ray-tube length
+ *     starts again at 0 (gain thresholding uses the current tube);
  *   - c0 = 299792458 m/s, eps0 = 8.8541878128e-12 F/m, phi_g = (1+sqrt 5)/2;
  *   - the plane is two-sided and non-occluding; a segment contributes iff
  *     0 < t_plane < t_hit (t_hit = inf on a miss); cells are half-open;
@@ -92,7 +113,7 @@ typedef double complex cplx;
 #define OR_FLAG_NEAR 8u
 #define OR_FLAG_POLAR 16u
 #define OR_FLAG_TERM 32u     /* early-termination decision within 1e-5 of its threshold */
-#define OR_FLAG_CHOICE 64u   /* reflection/transmission draw within 1e-5 of q(R) */
+#define OR_FLAG_CHOICE 64u   /* interaction-type draw within 1e-5 of a class boundary */
 
 #define OR_MAX_PARAMS 64
 #define OR_MAX_DEPTH 64
@@ -242,6 +263,27 @@ static double rr_uniform(uint32_t seed, int64_t n, int l, uint32_t stream)
     uint32_t out[4];
     or_philox4x32(ctr, key, out);
     return (double)(out[0] >> 8) * (1.0 / 16777216.0);
+}
+
+/* The four uniforms of one Philox4x32-10 block at counter (n_lo, n_hi, l,
+ * stream), key (seed, 0), each from the top 24 bits of its word. */
+static void uniform4(uint32_t seed, int64_t n, int l, uint32_t stream, double u[4])
+{
+    uint32_t ctr[4] = {(uint32_t)((uint64_t)n & 0xffffffffu), (uint32_t)((uint64_t)n >> 32), (uint32_t)l, stream};
+    uint32_t key[2] = {seed, 0u};
+    uint32_t out[4];
+    or_philox4x32(ctr, key, out);
+    for (int i = 0; i < 4; i++) u[i] = (double)(out[i] >> 8) * (1.0 / 16777216.0);
+}
+
+/* theta_hat and phi_hat of direction k (eq. spherical_vecs); phi = 0 on the
+ * z axis. */
+static void sph_basis(vec3 k, vec3* th, vec3* ph)
+{
+    double rho = sqrt(k.x * k.x + k.y * k.y);
+    double cp = rho > 0.0 ? k.x / rho : 1.0, sp = rho > 0.0 ? k.y / rho : 0.0;
+    *th = mk(k.z * cp, k.z * sp, -rho);
+    *ph = mk(-sp, cp, 0.0);
 }
 
 /* ------------------------------------------------- synthetic transmit array */
@@ -447,6 +489,7 @@ static hit_info closest_hit(const or_mesh* m, vec3 o, vec3 k, int64_t last, doub
 int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                  const int32_t* tri_mat, int32_t n_mat,
                  const double* eps_r, const double* sigma, const double* thickness,
+                 const double* scattering, const double* xpd,
                  const or_tx* tx, const or_plane* pl, const or_params* prm,
                  const int64_t* ray_ids, int64_t n_ids, int64_t ray_begin, int64_t ray_end,
                  or_out* out)
@@ -459,6 +502,13 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
         for (int32_t i = 0; i < n_mat; i++)
             if (!(thickness[i] >= 0.0)) return 1;
         if (out->grad_map && out->grad) return 1;   /* no slab derivatives */
+    }
+    if (scattering) {
+        for (int32_t i = 0; i < n_mat; i++)
+            if (!(scattering[i] >= 0.0 && scattering[i] <= 1.0) || !(xpd && xpd[i] >= 0.0 && xpd[i] <= 1.0))
+                return 1;
+        if (tx->pol == 2) return 1;                 /* Gamma depends on the field */
+        if (out->grad_map && out->grad) return 1;
     }
     for (int64_t i = 0; i < n_tri; i++) {
         for (int j = 0; j < 3; j++)
@@ -508,7 +558,8 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
         }
         vec3 o = mk(tx->pos[0], tx->pos[1], tx->pos[2]);
         int64_t last = -1;
-        double run_len = 0.0;
+        double run_len = 0.0;   /* unfolded length from the source */
+        double tube_len = 0.0;  /* length of the current ray tube */
         int32_t* hrow = out->hits ? out->hits + r * (L + 1) : NULL;
         uint8_t* frow = out->flags ? out->flags + r * (L + 1) : NULL;
         if (hrow) for (int l = 0; l <= L; l++) hrow[l] = -2;
@@ -616,55 +667,100 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             kr = vunit(kr);
             vec3 er_par = vunit(vcross(e_perp, kr));
 
-            /* interaction type (eq. path-solver-used-dist-event with S = 0,
-             * R = 1, q(D) = 0): reflection with q(R) = (|r_perp|^2 +
-             * |r_par|^2) / (|r_perp|^2 + |r_par|^2 + |t_perp|^2 + |t_par|^2),
-             * else transmission; the field of the sampled branch is divided
-             * by sqrt(q) so that ||E||^2 carries the Pr(chi)^-1 factor of
-             * eq. radio-map-solver-ci-all-2-estimator */
-            int transmit = 0;
-            double inv_sqrt_q = 1.0;
-            if (prm->refraction) {
+            /* interaction type (eq. path-solver-used-dist-event with
+             * q(D) = 0): with A = |r_perp|^2 + |r_par|^2 and B = |t_perp|^2 +
+             * |t_par|^2 (0 without refraction), q(R) = R^2 A / (A + B),
+             * q(S) = S^2 A / (A + B), q(T) = B / (A + B); the field of the
+             * sampled branch is divided by sqrt(q) so that ||E||^2 carries the
+             * Pr(chi)^-1 factor of eq. radio-map-solver-ci-all-2-estimator */
+            const double Sm = scattering ? scattering[m] : 0.0;
+            int kind = 0;                             /* 0 reflect, 1 diffuse, 2 transmit */
+            double qk = 1.0;
+            if (prm->refraction || Sm > 0.0) {
                 double ar = creal(r_perp * conj(r_perp)) + creal(r_par * conj(r_par));
-                double at = creal(t_perp * conj(t_perp)) + creal(t_par * conj(t_par));
-                double qr = (ar + at > 0.0) ? ar / (ar + at) : 1.0;
+                double at = prm->refraction ? creal(t_perp * conj(t_perp)) + creal(t_par * conj(t_par)) : 0.0;
+                double fa = (ar + at > 0.0) ? ar / (ar + at) : 1.0;
+                double qr = (1.0 - Sm * Sm) * fa, qs = Sm * Sm * fa;
+                double qt = (ar + at > 0.0) ? at / (ar + at) : 0.0;
                 double u = rr_uniform(prm->seed, n, l, 1u);
-                if (frow && fabs(u - qr) <= 1e-5) frow[l] |= OR_FLAG_CHOICE;
-                transmit = !(u < qr);
-                inv_sqrt_q = 1.0 / sqrt(transmit ? 1.0 - qr : qr);
+                if (frow && (fabs(u - qr) <= 1e-5 || (Sm > 0.0 && fabs(u - (qr + qs)) <= 1e-5)))
+                    frow[l] |= OR_FLAG_CHOICE;
+                kind = u < qr ? 0 : (u < qr + qs ? 1 : 2);
+                qk = kind == 0 ? qr : (kind == 1 ? qs : qt);
             }
-            cplx c_perp = transmit ? t_perp : r_perp;
-            cplx c_par = transmit ? t_par : r_par;
-            vec3 out_par = transmit ? e_par : er_par;
+            const double inv_sqrt_q = 1.0 / sqrt(qk);
 
-            for (int p = 0; p < npol; p++) {
-                cplx a_perp = cv_dot_real(e_perp, E[p]);
-                cplx a_par = cv_dot_real(e_par, E[p]);
-                if (want_grad) {
-                    for (int q = 0; q < P; q++) {
-                        cplx b_perp = cv_dot_real(e_perp, dE[p][q]);
-                        cplx b_par = cv_dot_real(e_par, dE[p][q]);
-                        cvec3 nd = cv_zero();
-                        nd = cv_axpy(nd, r_perp * b_perp, e_perp);
-                        nd = cv_axpy(nd, r_par * b_par, er_par);
-                        cplx deta = 0.0;
-                        if (q == m) deta = 1.0;                   /* d eta / d eps_r[m] */
-                        else if (q == n_mat + m) deta = deta_dsigma; /* d eta / d sigma[m] */
-                        if (deta != 0.0) {
-                            nd = cv_axpy(nd, dr_perp * deta * a_perp, e_perp);
-                            nd = cv_axpy(nd, dr_par * deta * a_par, er_par);
-                        }
-                        dE[p][q] = nd;
-                    }
+            vec3 k_new = kr;
+            if (kind == 1) {
+                /* diffuse reflection: Lambertian direction over the
+                 * hemisphere of the incident side (n points there) */
+                double u4[4];
+                uniform4(prm->seed, n, l, 2u, u4);
+                double cs = u4[0], ss = sqrt(fmax(0.0, 1.0 - cs * cs));
+                double phs = 2.0 * OR_PI * u4[1];
+                double ax = fabs(nrm.x), ay = fabs(nrm.y), az = fabs(nrm.z);
+                vec3 a = (ax <= ay && ax <= az) ? mk(1, 0, 0) : (ay <= az ? mk(0, 1, 0) : mk(0, 0, 1));
+                vec3 t1 = vunit(vcross(a, nrm)), t2 = vcross(nrm, t1);
+                k_new = vunit(vadd(vadd(vscale(t1, ss * cos(phs)), vscale(t2, ss * sin(phs))), vscale(nrm, cs)));
+                vec3 thi, phi_i, ths, phs_v;
+                sph_basis(k, &thi, &phi_i);
+                sph_basis(k_new, &ths, &phs_v);
+                const double K = xpd[m];
+                const cplx e1 = cexp(I * (2.0 * OR_PI * u4[2])), e2 = cexp(I * (2.0 * OR_PI * u4[3]));
+                for (int p = 0; p < npol; p++) {
+                    cplx a_perp = cv_dot_real(e_perp, E[p]);
+                    cplx a_par = cv_dot_real(e_par, E[p]);
+                    double en2 = cv_norm2(E[p]);
+                    /* Gamma^2: reflected share of the incident power, with
+                     * the Fresnel (or slab) coefficients before R */
+                    double g2 = en2 > 0.0 ? (creal(r_perp * a_perp * conj(r_perp * a_perp)) +
+                                             creal(r_par * a_par * conj(r_par * a_par))) / en2 : 0.0;
+                    cplx eth = cv_dot_real(thi, E[p]), eph = cv_dot_real(phi_i, E[p]);
+                    cplx sth = e1 * (sqrt(1.0 - K) * eth - sqrt(K) * eph);
+                    cplx sph = e2 * (sqrt(K) * eth + sqrt(1.0 - K) * eph);
+                    double sc = sqrt(2.0 * cs * Sm * Sm * g2) * inv_sqrt_q;
+                    cvec3 En = cv_zero();
+                    En = cv_axpy(En, sc * sth, ths);
+                    En = cv_axpy(En, sc * sph, phs_v);
+                    E[p] = En;
                 }
-                cvec3 En = cv_zero();
-                En = cv_axpy(En, c_perp * a_perp * inv_sqrt_q, e_perp);
-                En = cv_axpy(En, c_par * a_par * inv_sqrt_q, out_par);
-                E[p] = En;
+            } else {
+                const double Rr = sqrt(1.0 - Sm * Sm);   /* eq. R: specular share */
+                cplx c_perp = kind == 2 ? t_perp : Rr * r_perp;
+                cplx c_par = kind == 2 ? t_par : Rr * r_par;
+                vec3 out_par = kind == 2 ? e_par : er_par;
+                if (kind == 2) k_new = k;
+
+                for (int p = 0; p < npol; p++) {
+                    cplx a_perp = cv_dot_real(e_perp, E[p]);
+                    cplx a_par = cv_dot_real(e_par, E[p]);
+                    if (want_grad) {
+                        for (int q = 0; q < P; q++) {
+                            cplx b_perp = cv_dot_real(e_perp, dE[p][q]);
+                            cplx b_par = cv_dot_real(e_par, dE[p][q]);
+                            cvec3 nd = cv_zero();
+                            nd = cv_axpy(nd, r_perp * b_perp, e_perp);
+                            nd = cv_axpy(nd, r_par * b_par, er_par);
+                            cplx deta = 0.0;
+                            if (q == m) deta = 1.0;                   /* d eta / d eps_r[m] */
+                            else if (q == n_mat + m) deta = deta_dsigma; /* d eta / d sigma[m] */
+                            if (deta != 0.0) {
+                                nd = cv_axpy(nd, dr_perp * deta * a_perp, e_perp);
+                                nd = cv_axpy(nd, dr_par * deta * a_par, er_par);
+                            }
+                            dE[p][q] = nd;
+                        }
+                    }
+                    cvec3 En = cv_zero();
+                    En = cv_axpy(En, c_perp * a_perp * inv_sqrt_q, e_perp);
+                    En = cv_axpy(En, c_par * a_par * inv_sqrt_q, out_par);
+                    E[p] = En;
+                }
             }
             o = vadd(o, vscale(k, h.t));
             run_len += h.t;
-            if (!transmit) k = kr;
+            tube_len = kind == 1 ? 0.0 : tube_len + h.t;
+            k = k_new;
             last = h.prim;
 
             /* Early termination before segment l + 1 (Sec. "Practical Notes",
@@ -678,9 +774,9 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             const int next = l + 1;
             if (next >= prm->rr_depth && (prm->gain_threshold > 0.0 || prm->rr_p_max > 0.0)) {
                 const double gn = cv_norm2(E[0]);
-                if (prm->gain_threshold > 0.0) {
+                if (prm->gain_threshold > 0.0 && tube_len > 0.0) {
                     const double thr = prm->gain_threshold;
-                    const double gain = lam * lam / (16.0 * OR_PI * OR_PI * run_len * run_len) * gn;
+                    const double gain = lam * lam / (16.0 * OR_PI * OR_PI * tube_len * tube_len) * gn;
                     if (frow && fabs(gain - thr) <= 1e-5 * thr) frow[next] |= OR_FLAG_TERM;
                     if (gain < thr) break;
                 }

@@ -38,6 +38,14 @@ METAL = (1.0, 1.0e7)
 THICKNESS = {CONCRETE: 0.2, GLASS: 0.01, METAL: 0.005}
 
 
+def with_diffuse(scene: "Scene", scattering, xpd=None) -> "Scene":
+    """Copy of ``scene`` with a scattering coefficient S (and a
+    cross-polarisation share K_x, default 0) per material."""
+    S = np.broadcast_to(np.asarray(scattering, dtype=np.float64), scene.eps_r.shape).copy()
+    K = np.zeros_like(S) if xpd is None else np.broadcast_to(np.asarray(xpd, dtype=np.float64), S.shape).copy()
+    return dataclasses.replace(scene, scattering=S, xpd=K)
+
+
 def with_thickness(scene: "Scene", thickness=None) -> "Scene":
     """Copy of ``scene`` with slab thickness per material (default THICKNESS
     looked up by (eps_r, sigma))."""
@@ -59,6 +67,8 @@ class Scene:
     sigma: np.ndarray             # float64 [n_mat], S/m
     name: str = ""
     thickness: Optional[np.ndarray] = None   # float64 [n_mat] slab thickness (m); None = half-space
+    scattering: Optional[np.ndarray] = None  # float64 [n_mat] scattering coefficient S; None = no diffuse
+    xpd: Optional[np.ndarray] = None         # float64 [n_mat] cross-polarisation share K_x
 
     @property
     def n_triangles(self) -> int:

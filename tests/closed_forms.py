@@ -180,3 +180,55 @@ def dirichlet_gain(n: int, spacing_wl: float, c, c0: float) -> np.ndarray:
     num = np.sin(n * x) ** 2
     small = np.abs(np.sin(x)) < 1e-12
     return np.where(small, float(n), num / np.where(small, 1.0, den))
+
+
+def lambertian_ground_map(tx_pos, plane, lam, eta_g, pol, half, ceiling=None, n_beta=48, n_psi=96, n_cell=2):
+    """Expected map of paths Tx -> Lambertian ground (S = 1) -> plane, or,
+    with ceiling = (z_c, eta_c, "par" | "perp"), Tx -> ground -> specular
+    ceiling -> plane, over a ground square |x|, |y| <= half at z = 0.
+
+    The gain per ground element dA at q seen from a plane point t is
+    (lambda/4 pi)^2 Gamma^2 (cos theta_s / pi) cos theta_i dA / (r0^2 d^2)
+    (App. "Diffuse Reflection", eq. scattered_field with the Lambertian
+    pattern); with dA cos theta_s / d^2 = d(omega) seen from t (or from its
+    image above the ceiling) the integral runs over directions:
+    (lambda/4 pi)^2 / pi * int Gamma^2 cos theta_i / r0^2 [|r_c|^2] d(omega).
+    Gamma^2 is |r_par|^2 (V-pol: the field lies in the plane of incidence)
+    or |r_perp|^2 (H-pol).  Directions: Gauss-Legendre in the polar angle up
+    to the square's edge, uniform in azimuth; cells: n_cell^2 points.
+    """
+    tx = np.asarray(tx_pos, dtype=np.float64)
+    g, gw = np.polynomial.legendre.leggauss(n_beta)
+    c, cw = np.polynomial.legendre.leggauss(n_cell)
+    psi = (np.arange(n_psi) + 0.5) * 2 * math.pi / n_psi
+    cp, sp = np.cos(psi), np.sin(psi)
+    out = np.zeros((plane.H, plane.W))
+    for j in range(plane.H):
+        for i in range(plane.W):
+            acc = 0.0
+            for a, wa in zip(c, cw):
+                for b, wb in zip(c, cw):
+                    tx_ = plane.x0 + (i + (a + 1) / 2) * plane.dx
+                    ty_ = plane.y0 + (j + (b + 1) / 2) * plane.dy
+                    hz = plane.z if ceiling is None else 2 * ceiling[0] - plane.z
+                    # distance along psi from (tx_, ty_) to the square's edge
+                    with np.errstate(divide="ignore"):
+                        rx = np.where(cp > 0, (half - tx_) / cp, np.where(cp < 0, (-half - tx_) / cp, np.inf))
+                        ry = np.where(sp > 0, (half - ty_) / sp, np.where(sp < 0, (-half - ty_) / sp, np.inf))
+                    bmax = np.arctan(np.minimum(rx, ry) / hz)                    # [n_psi]
+                    beta = (g[None, :] + 1) / 2 * bmax[:, None]                 # [n_psi][n_beta]
+                    wbeta = gw[None, :] / 2 * bmax[:, None]
+                    rho = hz * np.tan(beta)
+                    qx = tx_ + rho * cp[:, None]
+                    qy = ty_ + rho * sp[:, None]
+                    r0 = np.sqrt((qx - tx[0]) ** 2 + (qy - tx[1]) ** 2 + tx[2] ** 2)
+                    ci = tx[2] / r0
+                    rp, rl = fresnel_general(eta_g, ci)
+                    gam = np.abs(rl) ** 2 if pol == "V" else np.abs(rp) ** 2
+                    f = gam * ci / r0 ** 2
+                    if ceiling is not None:
+                        cp_, cl_ = fresnel_general(ceiling[1], np.cos(beta))
+                        f = f * (np.abs(cl_) ** 2 if ceiling[2] == "par" else np.abs(cp_) ** 2)
+                    acc += wa * wb / 4 * np.sum(f * np.sin(beta) * wbeta) * (2 * math.pi / n_psi)
+            out[j, i] = (lam / (4 * math.pi)) ** 2 / math.pi * acc
+    return out
