@@ -240,6 +240,10 @@ def main():
             result["refraction"] = refraction_leg(rt, sg, cfg, dev, out, args.launch)
         except rt.RtError as e:
             result["refraction_error"] = str(e)
+        try:
+            result["diffuse"] = diffuse_leg(rt, sg, cfg, scene, eps, sig, dev, out)
+        except rt.RtError as e:
+            result["diffuse_error"] = str(e)
     if not args.no_large:
         try:
             result["large"] = large_leg(rt, sg, dev, args)
@@ -489,6 +493,23 @@ def refraction_leg(rt, sg, cfg, dev, out, launch=""):
         ms = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, p, out, thickness=t), 5, 1)
         res[name] = {"ms": round(ms, 3), "segments": seg, "M ray-bounces/s": round(seg / (ms * 1e-3) / 1e6, 1)}
     return res
+
+
+def diffuse_leg(rt, sg, cfg, scene, eps, sig, dev, out):
+    """Diffuse reflection: the Manhattan workload (1e7 rays, L = 5) with
+    scattering coefficients S = 0.4 (concrete) and 0.2 (glass) and
+    cross-polarisation shares K_x = 0.1 and 0.3, Lambertian pattern; every
+    hit samples specular or diffuse reflection."""
+    import torch
+    sca = torch.tensor([0.4, 0.2], dtype=torch.float32, device=dev)
+    xpd = torch.tensor([0.1, 0.3], dtype=torch.float32, device=dev)
+    p = sg.Params(cfg.params.freq_hz, cfg.params.n_rays, cfg.params.max_depth, seed=1)
+    stats = torch.zeros(8, dtype=torch.int64, device=dev)
+    rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, p, out, stats=stats, scattering=sca, xpd=xpd)
+    seg = int(stats[0])
+    ms = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, p, out, scattering=sca, xpd=xpd), 5, 1)
+    return {"workload": "manhattan, 1e7 rays, L = 5, Lambertian S = 0.4 / 0.2, K_x = 0.1 / 0.3 (concrete / glass)",
+            "ms": round(ms, 3), "segments": seg, "M ray-bounces/s": round(seg / (ms * 1e-3) / 1e6, 1)}
 
 
 def _time(fn, reps=10, warm=2):

@@ -114,11 +114,32 @@ rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
  * The array is read by the kernels of the call and must stay valid until it
  * completes; a negative or non-finite entry gives undefined results.  Not
  * supported with a tape or by rt_radio_map_batched (RT_EUNSUPPORTED).
+ * scattering, xpd (optional, both or neither; NULL = no diffuse reflection):
+ * scattering coefficient S in [0, 1] and cross-polarisation share K_x in
+ * [0, 1] (eq. xpd) per material.  A hit on a material with S > 0 samples a
+ * diffuse reflection with probability q(S) = S^2 A / (A + B) (A the
+ * reflected and B the transmitted power share of the hit, B = 0 without
+ * refraction; eq. path-solver-used-dist-event), specular reflection with
+ * q(R) = (1 - S^2) A / (A + B) and coefficients times R = sqrt(1 - S^2)
+ * (eq. R).  The diffuse ray leaves the hit point in a direction drawn
+ * uniformly over the hemisphere of the incident side (polar cosine from
+ * word 0 and azimuth from word 1 of the Philox4x32-10 block at counter
+ * (ray index, l, 2), in the frame t1 = (a x n)/|a x n|, t2 = n x t1, a the
+ * coordinate axis least aligned with the normal n), with the Lambertian
+ * pattern (eq. lambertian_model): its field is the incident one in the
+ * theta/phi bases of the two directions, mixed by the matrix of
+ * eq. scattered_field with phases 2 pi times words 2 and 3, times
+ * sqrt(2 cos(theta_s) S^2 Gamma^2 / q(S)).  One polarisation per call
+ * (Gamma depends on the field): dual polarisation, a tape and
+ * rt_radio_map_batched give RT_EUNSUPPORTED.  Entries outside [0, 1] give
+ * undefined results.
  */
 typedef struct {
     const float* eps_r;
     const float* sigma;
     const float* thickness;
+    const float* scattering;
+    const float* xpd;
 } rt_materials;
 
 enum { RT_PATTERN_ISO = 0, RT_PATTERN_DIRECTIONAL = 1 };

@@ -335,6 +335,11 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
               "rt_radio_map: refraction needs the slab thickness of every material");
     if (tape && materials.thickness)
         return rt_fail(RT_EUNSUPPORTED, "rt_radio_map: slab walls and refraction cannot be recorded on a tape");
+    CHECK_ARG((materials.scattering == nullptr) == (materials.xpd == nullptr),
+              "rt_radio_map: scattering and xpd must both be given or both be NULL");
+    if (materials.scattering && (tape || tx->pol == RT_POL_DUAL))
+        return rt_fail(RT_EUNSUPPORTED,
+                       "rt_radio_map: diffuse reflection takes one polarisation and cannot be recorded on a tape");
     if ((r = check_device(scene)) != RT_OK) return r;
     FwdLaunch f{};
     f.scene = scene;
@@ -370,6 +375,8 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
     if (tape && (f.rr_p_max > 0.0f || f.gain_threshold > 0.0f))
         return rt_fail(RT_EUNSUPPORTED, "rt_radio_map: early termination cannot be recorded on a tape");
     f.thickness = materials.thickness;
+    f.scattering = materials.scattering;
+    f.xpd = materials.xpd;
     f.refraction = params->refraction;
     f.k0 = (float)(2.0 * RT_PI * params->freq_hz / RT_C0);
     if (records) {
@@ -433,8 +440,9 @@ extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials m
                                            float* grad_sigma, float* grad_orient, void* stream) {
     CHECK_ARG(scene != nullptr, "rt_radio_map_backward: scene is NULL");
     CHECK_ARG(tape != nullptr, "rt_radio_map_backward: tape is NULL");
-    if (materials.thickness || (params && params->refraction))
-        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_backward: slab walls and refraction have no adjoint here");
+    if (materials.thickness || materials.scattering || (params && params->refraction))
+        return rt_fail(RT_EUNSUPPORTED,
+                       "rt_radio_map_backward: slab walls, refraction and diffuse reflection have no adjoint here");
     CHECK_ARG(grad_map != nullptr, "rt_radio_map_backward: grad_map is NULL");
     CHECK_ARG(materials.eps_r && materials.sigma, "rt_radio_map_backward: material pointers are NULL");
     rt_status r;
@@ -492,8 +500,9 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     if ((r = check_params(&p, &b, &e)) != RT_OK) return r;
     if (p.rr_p_max > 0.0f || p.gain_threshold > 0.0f)
         return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: early termination is not supported here");
-    if (p.refraction || materials.thickness)
-        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: slab walls and refraction are not supported here");
+    if (p.refraction || materials.thickness || materials.scattering || materials.xpd)
+        return rt_fail(RT_EUNSUPPORTED,
+                       "rt_radio_map_batched: slab walls, refraction and diffuse reflection are not supported here");
     if ((r = check_device(scene)) != RT_OK) return r;
     rt_scene* s = const_cast<rt_scene*>(scene);
     hipStream_t hs = (hipStream_t)stream;

@@ -181,6 +181,8 @@ struct FwdLaunch {
     uint32_t seed;
     float gain_scale;        // lambda^2 / (16 pi^2)
     const float* thickness;  // slab thickness per material (m), or null (half-space)
+    const float* scattering; // scattering coefficient per material, or null (no diffuse)
+    const float* xpd;        // cross-polarisation share per material
     int32_t refraction;      // sample reflection or transmission at every hit
     float k0;                // 2 pi / lambda
 };

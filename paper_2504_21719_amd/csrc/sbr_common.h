@@ -418,6 +418,30 @@ __device__ __forceinline__ void slab(Fresnel& F, float k_d, cf& tperp, cf& tpar)
     F.rpar = cdiv(cmul(F.rpar, omx2), dl);
 }
 
+// theta_hat and phi_hat of direction k (eq. spherical_vecs); phi = 0 on the
+// z axis.
+__device__ __forceinline__ void sph_basis(float3 k, float3& th, float3& ph) {
+    const float rho = sqrtf(k.x * k.x + k.y * k.y);
+    float cp = 1.0f, sp = 0.0f;
+    if (rho > 0.0f) {
+        cp = k.x / rho;
+        sp = k.y / rho;
+    }
+    th = f3(k.z * cp, k.z * sp, -rho);
+    ph = f3(-sp, cp, 0.0f);
+}
+
+// Direction of polar cosine cs (sine ss) and azimuth (cph, sph) about the
+// unit normal n, in the frame t1 = (a x n)/|a x n|, t2 = n x t1 with a the
+// coordinate axis least aligned with n.
+__device__ __forceinline__ float3 diffuse_direction(float3 n, float cs, float ss, float cph, float sph) {
+    const float ax = fabsf(n.x), ay = fabsf(n.y), az = fabsf(n.z);
+    const float3 a = (ax <= ay && ax <= az) ? f3(1, 0, 0) : (ay <= az ? f3(0, 1, 0) : f3(0, 0, 1));
+    const float3 t1 = unit3(cross3(a, n));
+    const float3 t2 = cross3(n, t1);
+    return unit3(t1 * (ss * cph) + t2 * (ss * sph) + n * cs);
+}
+
 // Orthonormal TE direction e_perp = (k x n)/|k x n|; at normal incidence any
 // direction transverse to k: k x a with a the axis least aligned with k.
 __device__ __forceinline__ float3 te_direction(float3 k, float3 n) {

@@ -70,6 +70,8 @@ struct FwdArgs {
     float inv_kappa;               // 1 / tx.kappa: |alpha|^2 = kap * inv_kappa
     // finite-thickness walls and refraction (kernel variant EXT)
     const float* thickness;        // slab thickness per material (m), or null
+    const float* scattering;       // scattering coefficient S per material, or null (no diffuse)
+    const float* xpd;              // cross-polarisation share K_x per material
     int refraction;                // 1: sample reflection or transmission at every hit
     float k0;                      // 2 pi / lambda
     int* spill;
@@ -128,11 +130,11 @@ __device__ __forceinline__ float wave_sum(float v) {
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011), written from its
 // definition: ten rounds, each multiplying words 0 and 2 by two odd constants,
 // keeping the low halves and XORing the high halves with words 1, 3 and the
-// round key, which advances by two Weyl constants.  Uniform in [0, 1) from
-// the top 24 bits of word 0 at counter (n_lo, n_hi, l, stream), key
-// (seed, 0); stream 0 decides early termination before segment l, stream 1
-// the interaction type at the end of segment l.
-__device__ __forceinline__ float philox_uniform(unsigned seed, int64_t n, int l, unsigned stream) {
+// round key, which advances by two Weyl constants.  Counter (n_lo, n_hi, l,
+// stream), key (seed, 0); stream 0 decides early termination before segment
+// l, stream 1 the interaction type at the end of segment l, stream 2 the
+// direction and phases of a diffuse reflection there.
+__device__ __forceinline__ uint4 philox4(unsigned seed, int64_t n, int l, unsigned stream) {
     unsigned c0 = (unsigned)((uint64_t)n & 0xffffffffu), c1 = (unsigned)((uint64_t)n >> 32), c2 = (unsigned)l,
              c3 = stream;
     unsigned k0 = seed, k1 = 0u;
@@ -147,7 +149,14 @@ __device__ __forceinline__ float philox_uniform(unsigned seed, int64_t n, int l,
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
-    return (float)(c0 >> 8) * (1.0f / 16777216.0f);
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// Uniform in [0, 1) from the top 24 bits of a word (exact in FP32).
+__device__ __forceinline__ float word_uniform(unsigned w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
+
+__device__ __forceinline__ float philox_uniform(unsigned seed, int64_t n, int l, unsigned stream) {
+    return word_uniform(philox4(seed, n, l, stream).x);
 }
 
 // Per-lane traversal stack: the first RT_STACK_LDS entries {node, entry
@@ -558,57 +567,113 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                 float4 nm = a.normals[slot];
                 int mat = __float_as_int(nm.w);
                 Bounce b = bounce_geometry(k, es, f3(nm.x, nm.y, nm.z));
-                bool transmit = false;
+                int kind = 0;          // 0 specular reflection, 1 diffuse reflection, 2 transmission
+                float3 knew = b.kr, esnew = b.es_new;
                 if (MODE != MODE_GEOM) {
                     cf eta = cf{a.eps_r[mat], -a.sigma[mat] * a.pl.inv_eps0_omega};
                     Fresnel F = fresnel<false>(b.c, eta);
                     cf cperp = F.rperp, cpar = F.rpar;
-                    if (EXT && a.thickness) {
+                    float qs = 1.0f, s2 = 0.0f;
+                    if (EXT) {
                         // single-layer slab: r and t from r' and x = exp(-j q)
-                        cf tperp, tpar;
-                        slab(F, a.k0 * a.thickness[mat], tperp, tpar);
+                        cf tperp = cf{0.0f, 0.0f}, tpar = cf{0.0f, 0.0f};
+                        if (a.thickness) slab(F, a.k0 * a.thickness[mat], tperp, tpar);
                         cperp = F.rperp;
                         cpar = F.rpar;
-                        if (a.refraction) {
-                            // reflect with q(R), else transmit with q(T); the
-                            // sampled branch carries 1/sqrt(q)
+                        const float Sm = a.scattering ? a.scattering[mat] : 0.0f;
+                        if (a.refraction || Sm > 0.0f) {
+                            // interaction shares with A = |r|^2, B = |t|^2 (0
+                            // without refraction): q(R) = R^2 A/(A+B),
+                            // q(S) = S^2 A/(A+B), q(T) = B/(A+B); the sampled
+                            // branch carries 1/sqrt(q)
                             const float ar = cabs2(F.rperp) + cabs2(F.rpar);
-                            const float at = cabs2(tperp) + cabs2(tpar);
+                            const float at = a.refraction ? cabs2(tperp) + cabs2(tpar) : 0.0f;
                             const float tot = ar + at;
-                            const float qr = tot > 0.0f ? ar / tot : 1.0f;
-                            transmit = !(philox_uniform(a.seed, a.ray_begin + rid, l, 1u) < qr);
-                            const float sc = __builtin_amdgcn_rsqf(transmit ? at / tot : qr);
-                            cperp = cscale(transmit ? tperp : F.rperp, sc);
-                            cpar = cscale(transmit ? tpar : F.rpar, sc);
+                            const float fa = tot > 0.0f ? ar / tot : 1.0f;
+                            s2 = Sm * Sm;
+                            const float qr = (1.0f - s2) * fa;
+                            qs = s2 * fa;
+                            const float u = philox_uniform(a.seed, a.ray_begin + rid, l, 1u);
+                            kind = u < qr ? 0 : (u < qr + qs ? 1 : 2);
+                            if (kind != 1) {
+                                const float q = kind == 0 ? qr : (tot > 0.0f ? at / tot : 0.0f);
+                                // specular share R = sqrt(1 - S^2) (eq. R)
+                                const float sc = __builtin_amdgcn_rsqf(q) * (kind == 0 ? sqrtf(1.0f - s2) : 1.0f);
+                                cperp = cscale(kind == 2 ? tperp : F.rperp, sc);
+                                cpar = cscale(kind == 2 ? tpar : F.rpar, sc);
+                                if (kind == 2) knew = k;
+                            }
                         }
                     }
-                    // T <- diag(c_perp, -c_par) W T: the new basis is (e_perp,
-                    // k' x e_perp), whose second vector is -e_par of the
-                    // outgoing wave for both k' = k_r and k' = k
-                    cf na = cadd(cscale(Ta, b.w00), cscale(Tc, b.w01));
-                    cf nb = cadd(cscale(Tb, b.w00), cscale(Td, b.w01));
-                    cf nc = cadd(cscale(Ta, b.w10), cscale(Tc, b.w11));
-                    cf nd = cadd(cscale(Tb, b.w10), cscale(Td, b.w11));
-                    Ta = cmul(cperp, na);
-                    Tb = cmul(cperp, nb);
-                    cf mr = cf{-cpar.re, -cpar.im};
-                    Tc = cmul(mr, nc);
-                    Td = cmul(mr, nd);
+                    if (EXT && kind == 1) {
+                        // diffuse reflection (Lambertian): direction drawn over
+                        // the hemisphere of the incident side, field scaled by
+                        // sqrt(2 cos(theta_s) S^2 Gamma^2 / q(S)) and mixed by
+                        // the cross-polarisation matrix with random phases, in
+                        // the theta/phi bases of the incident and new direction
+                        const cf e0 = cadd(cscale(Ta, c0t), cscale(Tb, c0p));
+                        const cf e1 = cadd(cscale(Tc, c0t), cscale(Td, c0p));
+                        const cf ap = cadd(cscale(e0, b.w00), cscale(e1, b.w01));
+                        const cf al = cadd(cscale(e0, b.w10), cscale(e1, b.w11));
+                        const float en2 = cabs2(e0) + cabs2(e1);
+                        const float g2 = en2 > 0.0f ? (cabs2(cmul(F.rperp, ap)) + cabs2(cmul(F.rpar, al))) / en2 : 0.0f;
+                        const uint4 w = philox4(a.seed, a.ray_begin + rid, l, 2u);
+                        const float cs = word_uniform(w.x), ss = sqrtf(fmaxf(0.0f, 1.0f - cs * cs));
+                        float sph, cph, s1, c1, s2p, c2p;
+                        sincospif(2.0f * word_uniform(w.y), &sph, &cph);
+                        sincospif(2.0f * word_uniform(w.z), &s1, &c1);
+                        sincospif(2.0f * word_uniform(w.w), &s2p, &c2p);
+                        float3 n = f3(nm.x, nm.y, nm.z);
+                        if (dot3(k, n) > 0.0f) n = n * -1.0f;
+                        knew = diffuse_direction(n, cs, ss, cph, sph);
+                        float3 thi, phi_i, phs;
+                        sph_basis(k, thi, phi_i);
+                        sph_basis(knew, esnew, phs);
+                        const float3 ep = cross3(k, es);
+                        const float p00 = dot3(thi, es), p01 = dot3(thi, ep);
+                        const float p10 = dot3(phi_i, es), p11 = dot3(phi_i, ep);
+                        const float K = a.xpd[mat], sk = sqrtf(K), ck = sqrtf(1.0f - K);
+                        const float sc = sqrtf(2.0f * cs * s2 * g2) * __builtin_amdgcn_rsqf(qs);
+                        const float a0 = ck * p00 - sk * p10, a1 = ck * p01 - sk * p11;   // theta row
+                        const float b0 = sk * p00 + ck * p10, b1 = sk * p01 + ck * p11;   // phi row
+                        const cf x1 = cf{c1 * sc, s1 * sc}, x2 = cf{c2p * sc, s2p * sc};
+                        const cf na = cmul(x1, cadd(cscale(Ta, a0), cscale(Tc, a1)));
+                        const cf nb = cmul(x1, cadd(cscale(Tb, a0), cscale(Td, a1)));
+                        const cf nc = cmul(x2, cadd(cscale(Ta, b0), cscale(Tc, b1)));
+                        const cf nd = cmul(x2, cadd(cscale(Tb, b0), cscale(Td, b1)));
+                        Ta = na;
+                        Tb = nb;
+                        Tc = nc;
+                        Td = nd;
+                    } else {
+                        // T <- diag(c_perp, -c_par) W T: the new basis is
+                        // (e_perp, k' x e_perp), whose second vector is -e_par
+                        // of the outgoing wave for both k' = k_r and k' = k
+                        cf na = cadd(cscale(Ta, b.w00), cscale(Tc, b.w01));
+                        cf nb = cadd(cscale(Tb, b.w00), cscale(Td, b.w01));
+                        cf nc = cadd(cscale(Ta, b.w10), cscale(Tc, b.w11));
+                        cf nd = cadd(cscale(Tb, b.w10), cscale(Td, b.w11));
+                        Ta = cmul(cperp, na);
+                        Tb = cmul(cperp, nb);
+                        cf mr = cf{-cpar.re, -cpar.im};
+                        Tc = cmul(mr, nc);
+                        Td = cmul(mr, nd);
+                    }
                 }
                 o = o + k * t_hit;
-                if (!transmit) k = b.kr;
-                es = b.es_new;
+                k = knew;
+                es = esnew;
                 last = slot;
                 l++;
+                if (EXT) rlen = kind == 1 ? 0.0f : rlen + t_hit;   // a diffuse point starts a new tube
                 if (EXT && l >= a.rr_depth && (a.rr_p_max > 0.0f || a.gain_threshold > 0.0f)) {
                     // early termination before segment l: the distance-normalised
                     // gain ||T C||^2 of polarisation 0 (times |alpha|^2)
-                    rlen += t_hit;
                     const cf e0 = cadd(cscale(Ta, c0t), cscale(Tb, c0p));
                     const cf e1 = cadd(cscale(Tc, c0t), cscale(Td, c0p));
                     const float gn = (cabs2(e0) + cabs2(e1)) * (kap * a.inv_kappa);
                     bool drop = false;
-                    if (a.gain_threshold > 0.0f)
+                    if (a.gain_threshold > 0.0f && rlen > 0.0f)
                         drop = a.gain_scale * gn * __builtin_amdgcn_rcpf(rlen * rlen) < a.gain_threshold;
                     if (!drop && a.rr_p_max > 0.0f) {
                         const float p = fminf(gn, a.rr_p_max);
@@ -623,8 +688,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                         }
                     }
                     if (drop) active = false;
-                } else if (EXT) {
-                    rlen += t_hit;
                 }
             }
         }
@@ -795,9 +858,11 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
     a.gain_scale = f.gain_scale;
     a.inv_kappa = 1.0f / f.tx.kappa;
     a.thickness = f.thickness;
+    a.scattering = f.scattering;
+    a.xpd = f.xpd;
     a.refraction = f.refraction;
     a.k0 = f.k0;
-    const bool ext = f.rr_p_max > 0.0f || f.gain_threshold > 0.0f || f.thickness != nullptr;
+    const bool ext = f.rr_p_max > 0.0f || f.gain_threshold > 0.0f || f.thickness != nullptr || f.scattering != nullptr;
     if (a.n_work > 0) launch_mode<MODE_SINGLE>(a, f.accel, use_wide(s, f.accel), blocks, f.block, st, ext);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rt_hip_fail(e, "forward launch");

@@ -69,13 +69,15 @@ def test_refraction_with_roulette():
 
 def test_refraction_brute_force_matches_bvh():
     """The brute-force and tree kernels share the interaction code: identical
-    hits, cells and weights."""
+    hits and cells, weights to rounding."""
     cfg = _tiny(seed=3)
     s = gpu_scene(cfg.scene)
     a = gpu_radio_map(cfg, scene_handle=s)
     b = gpu_radio_map(cfg, scene_handle=s, accel=1)
     assert np.array_equal(a.hits, b.hits) and np.array_equal(a.cells, b.cells)
-    assert np.array_equal(a.weights, b.weights)
+    # the two kernels contract multiply-adds independently: ulp-level
+    # differences, amplified at most 20x by the slab formula
+    np.testing.assert_allclose(b.weights, a.weights, rtol=5e-6, atol=0)
 
 
 def test_refraction_rejections():
