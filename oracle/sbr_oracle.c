@@ -322,6 +322,22 @@ static void slab(cplx s, double k_d, cplx* r_perp, cplx* r_par, cplx* t_perp, cp
     *r_par = *r_par * (1.0 - x2) / (1.0 - rl2 * x2);
 }
 
+/* Derivatives of the slab coefficients of one polarisation with respect to
+ * eta, by the quotient and chain rules: r = r' (1 - x^2) / D and
+ * t = (1 - r'^2) x / D with D = 1 - r'^2 x^2, x = exp(-j k_d s),
+ * dx/d(eta) = -j k_d x / (2 s), and dr'/d(eta) = dr1 of the half-space
+ * coefficient r1. */
+static void slab_deriv(cplx s, double k_d, cplx r1, cplx dr1, cplx* dr, cplx* dt)
+{
+    cplx x = cexp(-I * (k_d * s)), x2 = x * x;
+    cplx dx = -I * k_d * x / (2.0 * s);
+    cplx D = 1.0 - r1 * r1 * x2;
+    cplx dD = -(2.0 * r1 * dr1 * x2 + 2.0 * r1 * r1 * x * dx);
+    cplx r = r1 * (1.0 - x2) / D, t = (1.0 - r1 * r1) * x / D;
+    *dr = (dr1 * (1.0 - x2) - 2.0 * r1 * x * dx - r * dD) / D;
+    *dt = (-2.0 * r1 * dr1 * x + (1.0 - r1 * r1) * dx - t * dD) / D;
+}
+
 /* ------------------------------------------------------ lattice and launch */
 /* Spherical Fibonacci lattice (Sec. "Sampling Initial Ray Directions"). */
 void or_fibonacci(int64_t n, int64_t N, double* theta, double* phi)
@@ -501,7 +517,6 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
     if (thickness) {
         for (int32_t i = 0; i < n_mat; i++)
             if (!(thickness[i] >= 0.0)) return 1;
-        if (out->grad_map && out->grad) return 1;   /* no slab derivatives */
     }
     if (scattering) {
         for (int32_t i = 0; i < n_mat; i++)
@@ -650,8 +665,16 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             cplx dr_perp = ((-ds) * den_p - (c - s) * ds) / (den_p * den_p);
             cplx dr_par = ((c - ds) * den_l - (eta * c - s) * (c + ds)) / (den_l * den_l);
 
-            cplx t_perp = 0.0, t_par = 0.0;
-            if (thickness) slab(s, 2.0 * OR_PI * thickness[m] / lam, &r_perp, &r_par, &t_perp, &t_par);
+            cplx t_perp = 0.0, t_par = 0.0, dt_perp = 0.0, dt_par = 0.0;
+            if (thickness) {
+                const double k_d = 2.0 * OR_PI * thickness[m] / lam;
+                cplx dsp, dsl;
+                slab_deriv(s, k_d, r_perp, dr_perp, &dsp, &dt_perp);
+                slab_deriv(s, k_d, r_par, dr_par, &dsl, &dt_par);
+                dr_perp = dsp;
+                dr_par = dsl;
+                slab(s, k_d, &r_perp, &r_par, &t_perp, &t_par);
+            }
 
             vec3 kn = vcross(k, nrm);
             vec3 e_perp;
@@ -728,6 +751,10 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                 const double Rr = sqrt(1.0 - Sm * Sm);   /* eq. R: specular share */
                 cplx c_perp = kind == 2 ? t_perp : Rr * r_perp;
                 cplx c_par = kind == 2 ? t_par : Rr * r_par;
+                /* derivatives w.r.t. eta; the sampling probability q is held
+                 * constant (its draw decides the branch, not the value) */
+                cplx dc_perp = (kind == 2 ? dt_perp : Rr * dr_perp) * inv_sqrt_q;
+                cplx dc_par = (kind == 2 ? dt_par : Rr * dr_par) * inv_sqrt_q;
                 vec3 out_par = kind == 2 ? e_par : er_par;
                 if (kind == 2) k_new = k;
 
@@ -739,14 +766,14 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                             cplx b_perp = cv_dot_real(e_perp, dE[p][q]);
                             cplx b_par = cv_dot_real(e_par, dE[p][q]);
                             cvec3 nd = cv_zero();
-                            nd = cv_axpy(nd, r_perp * b_perp, e_perp);
-                            nd = cv_axpy(nd, r_par * b_par, er_par);
+                            nd = cv_axpy(nd, c_perp * inv_sqrt_q * b_perp, e_perp);
+                            nd = cv_axpy(nd, c_par * inv_sqrt_q * b_par, out_par);
                             cplx deta = 0.0;
                             if (q == m) deta = 1.0;                   /* d eta / d eps_r[m] */
                             else if (q == n_mat + m) deta = deta_dsigma; /* d eta / d sigma[m] */
                             if (deta != 0.0) {
-                                nd = cv_axpy(nd, dr_perp * deta * a_perp, e_perp);
-                                nd = cv_axpy(nd, dr_par * deta * a_par, er_par);
+                                nd = cv_axpy(nd, dc_perp * deta * a_perp, e_perp);
+                                nd = cv_axpy(nd, dc_par * deta * a_par, out_par);
                             }
                             dE[p][q] = nd;
                         }

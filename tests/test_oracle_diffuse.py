@@ -130,6 +130,9 @@ def test_diffuse_inputs_validated(oracle_lib):
     for S, K in ((1.5, 0.0), (0.5, -0.1), (0.5, 2.0)):
         with pytest.raises(ValueError):
             oracle_lib.radio_map(sg.with_diffuse(cfg.scene, S, K), cfg.tx, cfg.plane, cfg.params)
+    with pytest.raises(ValueError):          # no adjoint of the diffuse bounce
+        oracle_lib.radio_map(sg.with_diffuse(cfg.scene, 0.5), cfg.tx, cfg.plane, cfg.params,
+                             grad_map=np.ones((1, cfg.plane.H, cfg.plane.W)))
     with pytest.raises(ValueError):          # Gamma depends on the field: one polarisation only
         oracle_lib.radio_map(sg.with_diffuse(cfg.scene, 0.5), sg.Tx((0.0, 0.0, 10.0), pol=sg.POL_DUAL),
                              cfg.plane, cfg.params)

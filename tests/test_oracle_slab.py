@@ -84,9 +84,6 @@ def test_refraction_needs_a_thickness(oracle_lib):
     cfg.params.refraction = 1
     with pytest.raises(ValueError):
         oracle_lib.radio_map(cfg.scene, cfg.tx, cfg.plane, cfg.params)
-    sc = sg.with_thickness(cfg.scene)
-    with pytest.raises(ValueError):          # no slab derivatives
-        oracle_lib.radio_map(sc, cfg.tx, cfg.plane, cfg.params, grad_map=np.ones((1, cfg.plane.H, cfg.plane.W)))
 
 
 def test_transparent_ground_is_free_space(oracle_lib):
@@ -176,3 +173,43 @@ def test_transparent_wall_keeps_the_field(oracle_lib):
     through = (b.hits[:, :2] >= 2).any(1)                 # triangles 2, 3 are the wall
     assert through.sum() > 10_000
     np.testing.assert_allclose(b.map, a.map, rtol=1e-12, atol=0)
+
+
+def _dlog_gain_dsigma(coef, eps, sig, cos_t, d, h=1e-6):
+    """d ln|c|^2 / d sigma of a characteristic-matrix coefficient by central
+    differences (c = 0 r_s, 2 t_s)."""
+    up = cf.slab_characteristic(cf.eta(eps, sig + h, FREQ), cos_t, d, LAM)[coef]
+    dn = cf.slab_characteristic(cf.eta(eps, sig - h, FREQ), cos_t, d, LAM)[coef]
+    c0 = cf.slab_characteristic(cf.eta(eps, sig, FREQ), cos_t, d, LAM)[coef]
+    return (np.abs(up) ** 2 - np.abs(dn) ** 2) / (2 * h * np.abs(c0) ** 2)
+
+
+@pytest.mark.parametrize("case", ["reflect", "transmit"])
+def test_detached_slab_gradient(oracle_lib, case):
+    """H-pol over a horizontal glass slab is pure TE: a crossing after one
+    interaction weighs w = kappa |c_perp|^2 / (q |k_z|), so with the sampling
+    probability held constant dw/d sigma = w d ln|c_perp|^2 / d sigma.  The
+    oracle's forward-mode gradient of the map sum must equal the sum of
+    these over the crossings, with the derivative taken from the layer
+    matrix by central differences (reflect: a glass ground seen from above;
+    transmit: a pane between the source and the plane)."""
+    tx = sg.Tx((0.0, 0.0, 10.0), pol=sg.POL_H)
+    N = 200_000
+    if case == "reflect":
+        sc = sg.with_thickness(sg.ground_quad(100.0, sg.GLASS))
+        pl = sg.Plane(1.5, -40.0, -40.0, 2.0, 2.0, 40, 40)
+    else:
+        mb = sg._MeshBuilder()
+        mb.quad((-40.0, -40.0, 5.0), (40.0, -40.0, 5.0), (40.0, 40.0, 5.0), (-40.0, 40.0, 5.0), 0)
+        sc = sg.with_thickness(mb.build([sg.GLASS], "pane"))
+        pl = sg.Plane(1.5, -20.0, -20.0, 2.0, 2.0, 20, 20)
+    G = np.ones((1, pl.H, pl.W))
+    r = oracle_lib.radio_map(sc, tx, pl, sg.Params(FREQ, N, 1, refraction=1, seed=3), want_records=True,
+                             grad_map=G)
+    sel = r.records["depth"] == 1
+    rays = r.records["ray"][sel]
+    assert rays.size > 1000
+    kz = np.abs(np.array([oracle_lib.lattice(n, N)[2] for n in rays]))
+    dl = _dlog_gain_dsigma(0 if case == "reflect" else 2, *sg.GLASS, kz, 0.01)
+    expect = np.sum(r.records["w"][sel] * dl)
+    assert r.grad[1] == pytest.approx(expect, rel=2e-5), (r.grad[1], expect)
