@@ -112,8 +112,10 @@ rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
  * coefficients of eq. fresnel_slab with eq. q_fresnel_slab (Sec.
  * "Single-Layer Slab") instead of the half-space ones of eq. fresnel_vac.
  * The array is read by the kernels of the call and must stay valid until it
- * completes; a negative or non-finite entry gives undefined results.  Not
- * supported with a tape or by rt_radio_map_batched (RT_EUNSUPPORTED).
+ * completes; a negative or non-finite entry gives undefined results.  A tape
+ * and rt_radio_map_backward take it (the backward needs the same array; the
+ * sampling probabilities of refraction are held constant in the gradient);
+ * rt_radio_map_batched does not (RT_EUNSUPPORTED).
  * scattering, xpd (optional, both or neither; NULL = no diffuse reflection):
  * scattering coefficient S in [0, 1] and cross-polarisation share K_x in
  * [0, 1] (eq. xpd) per material.  A hit on a material with S > 0 samples a
@@ -248,8 +250,9 @@ typedef struct {
      * sampled branch is divided by sqrt(q), the Pr(chi)^-1 factor of the
      * estimator.  A transmitted ray keeps its direction (Sec. "Interactions
      * with Scene Objects") and its TE/TM basis.  Needs materials.thickness
-     * (RT_EINVAL otherwise); not available with a tape or in
-     * rt_radio_map_batched (RT_EUNSUPPORTED). */
+     * (RT_EINVAL otherwise).  A tape records the sampled branches; the
+     * adjoint differentiates the sampled coefficients with q held constant.
+     * Not available in rt_radio_map_batched (RT_EUNSUPPORTED). */
     int32_t refraction;
 } rt_sbr_params;
 
@@ -313,9 +316,13 @@ rt_status rt_tape_destroy(rt_tape* tape);
  * filled by the rt_radio_map call with the same scene, materials, tx, plane
  * and params; it traces nothing.  Derivatives follow eq. fresnel_vac,
  * eq. eta (d eta/d eps_r = 1, d eta/d sigma = -j/(eps0 omega)) and
- * eq. rotation.  Partial sums are reduced in a fixed order, so results are
- * run-to-run deterministic.
- * Errors: RT_EINVAL if the tape was not filled by a matching forward call.
+ * eq. rotation; with slab walls, eq. fresnel_slab (quotient and chain rules
+ * through x = exp(-j q)); with refraction, the sampled branch (a transmitted
+ * segment keeps its direction) with its probability held constant.  Partial
+ * sums are reduced in a fixed order, so results are run-to-run
+ * deterministic.
+ * Errors: RT_EINVAL if the tape was not filled by a matching forward call;
+ * RT_EUNSUPPORTED with diffuse reflection.
  */
 rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials materials,
                                 const rt_tx* tx, const rt_plane* plane,

@@ -258,6 +258,9 @@ static uint64_t call_key(const rt_scene* s, rt_materials m, const rt_tx* tx, con
     h = mix(h, &s, sizeof(s));
     h = mix(h, &m.eps_r, sizeof(m.eps_r));
     h = mix(h, &m.sigma, sizeof(m.sigma));
+    h = mix(h, &m.thickness, sizeof(m.thickness));
+    h = mix(h, &p->refraction, sizeof(int32_t));
+    h = mix(h, &p->seed, sizeof(uint32_t));
     h = mix(h, tx, sizeof(rt_tx));
     h = mix(h, pl, sizeof(rt_plane));
     h = mix(h, &p->freq_hz, sizeof(double));
@@ -333,8 +336,6 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
     }
     CHECK_ARG(!params->refraction || materials.thickness,
               "rt_radio_map: refraction needs the slab thickness of every material");
-    if (tape && materials.thickness)
-        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map: slab walls and refraction cannot be recorded on a tape");
     CHECK_ARG((materials.scattering == nullptr) == (materials.xpd == nullptr),
               "rt_radio_map: scattering and xpd must both be given or both be NULL");
     if (materials.scattering && (tape || tx->pol == RT_POL_DUAL))
@@ -440,9 +441,8 @@ extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials m
                                            float* grad_sigma, float* grad_orient, void* stream) {
     CHECK_ARG(scene != nullptr, "rt_radio_map_backward: scene is NULL");
     CHECK_ARG(tape != nullptr, "rt_radio_map_backward: tape is NULL");
-    if (materials.thickness || materials.scattering || (params && params->refraction))
-        return rt_fail(RT_EUNSUPPORTED,
-                       "rt_radio_map_backward: slab walls, refraction and diffuse reflection have no adjoint here");
+    if (materials.scattering)
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_backward: diffuse reflection has no adjoint here");
     CHECK_ARG(grad_map != nullptr, "rt_radio_map_backward: grad_map is NULL");
     CHECK_ARG(materials.eps_r && materials.sigma, "rt_radio_map_backward: material pointers are NULL");
     rt_status r;
@@ -467,6 +467,9 @@ extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials m
     bl.grad_eps = grad_eps_r;
     bl.grad_sigma = grad_sigma;
     bl.grad_orient = grad_orient;
+    bl.thickness = materials.thickness;
+    bl.refraction = params->refraction;
+    bl.k0 = (float)(2.0 * RT_PI * params->freq_hz / RT_C0);
     return rt_launch_backward(bl, (hipStream_t)stream);
 }
 

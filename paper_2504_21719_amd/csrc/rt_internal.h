@@ -201,6 +201,9 @@ struct BwdLaunch {
     float* grad_eps;
     float* grad_sigma;
     float* grad_orient;
+    const float* thickness;  // slab thickness per material (m), or null
+    int32_t refraction;
+    float k0;                // 2 pi / lambda
 };
 rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st);
 

@@ -60,6 +60,9 @@ struct BwdArgs {
     int P;                // parameters written by this launch into partials
     double* partials;     // [gridDim.x][P]
     int write_orient;     // 1: this chunk also produces the orientation terms
+    const float* thickness;  // slab thickness per material (m), or null
+    int refraction;          // 1: the forward sampled reflection or transmission
+    float k0;                // 2 pi / lambda
 };
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -116,6 +119,30 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 Bounce b = bounce_geometry(f3(p0.x, p0.y, p0.z), f3(p1.x, p1.y, p1.z), f3(nm.x, nm.y, nm.z));
                 cf eta = cf{a.eps_r[mat], -a.sigma[mat] * a.pl.inv_eps0_omega};
                 Fresnel F = fresnel<true>(b.c, eta);
+                // coefficient of the interaction and its eta-derivative: the
+                // slab r (or t for a transmitted ray, whose direction did not
+                // change) divided by sqrt(q), the sampling probability held
+                // constant
+                cf kpe = F.rperp, kpa = F.rpar, dkpe = F.drperp, dkpa = F.drpar;
+                if (a.thickness) {
+                    cf tp, tl, dtp, dtl;
+                    slab_grad(F, a.k0 * a.thickness[mat], tp, tl, dtp, dtl);
+                    kpe = F.rperp;
+                    kpa = F.rpar;
+                    dkpe = F.drperp;
+                    dkpa = F.drpar;
+                    if (a.refraction) {
+                        const float ar = cabs2(F.rperp) + cabs2(F.rpar), at = cabs2(tp) + cabs2(tl);
+                        const float tot = ar + at;
+                        const bool transmit = s0.x == p0.x && s0.y == p0.y && s0.z == p0.z;
+                        const float q = transmit ? (tot > 0.0f ? at / tot : 0.0f) : (tot > 0.0f ? ar / tot : 1.0f);
+                        const float sc = __builtin_amdgcn_rsqf(q);
+                        kpe = cscale(transmit ? tp : F.rperp, sc);
+                        kpa = cscale(transmit ? tl : F.rpar, sc);
+                        dkpe = cscale(transmit ? dtp : F.drperp, sc);
+                        dkpa = cscale(transmit ? dtl : F.drpar, sc);
+                    }
+                }
                 // u = W E_{l-1}
                 cf f0 = cadd(cscale(cf{p2.x, p2.y}, ct), cscale(cf{p2.z, p2.w}, cp));
                 cf f1 = cadd(cscale(cf{p3.x, p3.y}, ct), cscale(cf{p3.z, p3.w}, cp));
@@ -124,7 +151,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 int j = mat - a.mat0;
                 if (j >= 0 && j < kMatChunk) {
                     // z = lambda^H dD/deta u, dD/deta = diag(dr_perp, -dr_par)
-                    cf z = csub(cmulc(lam0, cmul(F.drperp, u0)), cmulc(lam1, cmul(F.drpar, u1)));
+                    cf z = csub(cmulc(lam0, cmul(dkpe, u0)), cmulc(lam1, cmul(dkpa, u1)));
 #pragma unroll
                     for (int jj = 0; jj < kMatChunk; jj++) {
                         if (jj == j) {
@@ -134,8 +161,8 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                     }
                 }
                 // lambda <- R^H lambda = W^T diag(conj r_perp, -conj r_par) lambda
-                cf v0 = cmulc(F.rperp, lam0);
-                cf v1 = cmulc(F.rpar, lam1);
+                cf v0 = cmulc(kpe, lam0);
+                cf v1 = cmulc(kpa, lam1);
                 v1 = cf{-v1.re, -v1.im};
                 lam0 = cadd(cscale(v0, b.w00), cscale(v1, b.w10));
                 lam1 = cadd(cscale(v0, b.w01), cscale(v1, b.w11));
@@ -219,6 +246,9 @@ rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
     a.tx = b.tx;
     a.pl = b.pl;
     a.npol = b.tx.pol == RT_POL_DUAL ? 2 : 1;
+    a.thickness = b.thickness;
+    a.refraction = b.refraction;
+    a.k0 = b.k0;
     a.grad_map = b.grad_map;
     a.map_stride = (int64_t)b.pl.W * b.pl.H;
     a.n_mat = s->n_mat;

@@ -418,6 +418,41 @@ __device__ __forceinline__ void slab(Fresnel& F, float k_d, cf& tperp, cf& tpar)
     F.rpar = cdiv(cmul(F.rpar, omx2), dl);
 }
 
+// Slab coefficients of one polarisation with their eta-derivatives, from the
+// half-space r1 and dr1 = dr1/d eta: with D = 1 - r1^2 x^2 and
+// dx/d eta = -j k_d x / (2 s), r = r1 (1 - x^2) / D, t = (1 - r1^2) x / D
+// and their derivatives by the quotient rule.
+__device__ __forceinline__ void slab_pol_grad(cf r1, cf dr1, cf x, cf dx, cf& r, cf& dr, cf& t, cf& dt) {
+    const cf one = cf{1.0f, 0.0f};
+    const cf x2 = cmul(x, x), r12 = cmul(r1, r1);
+    const cf D = csub(one, cmul(r12, x2));
+    const cf two_r1 = cscale(r1, 2.0f);
+    const cf dD = cscale(cadd(cmul(cmul(two_r1, dr1), x2), cmul(cmul(cscale(r12, 2.0f), x), dx)), -1.0f);
+    const cf omx2 = csub(one, x2), om12 = csub(one, r12);
+    r = cdiv(cmul(r1, omx2), D);
+    t = cdiv(cmul(om12, x), D);
+    dr = cdiv(csub(csub(cmul(dr1, omx2), cmul(cmul(two_r1, x), dx)), cmul(r, dD)), D);
+    dt = cdiv(csub(cadd(cscale(cmul(cmul(two_r1, dr1), x), -1.0f), cmul(om12, dx)), cmul(t, dD)), D);
+}
+
+// slab() with derivatives: F (from fresnel<true>) becomes the slab r and
+// dr/d eta; t and dt/d eta are returned.
+__device__ __forceinline__ void slab_grad(Fresnel& F, float k_d, cf& tperp, cf& tpar, cf& dtperp, cf& dtpar) {
+    const float qre = k_d * F.s.re, qim = k_d * F.s.im;
+    float sn, cs;
+    sincosf(qre, &sn, &cs);
+    const float m = __expf(qim);
+    const cf x = cf{m * cs, -m * sn};
+    const cf dx = cdiv(cmul(cf{0.0f, -k_d}, x), cscale(F.s, 2.0f));
+    cf r, dr;
+    slab_pol_grad(F.rperp, F.drperp, x, dx, r, dr, tperp, dtperp);
+    F.rperp = r;
+    F.drperp = dr;
+    slab_pol_grad(F.rpar, F.drpar, x, dx, r, dr, tpar, dtpar);
+    F.rpar = r;
+    F.drpar = dr;
+}
+
 // theta_hat and phi_hat of direction k (eq. spherical_vecs); phi = 0 on the
 // z axis.
 __device__ __forceinline__ void sph_basis(float3 k, float3& th, float3& ph) {

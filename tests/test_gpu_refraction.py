@@ -92,10 +92,13 @@ def test_refraction_rejections():
     with pytest.raises(rt.RtError) as e:           # refraction without a thickness
         rt.rt_radio_map(s, eps, sig, cfg.tx, cfg.plane, cfg.params, out)
     assert e.value.status == rt.RT_EINVAL
-    tape = rt.rt_tape_create(cfg.params)
-    with pytest.raises(rt.RtError) as e:
-        rt.rt_radio_map(s, eps, sig, cfg.tx, cfg.plane, cfg.params, out, tape=tape, thickness=thk)
-    assert e.value.status == rt.RT_EUNSUPPORTED
+    tape = rt.rt_tape_create(cfg.params)             # a tape records the sampled branches
+    rt.rt_radio_map(s, eps, sig, cfg.tx, cfg.plane, cfg.params, out, tape=tape, thickness=thk)
+    g = torch.ones_like(out)
+    ge = torch.empty(1, dtype=torch.float32, device="cuda")
+    with pytest.raises(rt.RtError) as e:             # the backward needs the same thickness
+        rt.rt_radio_map_backward(s, eps, sig, cfg.tx, cfg.plane, cfg.params, tape, g, ge)
+    assert e.value.status == rt.RT_EINVAL
     maps = torch.empty((1, 1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device="cuda")
     with pytest.raises(rt.RtError) as e:
         rt.rt_radio_map_batched(s, eps[None], sig[None], [cfg.tx], [10_000], cfg.plane, cfg.params, maps)
