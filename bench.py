@@ -492,6 +492,29 @@ def refraction_leg(rt, sg, cfg, dev, out, launch=""):
         seg = int(stats[0])
         ms = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, p, out, thickness=t), 5, 1)
         res[name] = {"ms": round(ms, 3), "segments": seg, "M ray-bounces/s": round(seg / (ms * 1e-3) / 1e6, 1)}
+    # forward with a tape + adjoint over forward: the differentiation
+    # transmitter (directional, yaw 30 deg, pitch -10 deg), 1e6 rays, L = 4
+    dc = sg.diff_config()
+    pd = sg.Params(dc.params.freq_hz, dc.params.n_rays, dc.params.max_depth, refraction=1, seed=1)
+    m = torch.empty((1, dc.plane.H, dc.plane.W), dtype=torch.float32, device=dev)
+    tape = rt.rt_tape_create(pd)
+    g = torch.randn((1, dc.plane.H, dc.plane.W), dtype=torch.float32, device=dev)
+    ge = torch.empty(2, dtype=torch.float32, device=dev)
+    gs = torch.empty(2, dtype=torch.float32, device=dev)
+    go = torch.empty(3, dtype=torch.float32, device=dev)
+
+    def fwd():
+        rt.rt_radio_map(scene, eps, sig, dc.tx, dc.plane, pd, m, thickness=thk)
+
+    def fwdbwd():
+        rt.rt_radio_map(scene, eps, sig, dc.tx, dc.plane, pd, m, tape=tape, thickness=thk)
+        rt.rt_radio_map_backward(scene, eps, sig, dc.tx, dc.plane, pd, tape, g, ge, gs, go, thickness=thk)
+
+    t_f = _time(fwd, 5)
+    t_fb = _time(fwdbwd, 5)
+    res["fwd_bwd_over_fwd"] = {"workload": "same scene and slabs, refraction, directional Tx (yaw 30, pitch -10 "
+                                           "deg), 1e6 rays, L = 4", "fwd_ms": round(t_f, 4),
+                               "fwd_bwd_ms": round(t_fb, 4), "ratio": round(t_fb / t_f, 3)}
     return res
 
 
