@@ -78,13 +78,15 @@ def lib():
             L.or_radio_map.restype = C.c_int
             L.or_radio_map.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                        C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                       C.POINTER(_Tx),
+                                       C.c_void_p, C.POINTER(_Tx),
                                        C.POINTER(_Plane), C.POINTER(_Params), C.c_void_p, C.c_int64,
                                        C.c_int64, C.c_int64, C.POINTER(_Out)]
             L.or_fresnel.restype = None
             L.or_fresnel.argtypes = [C.c_double] * 4 + [C.POINTER(C.c_double)] * 4
             L.or_fresnel_slab.restype = None
             L.or_fresnel_slab.argtypes = [C.c_double] * 5 + [C.c_void_p]
+            L.or_scatter_pattern.restype = C.c_double
+            L.or_scatter_pattern.argtypes = [C.c_void_p] * 4
             L.or_uniform.restype = C.c_double
             L.or_uniform.argtypes = [C.c_uint32, C.c_int64, C.c_int, C.c_uint32]
             L.or_launch_field.restype = None
@@ -147,7 +149,7 @@ class OracleResult:
 
 
 def radio_map(scene, tx, plane, params, *, ray_ids=None, ray_begin=None, ray_end=None,
-              eps_r=None, sigma=None, thickness=None, scattering=None, xpd=None, want_hits=False,
+              eps_r=None, sigma=None, thickness=None, scattering=None, xpd=None, pattern=None, want_hits=False,
               want_records=False, rec_cap=None,
               grad_map=None, replay_hits=None) -> OracleResult:
     """Run the oracle over a ray range (default: the params' range) or an explicit list.
@@ -172,6 +174,9 @@ def radio_map(scene, tx, plane, params, *, ray_ids=None, ray_begin=None, ray_end
         xpd = getattr(scene, "xpd", None)
     sca = None if scattering is None else np.ascontiguousarray(scattering, dtype=np.float64)
     xp = None if xpd is None else np.ascontiguousarray(xpd, dtype=np.float64)
+    if pattern is None:
+        pattern = getattr(scene, "scatter_pattern", None)
+    pat = None if pattern is None else np.ascontiguousarray(pattern, dtype=np.float64).reshape(-1, 4)
     n_mat = int(eps.shape[0])
     npol = 2 if int(tx.pol) == 2 else 1
     Lmax = int(params.max_depth)
@@ -221,7 +226,7 @@ def radio_map(scene, tx, plane, params, *, ray_ids=None, ray_begin=None, ray_end
                   int(getattr(params, "refraction", 0)))
     txs, pls = _tx(tx), _plane(plane)
     rc = L.or_radio_map(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], M.ctypes.data, n_mat,
-                        eps.ctypes.data, sig.ctypes.data, _ptr(thk), _ptr(sca), _ptr(xp), C.byref(txs), C.byref(pls), C.byref(prm),
+                        eps.ctypes.data, sig.ctypes.data, _ptr(thk), _ptr(sca), _ptr(xp), _ptr(pat), C.byref(txs), C.byref(pls), C.byref(prm),
                         _ptr(ids), n_run if ids is not None else 0, b, e, C.byref(out))
     if rc != 0:
         raise ValueError("oracle rejected its arguments (code %d)" % rc)
@@ -246,6 +251,12 @@ def fresnel_slab(eps_r, sigma, freq, cos_theta, d):
     o = np.zeros(8)
     lib().or_fresnel_slab(eps_r, sigma, freq, cos_theta, d, o.ctypes.data)
     return complex(o[0], o[1]), complex(o[2], o[3]), complex(o[4], o[5]), complex(o[6], o[7])
+
+
+def scatter_pattern(pp, ki, ks, n):
+    """f_s of the oracle: pp = (kind, alpha_R, alpha_I, Lambda); unit vectors."""
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (pp, ki, ks, n)]
+    return float(lib().or_scatter_pattern(*[x.ctypes.data for x in a]))
 
 
 def uniform(seed, n, l, stream):

@@ -36,8 +36,9 @@
  *     App. "Diffuse Reflection"): a material with scattering coefficient
  *     S > 0 scatters with probability q(S) of eq. path-solver-used-dist-event
  *     into a direction drawn uniformly over the hemisphere of the incident
- *     side (solid angle 2 pi), with the Lambertian pattern
- *     (eq. lambertian_model), the reflected power ratio Gamma^2 and the
+ *     side (solid angle 2 pi), with the Lambertian, directive or
+ *     backscattering pattern (eq. lambertian_model, eq. directive_model,
+ *     eq. backscattering_model), the reflected power ratio Gamma^2 and the
  *     cross-polarisation matrix of eq. scattered_field with random phases;
  *     the specular coefficients are multiplied by R = sqrt(1 - S^2) (eq. R);
  *   - an optional synthetic transmit array with a precoding vector
@@ -79,8 +80,8 @@
  *     scattered direction (phi = 0 on the z axis).  With the change of
  *     variables of eq. radio-map-solver-ci-all-2 the footprint dA, r^2 and
  *     cos(theta_i) cancel, so the scattered distance-normalised field is the
- *     incident one times sqrt(2 pi f_s S^2 Gamma^2 / q(S)) =
- *     sqrt(2 cos(theta_s) S^2 Gamma^2 / q(S)), and the ray-tube length
+ *     incident one times sqrt(2 pi f_s S^2 Gamma^2 / q(S)) (for the
+ *     Lambertian pattern 2 pi f_s = 2 cos(theta_s)), and the ray-tube length
  *     starts again at 0 (gain thresholding uses the current tube);
  *   - c0 = 299792458 m/s, eps0 = 8.8541878128e-12 F/m, phi_g = (1+sqrt 5)/2;
  *   - the plane is two-sided and non-occluding; a segment contributes iff
@@ -284,6 +285,58 @@ static void sph_basis(vec3 k, vec3* th, vec3* ph)
     double cp = rho > 0.0 ? k.x / rho : 1.0, sp = rho > 0.0 ? k.y / rho : 0.0;
     *th = mk(k.z * cp, k.z * sp, -rho);
     *ph = mk(-sp, cp, 0.0);
+}
+
+/* Scattering pattern f_s (App. "Diffuse Reflection"): pp = (kind, alpha_R,
+ * alpha_I, Lambda) with kind 0 Lambertian (eq. lambertian_model), 1
+ * directive (eq. directive_model), 2 backscattering
+ * (eq. backscattering_model); n is the unit normal on the incident side,
+ * ki the incident and ks the scattered direction, kr the specular one. */
+static double lobe_norm(int alpha, double ci)
+{
+    /* F_alpha(theta_i) = 2^-alpha sum_k C(alpha, k) I_k, with
+     * I_k = 2 pi/(k+1) (k even) or 2 pi/(k+1) cos(theta_i) sum_{w <= (k-1)/2}
+     * C(2w, w) sin^{2w}(theta_i) / 2^{2w} (k odd) */
+    double s2 = fmax(0.0, 1.0 - ci * ci), F = 0.0, binom = 1.0;
+    for (int k = 0; k <= alpha; k++) {
+        if (k > 0) binom = binom * (double)(alpha - k + 1) / (double)k;
+        double Ik = 2.0 * OR_PI / (double)(k + 1);
+        if (k % 2 == 1) {
+            double sum = 0.0, cw = 1.0, p = 1.0;
+            for (int w = 0; w <= (k - 1) / 2; w++) {
+                if (w > 0) cw = cw * (double)(2 * w) * (double)(2 * w - 1) / ((double)w * (double)w);
+                sum += cw * p / pow(4.0, (double)w);
+                p *= s2;
+            }
+            Ik *= ci * sum;
+        }
+        F += binom * Ik;
+    }
+    return F / pow(2.0, (double)alpha);
+}
+
+static double scatter_pattern(const double* pp, vec3 ki, vec3 ks, vec3 n, vec3 kr)
+{
+    int kind = pp ? (int)pp[0] : 0;
+    if (kind == 0) return vdot(n, ks) / OR_PI;
+    int aR = (int)pp[1], aI = (int)pp[2];
+    double lam = kind == 1 ? 1.0 : pp[3];
+    double ci = -vdot(ki, n);
+    double num = lam * pow(0.5 * (1.0 + vdot(kr, ks)), (double)aR);
+    double F = lam * lobe_norm(aR, ci);
+    if (kind == 2) {
+        num += (1.0 - lam) * pow(0.5 * (1.0 - vdot(ki, ks)), (double)aI);
+        F += (1.0 - lam) * lobe_norm(aI, ci);
+    }
+    return num / F;
+}
+
+/* f_s for tests: pp as above, directions as 3-vectors. */
+double or_scatter_pattern(const double* pp, const double* ki, const double* ks, const double* n)
+{
+    vec3 vi = mk(ki[0], ki[1], ki[2]), vs = mk(ks[0], ks[1], ks[2]), vn = mk(n[0], n[1], n[2]);
+    vec3 kr = vsub(vi, vscale(vn, 2.0 * vdot(vi, vn)));
+    return scatter_pattern(pp, vi, vs, vn, kr);
 }
 
 /* ------------------------------------------------- synthetic transmit array */
@@ -505,7 +558,7 @@ static hit_info closest_hit(const or_mesh* m, vec3 o, vec3 k, int64_t last, doub
 int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                  const int32_t* tri_mat, int32_t n_mat,
                  const double* eps_r, const double* sigma, const double* thickness,
-                 const double* scattering, const double* xpd,
+                 const double* scattering, const double* xpd, const double* pattern,
                  const or_tx* tx, const or_plane* pl, const or_params* prm,
                  const int64_t* ray_ids, int64_t n_ids, int64_t ray_begin, int64_t ray_end,
                  or_out* out)
@@ -523,6 +576,14 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             if (!(scattering[i] >= 0.0 && scattering[i] <= 1.0) || !(xpd && xpd[i] >= 0.0 && xpd[i] <= 1.0))
                 return 1;
         if (tx->pol == 2) return 1;                 /* Gamma depends on the field */
+        if (pattern)
+            for (int32_t i = 0; i < n_mat; i++) {
+                const double* pp = pattern + 4 * (int64_t)i;
+                if (!(pp[0] == 0.0 || pp[0] == 1.0 || pp[0] == 2.0)) return 1;
+                if (pp[0] != 0.0 && !(pp[1] >= 1.0 && pp[1] <= 64.0 && pp[1] == floor(pp[1]))) return 1;
+                if (pp[0] == 2.0 && !(pp[2] >= 1.0 && pp[2] <= 64.0 && pp[2] == floor(pp[2]) &&
+                                      pp[3] >= 0.0 && pp[3] <= 1.0)) return 1;
+            }
         if (out->grad_map && out->grad) return 1;
     }
     for (int64_t i = 0; i < n_tri; i++) {
@@ -741,7 +802,9 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                     cplx eth = cv_dot_real(thi, E[p]), eph = cv_dot_real(phi_i, E[p]);
                     cplx sth = e1 * (sqrt(1.0 - K) * eth - sqrt(K) * eph);
                     cplx sph = e2 * (sqrt(K) * eth + sqrt(1.0 - K) * eph);
-                    double sc = sqrt(2.0 * cs * Sm * Sm * g2) * inv_sqrt_q;
+                    /* 2 pi f_s S^2 Gamma^2 / q(S) */
+                    double fs = scatter_pattern(pattern ? pattern + 4 * (int64_t)m : NULL, k, k_new, nrm, kr);
+                    double sc = sqrt(2.0 * OR_PI * fs * Sm * Sm * g2) * inv_sqrt_q;
                     cvec3 En = cv_zero();
                     En = cv_axpy(En, sc * sth, ths);
                     En = cv_axpy(En, sc * sph, phs_v);

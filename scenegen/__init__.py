@@ -38,12 +38,15 @@ METAL = (1.0, 1.0e7)
 THICKNESS = {CONCRETE: 0.2, GLASS: 0.01, METAL: 0.005}
 
 
-def with_diffuse(scene: "Scene", scattering, xpd=None) -> "Scene":
+def with_diffuse(scene: "Scene", scattering, xpd=None, pattern=None) -> "Scene":
     """Copy of ``scene`` with a scattering coefficient S (and a
-    cross-polarisation share K_x, default 0) per material."""
+    cross-polarisation share K_x, default 0, and a scattering pattern
+    (kind, alpha_R, alpha_I, Lambda), default Lambertian) per material."""
     S = np.broadcast_to(np.asarray(scattering, dtype=np.float64), scene.eps_r.shape).copy()
     K = np.zeros_like(S) if xpd is None else np.broadcast_to(np.asarray(xpd, dtype=np.float64), S.shape).copy()
-    return dataclasses.replace(scene, scattering=S, xpd=K)
+    P = None if pattern is None else np.broadcast_to(np.asarray(pattern, dtype=np.float64),
+                                                     (S.shape[0], 4)).copy()
+    return dataclasses.replace(scene, scattering=S, xpd=K, scatter_pattern=P)
 
 
 def with_thickness(scene: "Scene", thickness=None) -> "Scene":
@@ -69,6 +72,9 @@ class Scene:
     thickness: Optional[np.ndarray] = None   # float64 [n_mat] slab thickness (m); None = half-space
     scattering: Optional[np.ndarray] = None  # float64 [n_mat] scattering coefficient S; None = no diffuse
     xpd: Optional[np.ndarray] = None         # float64 [n_mat] cross-polarisation share K_x
+    # float64 [n_mat][4] scattering pattern (kind, alpha_R, alpha_I, Lambda):
+    # kind 0 Lambertian, 1 directive, 2 backscattering; None = Lambertian
+    scatter_pattern: Optional[np.ndarray] = None
 
     @property
     def n_triangles(self) -> int:

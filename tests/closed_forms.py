@@ -182,7 +182,60 @@ def dirichlet_gain(n: int, spacing_wl: float, c, c0: float) -> np.ndarray:
     return np.where(small, float(n), num / np.where(small, 1.0, den))
 
 
-def lambertian_ground_map(tx_pos, plane, lam, eta_g, pol, half, ceiling=None, n_beta=48, n_psi=96, n_cell=2):
+def directive_pattern(alpha, ki, ks, n, lobe2=None):
+    """Scattering pattern of eq. directive_model (lobe2 = (alpha_I, Lambda):
+    eq. backscattering_model) for arrays of unit vectors [..., 3]; the
+    normalisation F_alpha(theta_i) is taken by numerical quadrature over the
+    hemisphere (so that int f_s d(omega) = 1 holds by construction here and
+    the closed-form F of the paper is what the oracle pins against)."""
+    ci = -np.sum(ki * n, -1)
+    kr = ki + 2.0 * ci[..., None] * n
+    lobe = (0.5 * (1.0 + np.sum(kr * ks, -1))) ** alpha
+    F = _lobe_norm_interp(alpha, "r", ci)
+    if lobe2 is not None:
+        aI, L = lobe2
+        lobe = L * lobe + (1 - L) * (0.5 * (1.0 - np.sum(ki * ks, -1))) ** aI
+        F = L * F + (1 - L) * _lobe_norm_interp(aI, "i", ci)
+    return lobe / F
+
+
+_LOBE_CACHE = {}
+
+
+def _lobe_norm_interp(alpha, which, ci):
+    """lobe_norm_quadrature on a 2,001-point grid of cos(theta_i), cubic
+    interpolation in between (smooth in cos(theta_i))."""
+    key = (alpha, which)
+    if key not in _LOBE_CACHE:
+        grid = np.linspace(0.0, 1.0, 2001)
+        _LOBE_CACHE[key] = (grid, lobe_norm_quadrature(alpha, grid, which))
+    grid, vals = _LOBE_CACHE[key]
+    from scipy.interpolate import CubicSpline
+    return CubicSpline(grid, vals)(np.clip(ci, 0.0, 1.0))
+
+
+def lobe_norm_quadrature(alpha, ci, which, n_t=64, n_p=128):
+    """int over the hemisphere of ((1 + k_r.k_s)/2)^alpha (which = "r") or
+    ((1 - k_i.k_s)/2)^alpha ("i") d(omega), for incidence cosines ci, by
+    Gauss-Legendre in cos(theta_s) and the midpoint rule in azimuth, in the
+    frame n = z, incidence plane x-z."""
+    ci = np.asarray(ci, dtype=np.float64)
+    g, w = np.polynomial.legendre.leggauss(n_t)
+    mu = (g + 1) / 2
+    wm = w / 2
+    ph = (np.arange(n_p) + 0.5) * 2 * math.pi / n_p
+    si = np.sqrt(np.maximum(0.0, 1 - ci ** 2))[..., None, None]
+    c = ci[..., None, None]
+    st = np.sqrt(1 - mu ** 2)[:, None]
+    # k_i = (si, 0, -ci), k_r = (si, 0, ci), k_s = (st cos ph, st sin ph, mu)
+    dot_r = si * st * np.cos(ph)[None, :] + c * mu[:, None]
+    dot_i = si * st * np.cos(ph)[None, :] - c * mu[:, None]
+    base = 0.5 * (1 + dot_r) if which == "r" else 0.5 * (1 - dot_i)
+    return np.sum(base ** alpha * wm[:, None], axis=(-2, -1)) * (2 * math.pi / n_p)
+
+
+def lambertian_ground_map(tx_pos, plane, lam, eta_g, pol, half, ceiling=None, n_beta=48, n_psi=96, n_cell=2,
+                          pattern=None):
     """Expected map of paths Tx -> Lambertian ground (S = 1) -> plane, or,
     with ceiling = (z_c, eta_c, "par" | "perp"), Tx -> ground -> specular
     ceiling -> plane, over a ground square |x|, |y| <= half at z = 0.
@@ -196,6 +249,7 @@ def lambertian_ground_map(tx_pos, plane, lam, eta_g, pol, half, ceiling=None, n_
     Gamma^2 is |r_par|^2 (V-pol: the field lies in the plane of incidence)
     or |r_perp|^2 (H-pol).  Directions: Gauss-Legendre in the polar angle up
     to the square's edge, uniform in azimuth; cells: n_cell^2 points.
+    pattern(ki, ks, n) replaces the Lambertian cos(theta_s)/pi (no ceiling).
     """
     tx = np.asarray(tx_pos, dtype=np.float64)
     g, gw = np.polynomial.legendre.leggauss(n_beta)
@@ -226,6 +280,14 @@ def lambertian_ground_map(tx_pos, plane, lam, eta_g, pol, half, ceiling=None, n_
                     rp, rl = fresnel_general(eta_g, ci)
                     gam = np.abs(rl) ** 2 if pol == "V" else np.abs(rp) ** 2
                     f = gam * ci / r0 ** 2
+                    if pattern is not None:
+                        # f_s / (cos(theta_s)/pi) at (incident q - tx, scattered t - q)
+                        ki = np.stack([qx - tx[0], qy - tx[1], np.full_like(qx, -tx[2])], -1) / r0[..., None]
+                        dvec = np.stack([tx_ - qx, ty_ - qy, np.full_like(qx, hz)], -1)
+                        ks = dvec / np.linalg.norm(dvec, axis=-1)[..., None]
+                        nz = np.zeros_like(ks)
+                        nz[..., 2] = 1.0
+                        f = f * pattern(ki, ks, nz) * math.pi / ks[..., 2]
                     if ceiling is not None:
                         cp_, cl_ = fresnel_general(ceiling[1], np.cos(beta))
                         f = f * (np.abs(cl_) ** 2 if ceiling[2] == "par" else np.abs(cp_) ** 2)
