@@ -135,6 +135,14 @@ rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
  * (Gamma depends on the field): dual polarisation, a tape and
  * rt_radio_map_batched give RT_EUNSUPPORTED.  Entries outside [0, 1] give
  * undefined results.
+ * scatter_pattern (optional, needs scattering; NULL = Lambertian for every
+ * material): device float32 [n_materials][4] = (kind, alpha_R, alpha_I,
+ * Lambda) with kind 0 Lambertian (eq. lambertian_model), 1 directive
+ * (eq. directive_model, lobe width alpha_R), 2 backscattering
+ * (eq. backscattering_model, lobe widths alpha_R and alpha_I, share
+ * Lambda); the diffuse factor 2 cos(theta_s) becomes 2 pi f_s.  alpha_R and
+ * alpha_I are integers in [1, 64], Lambda in [0, 1]; other values give
+ * undefined results.
  */
 typedef struct {
     const float* eps_r;
@@ -142,6 +150,7 @@ typedef struct {
     const float* thickness;
     const float* scattering;
     const float* xpd;
+    const float* scatter_pattern;
 } rt_materials;
 
 enum { RT_PATTERN_ISO = 0, RT_PATTERN_DIRECTIONAL = 1 };

@@ -44,7 +44,7 @@ class rt_scene_info(C.Structure):
 
 class rt_materials(C.Structure):
     _fields_ = [("eps_r", C.c_void_p), ("sigma", C.c_void_p), ("thickness", C.c_void_p),
-                ("scattering", C.c_void_p), ("xpd", C.c_void_p)]
+                ("scattering", C.c_void_p), ("xpd", C.c_void_p), ("scatter_pattern", C.c_void_p)]
 
 
 class rt_tx(C.Structure):
@@ -231,25 +231,28 @@ def scene_from_mesh(scene, device="cuda") -> RtScene:
     return rt_build_scene(V, F, M, len(scene.eps_r))
 
 
-def materials(eps_r, sigma, thickness=None, scattering=None, xpd=None) -> rt_materials:
-    return rt_materials(_ptr(eps_r), _ptr(sigma), _ptr(thickness), _ptr(scattering), _ptr(xpd))
+def materials(eps_r, sigma, thickness=None, scattering=None, xpd=None, scatter_pattern=None) -> rt_materials:
+    return rt_materials(_ptr(eps_r), _ptr(sigma), _ptr(thickness), _ptr(scattering), _ptr(xpd),
+                        _ptr(scatter_pattern))
 
 
 # ----------------------------------------------------------------- forward
 def rt_radio_map(scene: RtScene, eps_r, sigma, tx, plane, params, out_map, *, tape=None, hits=None,
                  cells=None, weights=None, stats=None, stream=None, thickness=None, scattering=None, xpd=None,
-                 **pkw):
+                 scatter_pattern=None, **pkw):
     """Queue the SBR radio map into ``out_map`` (device f32 [H][W] or [2][H][W]).
 
     ``thickness`` (device f32 [n_mat], metres) selects slab walls; with
     ``params.refraction`` every hit samples reflection or transmission;
-    ``scattering`` and ``xpd`` (device f32 [n_mat]) enable Lambertian diffuse
-    reflection."""
+    ``scattering`` and ``xpd`` (device f32 [n_mat]) enable diffuse
+    reflection, Lambertian unless ``scatter_pattern`` (device f32 [n_mat][4])
+    selects directive or backscattering lobes."""
     rec = rt_records(_ptr(hits), _ptr(cells), _ptr(weights), _ptr(stats))
     p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
     t = tx if isinstance(tx, rt_tx) else make_tx(tx)
     pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
-    _check(lib().rt_radio_map(scene.handle, materials(eps_r, sigma, thickness, scattering, xpd), C.byref(t),
+    _check(lib().rt_radio_map(scene.handle, materials(eps_r, sigma, thickness, scattering, xpd, scatter_pattern),
+                              C.byref(t),
                               C.byref(pl), C.byref(p),
                               _ptr(out_map), tape.handle if tape is not None else None, C.byref(rec),
                               _stream(stream)))

@@ -338,6 +338,8 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
               "rt_radio_map: refraction needs the slab thickness of every material");
     CHECK_ARG((materials.scattering == nullptr) == (materials.xpd == nullptr),
               "rt_radio_map: scattering and xpd must both be given or both be NULL");
+    CHECK_ARG(!materials.scatter_pattern || materials.scattering,
+              "rt_radio_map: scatter_pattern needs scattering and xpd");
     if (materials.scattering && (tape || tx->pol == RT_POL_DUAL))
         return rt_fail(RT_EUNSUPPORTED,
                        "rt_radio_map: diffuse reflection takes one polarisation and cannot be recorded on a tape");
@@ -378,6 +380,7 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
     f.thickness = materials.thickness;
     f.scattering = materials.scattering;
     f.xpd = materials.xpd;
+    f.pattern = materials.scatter_pattern;
     f.refraction = params->refraction;
     f.k0 = (float)(2.0 * RT_PI * params->freq_hz / RT_C0);
     if (records) {
@@ -503,7 +506,7 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     if ((r = check_params(&p, &b, &e)) != RT_OK) return r;
     if (p.rr_p_max > 0.0f || p.gain_threshold > 0.0f)
         return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: early termination is not supported here");
-    if (p.refraction || materials.thickness || materials.scattering || materials.xpd)
+    if (p.refraction || materials.thickness || materials.scattering || materials.xpd || materials.scatter_pattern)
         return rt_fail(RT_EUNSUPPORTED,
                        "rt_radio_map_batched: slab walls, refraction and diffuse reflection are not supported here");
     if ((r = check_device(scene)) != RT_OK) return r;

@@ -183,6 +183,7 @@ struct FwdLaunch {
     const float* thickness;  // slab thickness per material (m), or null (half-space)
     const float* scattering; // scattering coefficient per material, or null (no diffuse)
     const float* xpd;        // cross-polarisation share per material
+    const float* pattern;    // [n_mat][4] scattering pattern, or null (Lambertian)
     int32_t refraction;      // sample reflection or transmission at every hit
     float k0;                // 2 pi / lambda
 };

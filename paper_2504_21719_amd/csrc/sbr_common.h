@@ -453,6 +453,50 @@ __device__ __forceinline__ void slab_grad(Fresnel& F, float k_d, cf& tperp, cf& 
     F.drpar = dr;
 }
 
+// Normalisation F_alpha(theta_i) of a scattering lobe (eq. directive_model):
+// 2^-alpha sum_k C(alpha, k) I_k with I_k = 2 pi/(k+1) for even k and
+// 2 pi/(k+1) cos(theta_i) sum_{w <= (k-1)/2} C(2w, w) (sin^2(theta_i)/4)^w
+// for odd k; the inner terms follow from C(2w, w)/4^w = (2w-1)/(2w) times
+// the previous one.
+__device__ __forceinline__ float lobe_norm(int alpha, float ci) {
+    const float s2 = fmaxf(0.0f, 1.0f - ci * ci);
+    float F = 0.0f, binom = 1.0f;
+    for (int k = 0; k <= alpha; k++) {
+        if (k > 0) binom = binom * (float)(alpha - k + 1) / (float)k;
+        float Ik = 2.0f * (float)RT_PI / (float)(k + 1);
+        if (k & 1) {
+            float sum = 0.0f, term = 1.0f;
+            for (int w = 0; w <= (k - 1) / 2; w++) {
+                if (w > 0) term *= (float)(2 * w - 1) / (float)(2 * w) * s2;
+                sum += term;
+            }
+            Ik *= ci * sum;
+        }
+        F += binom * Ik;
+    }
+    return ldexpf(F, -alpha);
+}
+
+// 2 pi f_s of a diffuse bounce: pp = (kind, alpha_R, alpha_I, Lambda) or
+// null (Lambertian, eq. lambertian_model: 2 cos(theta_s)); kind 1 directive
+// (eq. directive_model), 2 backscattering (eq. backscattering_model).  ci =
+// cos(theta_i), cs = cos(theta_s), ki / ks / kr the incident, scattered and
+// specular directions.
+__device__ __forceinline__ float scatter_weight(const float* pp, float ci, float cs, float3 ki, float3 ks, float3 kr) {
+    const int kind = pp ? (int)pp[0] : 0;
+    if (kind == 0) return 2.0f * cs;
+    const int aR = (int)pp[1];
+    const float lam = kind == 1 ? 1.0f : pp[3];
+    float num = lam * powf(0.5f * (1.0f + dot3(kr, ks)), (float)aR);
+    float F = lam * lobe_norm(aR, ci);
+    if (kind == 2) {
+        const int aI = (int)pp[2];
+        num += (1.0f - lam) * powf(0.5f * (1.0f - dot3(ki, ks)), (float)aI);
+        F += (1.0f - lam) * lobe_norm(aI, ci);
+    }
+    return 2.0f * (float)RT_PI * num / F;
+}
+
 // theta_hat and phi_hat of direction k (eq. spherical_vecs); phi = 0 on the
 // z axis.
 __device__ __forceinline__ void sph_basis(float3 k, float3& th, float3& ph) {

@@ -72,6 +72,7 @@ struct FwdArgs {
     const float* thickness;        // slab thickness per material (m), or null
     const float* scattering;       // scattering coefficient S per material, or null (no diffuse)
     const float* xpd;              // cross-polarisation share K_x per material
+    const float* pattern;          // [n_mat][4] scattering pattern, or null (Lambertian)
     int refraction;                // 1: sample reflection or transmission at every hit
     float k0;                      // 2 pi / lambda
     int* spill;
@@ -633,7 +634,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                         const float p00 = dot3(thi, es), p01 = dot3(thi, ep);
                         const float p10 = dot3(phi_i, es), p11 = dot3(phi_i, ep);
                         const float K = a.xpd[mat], sk = sqrtf(K), ck = sqrtf(1.0f - K);
-                        const float sc = sqrtf(2.0f * cs * s2 * g2) * __builtin_amdgcn_rsqf(qs);
+                        const float fw = scatter_weight(a.pattern ? a.pattern + 4 * mat : nullptr, b.c, cs, k, knew, b.kr);
+                        const float sc = sqrtf(fw * s2 * g2) * __builtin_amdgcn_rsqf(qs);
                         const float a0 = ck * p00 - sk * p10, a1 = ck * p01 - sk * p11;   // theta row
                         const float b0 = sk * p00 + ck * p10, b1 = sk * p01 + ck * p11;   // phi row
                         const cf x1 = cf{c1 * sc, s1 * sc}, x2 = cf{c2p * sc, s2p * sc};
@@ -860,6 +862,7 @@ rt_status rt_launch_forward(const FwdLaunch& f, hipStream_t st) {
     a.thickness = f.thickness;
     a.scattering = f.scattering;
     a.xpd = f.xpd;
+    a.pattern = f.pattern;
     a.refraction = f.refraction;
     a.k0 = f.k0;
     const bool ext = f.rr_p_max > 0.0f || f.gain_threshold > 0.0f || f.thickness != nullptr || f.scattering != nullptr;

@@ -36,7 +36,7 @@ def gpu_scene(scene):
 
 def gpu_radio_map(cfg, *, scene_handle=None, ray_begin=None, ray_end=None, records=True, accel=0, deposit=0,
                   block_size=0, eps_r=None, sigma=None, tx=None, stream=None, thickness=None, scattering=None,
-                  xpd=None):
+                  xpd=None, pattern=None):
     import torch
     import paper_2504_21719_amd as rt
     s = scene_handle if scene_handle is not None else gpu_scene(cfg.scene)
@@ -56,6 +56,9 @@ def gpu_radio_map(cfg, *, scene_handle=None, ray_begin=None, ray_end=None, recor
         scattering, xpd = cfg.scene.scattering, cfg.scene.xpd
     sca = None if scattering is None else torch.tensor(scattering, dtype=torch.float32, device=dev)
     xp = None if xpd is None else torch.tensor(xpd, dtype=torch.float32, device=dev)
+    if pattern is None:
+        pattern = cfg.scene.scatter_pattern
+    pat = None if pattern is None else torch.tensor(pattern, dtype=torch.float32, device=dev)
     out = torch.full((npol, cfg.plane.H, cfg.plane.W), float("nan"), dtype=torch.float32, device=dev)
     hits = cells = weights = stats = None
     if records:
@@ -65,7 +68,7 @@ def gpu_radio_map(cfg, *, scene_handle=None, ray_begin=None, ray_end=None, recor
         stats = torch.zeros(8, dtype=torch.int64, device=dev)
     rt.rt_radio_map(s, eps, sig, tx, cfg.plane, cfg.params, out, hits=hits, cells=cells, weights=weights,
                     stats=stats, ray_begin=b, ray_end=e, accel=accel, deposit=deposit, block_size=block_size,
-                    stream=stream, thickness=thk, scattering=sca, xpd=xp)
+                    stream=stream, thickness=thk, scattering=sca, xpd=xp, scatter_pattern=pat)
     torch.cuda.synchronize()
     c = lambda t: None if t is None else t.cpu().numpy()[:n] if t.dim() == 2 else t.cpu().numpy()
     return GpuResult(out.cpu().numpy(), c(hits), c(cells), c(weights), None if stats is None else stats.cpu().numpy())

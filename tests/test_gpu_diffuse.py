@@ -55,6 +55,15 @@ def test_diffuse_manhattan():
     _parity(cfg)
 
 
+@pytest.mark.parametrize("pp", [(1, 3, 1, 1.0), (2, 2, 4, 0.5)])
+def test_diffuse_directive_and_backscattering_patterns(pp):
+    cfg = sg.manhattan_config(n_rays=200_000, max_depth=5)
+    cfg.plane = sg.Plane(1.5, -500.0, -500.0, 10.0, 10.0, 100, 100)
+    cfg.scene = sg.with_diffuse(cfg.scene, [0.5, 0.3], [0.2, 0.0], pp)
+    cfg.params.seed = 5
+    _parity(cfg)
+
+
 def test_diffuse_with_refraction_and_roulette():
     cfg = sg.tiny_config(n_rays=100_000)
     cfg.scene = sg.with_diffuse(sg.with_thickness(sg.tiny_scene(bottom=False), [0.05]), 0.5, 0.2)
