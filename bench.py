@@ -53,6 +53,7 @@ ALU_OPS = {"child_box": 15, "tri": 45, "segment": 250}
 # 3 vertices + id = 40 B, per deposit a 4 B read-modify-write = 8 B
 NODE_BYTES = {2: 56, 4: 112}
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "forward_manhattan_counters.json")
+PROFILE_COUNTERS_LARGE = os.path.join(ROOT, "profiles", "forward_large_counters.json")
 KERNEL_SOURCES = ["paper_2504_21719_amd/csrc/sbr_forward.hip", "paper_2504_21719_amd/csrc/sbr_common.h",
                   "paper_2504_21719_amd/csrc/rt_device.h"]
 
@@ -78,6 +79,10 @@ def parse():
     ap.add_argument("--launch", default="", help="width,order,block,deposit,refill: apply instead of tuning")
     ap.add_argument("--calib-copy", action="store_true", help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run N forward steps (for rocprofv3)")
+    ap.add_argument("--profile-large", type=int, default=0,
+                    help="only run N forward steps of the 1 M-triangle workload (for rocprofv3)")
+    ap.add_argument("--large-counters", action="store_true",
+                    help="with --ingest-counters: the CSVs are of a --profile-large run")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs of a --profile-steps --calib-copy "
                          "run into the per-launch traffic record, then exit")
@@ -87,7 +92,7 @@ def parse():
 CALIB_COPY_BYTES = (64 << 20) * 4
 
 
-def ingest_counters(fetch_csv, write_csv):
+def ingest_counters(fetch_csv, write_csv, large=False):
     """Per-launch HBM traffic of the forward kernel from two counter runs.
 
     Each run holds the forward dispatches and three plain device copies of
@@ -95,7 +100,7 @@ def ingest_counters(fetch_csv, write_csv):
     over what the counter reports for it."""
     import csv
     out = {"kernel_source_sha": kernel_source_sha(), "kernel": "k_forward (single transmitter, 4-wide tree)",
-           "workload": "manhattan, 1e7 rays, L = 5"}
+           "workload": "large: 1,021,074 triangles, 1e8 rays, L = 8" if large else "manhattan, 1e7 rays, L = 5"}
     for path, counter, key in ((fetch_csv, "FETCH_SIZE", "fetch"), (write_csv, "WRITE_SIZE", "write")):
         with open(path) as f:
             rows = [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
@@ -113,7 +118,7 @@ def ingest_counters(fetch_csv, write_csv):
         out[key + "_bytes_per_launch"] = int(round(kib * 1024 * factor))
         out[key + "_dispatches"] = len(fwd)
     out["calibration_factor"] = {"fetch": out["fetch_factor"], "write": out["write_factor"]}
-    with open(PROFILE_COUNTERS, "w") as f:
+    with open(PROFILE_COUNTERS_LARGE if large else PROFILE_COUNTERS, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
     print(json.dumps(out))
@@ -122,7 +127,7 @@ def ingest_counters(fetch_csv, write_csv):
 def main():
     args = parse()
     if args.ingest_counters:
-        ingest_counters(*args.ingest_counters)
+        ingest_counters(*args.ingest_counters, large=args.large_counters)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the map would be "
@@ -138,6 +143,28 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile_large:
+        lc = sg.large_config()
+        ls = rt.scene_from_mesh(lc.scene)
+        le = torch.tensor(lc.scene.eps_r, dtype=torch.float32, device=dev)
+        lg = torch.tensor(lc.scene.sigma, dtype=torch.float32, device=dev)
+        lo = torch.empty((1, lc.plane.H, lc.plane.W), dtype=torch.float32, device=dev)
+        if args.launch:
+            rt.rt_set_launch_config(ls, *[int(x) for x in args.launch.split(",")])
+        else:
+            rt.rt_tune(ls, le, lg, lc.tx, lc.plane, lc.params, 4_000_000, lo)
+        for _ in range(args.profile_large):
+            rt.rt_radio_map(ls, le, lg, lc.tx, lc.plane, lc.params, lo)
+        if args.calib_copy:
+            a = torch.empty(CALIB_COPY_BYTES // 4, dtype=torch.float32, device=dev)
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+        torch.cuda.synchronize()
+        inf = ls.info()
+        print(json.dumps({"profile_large": args.profile_large, "launch": "%d,%d,%d,%d,%d" % (
+            inf.tuned_width, inf.tuned_order, inf.tuned_block, inf.tuned_deposit, inf.tuned_refill)}))
+        return
     cfg = sg.manhattan_config()
     scene = rt.scene_from_mesh(cfg.scene)
     eps = torch.tensor(cfg.scene.eps_r, dtype=torch.float32, device=dev)
@@ -293,14 +320,14 @@ def rooflines(n_seg, n_cross, n_node, n_tri, width, kern_ms, traffic,
                           "note": note}}
 
 
-def traffic_from_profile():
+def traffic_from_profile(path=PROFILE_COUNTERS):
     try:
-        with open(PROFILE_COUNTERS) as f:
+        with open(path) as f:
             pc = json.load(f)
         if pc.get("kernel_source_sha") == kernel_source_sha():
             return {"fetch_bytes": pc["fetch_bytes_per_launch"], "write_bytes": pc["write_bytes_per_launch"],
                     "calibration_factor": pc.get("calibration_factor"),
-                    "source": os.path.relpath(PROFILE_COUNTERS, ROOT)}
+                    "source": os.path.relpath(path, ROOT)}
     except (OSError, KeyError, ValueError):
         pass
     return None
@@ -325,9 +352,16 @@ def large_leg(rt, sg, dev, args, reps=3):
     torch.cuda.synchronize()
     st = stats.cpu().numpy().astype(np.int64)
     t = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out), reps, 1)
-    r = rooflines(int(st[0]), int(st[1]), int(st[2]), int(st[3]), width, t, None,
+    tr = traffic_from_profile(PROFILE_COUNTERS_LARGE)
+    r = rooflines(int(st[0]), int(st[1]), int(st[2]), int(st[3]), width, t, tr,
                   note="tree + triangles about %d MB: larger than L2, partly held in the 256 MB MALL"
                   % (info.device_bytes >> 20))
+    if tr:
+        # measured bytes that crossed the fabric per launch, against the HBM peak
+        mb = tr["fetch_bytes"] + tr["write_bytes"]
+        r["hbm_model"]["measured_traffic"] = {"bytes_per_launch": mb, "GB/s": round(mb / (t * 1e-3) / 1e9, 1),
+                                              "frac": round(mb / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                              "source": tr["source"]}
     # early termination from depth 2: Russian roulette with p_max = 0.5
     import dataclasses
     prr = dataclasses.replace(cfg.params, rr_depth=2, rr_p_max=0.5, seed=1)
