@@ -1,4 +1,6 @@
-"""FP64 CPU oracle of the specular-only SBR radio map (test infrastructure).
+"""FP64 CPU oracle of the SBR radio map (test infrastructure): specular
+reflection by default; slab walls, refraction, diffuse reflection, transmit
+arrays and early termination on request.
 
 Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The HIP library never calls it.

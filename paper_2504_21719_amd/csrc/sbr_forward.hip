@@ -16,6 +16,11 @@
 //   3. unless the segment escaped or l = L, reflects specularly and updates
 //      the 2x2 field transfer matrix T (eq. fresnel_vac and the bases of
 //      eq. fresnel_in_vectors / eq. fresnel_out_vectors).
+// The extended variant (template flag EXT) adds, per hit, the single-layer
+// slab coefficients, the sampled interaction type (specular or diffuse
+// reflection, transmission) with its 1/sqrt(q) weight, and early
+// termination by Russian roulette or gain thresholding before the next
+// segment; its random draws come from a counter-based Philox4x32-10 stream.
 // Ray state (origin, direction, basis, T) stays in VGPRs for the whole ray.
 #include <hip/hip_runtime.h>
 
