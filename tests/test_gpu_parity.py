@@ -6,6 +6,7 @@ borders, per-crossing weights within 1e-5 relative, and per-cell maps within
 1e-3 relative for cells with >= 100 crossings (plus the border allowance).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -207,21 +208,60 @@ def test_manhattan_full_size_sampled():
             assert abs(float(g.weights[r_, l_]) - w_) <= 1e-5 * w_
 
 
+_LARGE = None
+
+
+def _large_chunk(be):
+    """Oracle on one ray range of the 1 M-triangle workload (process-pool worker)."""
+    cfg = _LARGE
+    return oracle.radio_map(cfg.scene, cfg.tx, cfg.plane, cfg.params, ray_begin=be[0], ray_end=be[1],
+                            want_records=True)
+
+
 def test_large_mesh_strided_rays():
     """~1.0 M-triangle terrain + buildings, full N_S = 1e8 lattice, L = 8:
-    a strided subset of rays (the oracle is brute force) matches ray by ray."""
+    40 chunks of 256 rays spread over the lattice (10,240 rays; the oracle is
+    brute force over every triangle, run on a process pool) match ray by ray:
+    hit sequences bit-exact except oracle-flagged rays (at most 2), crossing
+    cells equal away from cell borders, weights within 1e-5."""
+    import multiprocessing as mp
+    global _LARGE
     cfg = sg.large_config()
-    ids = np.arange(0, cfg.params.n_rays, cfg.params.n_rays // 96, dtype=np.int64)[1:] + 3
     s = gpu_scene(cfg.scene)
     info = s.info()
     assert info.n_triangles == cfg.scene.n_triangles
-    # GPU: trace exactly those rays (one call per ray; each is its own range)
-    hits = []
-    for n in ids:
-        g = gpu_radio_map(cfg, scene_handle=s, ray_begin=int(n), ray_end=int(n) + 1)
-        hits.append(g.hits[0])
-    hits = np.array(hits)
-    o = oracle.radio_map(cfg.scene, cfg.tx, cfg.plane, cfg.params, ray_ids=ids, want_hits=True)
-    rep, _ = compare_hits(hits, o.hits, o.flags, ids.size, max_frac=1.0)
+    starts = np.linspace(0, cfg.params.n_rays - 512, 40).astype(np.int64) // 64 * 64 + 5
+    chunks = [(int(b), int(b) + 256) for b in starts]
+    gh, gc, gw = [], [], []
+    for b, e in chunks:
+        g = gpu_radio_map(cfg, scene_handle=s, ray_begin=b, ray_end=e)
+        assert int(g.stats[4]) == 0
+        gh.append(g.hits)
+        gc.append(g.cells)
+        gw.append(g.weights)
+    hits, cells, weights = np.concatenate(gh), np.concatenate(gc), np.concatenate(gw)
+    _LARGE = cfg
+    oracle.lib()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        parts = pool.map(_large_chunk, chunks)
+    o_hits = np.concatenate([p.hits for p in parts])
+    o_flags = np.concatenate([p.flags for p in parts])
+    rep, bad = compare_hits(hits, o_hits, o_flags, hits.shape[0], max_frac=1.0)
     assert not rep["unexplained"], rep
-    assert rep["mismatched"] <= 1, rep
+    assert rep["mismatched"] <= 2, rep
+    ok = np.ones(hits.shape[0], bool)
+    ok[bad] = False
+    base = 0
+    n_checked = 0
+    for (b, e), p in zip(chunks, parts):
+        rec = p.records
+        for r_, l_, cell_, w_, bd_, len_ in zip(rec["ray"], rec["depth"], rec["cell"], rec["w"], rec["border"],
+                                               rec["length"]):
+            i = base + int(r_) - b
+            if not ok[i] or bd_ <= 1e-6 * (len_ + 3000.0):
+                continue
+            assert int(cells[i, l_]) == int(cell_), (r_, l_)
+            assert abs(float(weights[i, l_]) - w_) <= 1e-5 * w_, (r_, l_, weights[i, l_], w_)
+            n_checked += 1
+        base += e - b
+    assert n_checked > 1000
