@@ -103,3 +103,26 @@ def test_refraction_rejections():
     with pytest.raises(rt.RtError) as e:
         rt.rt_radio_map_batched(s, eps[None], sig[None], [cfg.tx], [10_000], cfg.plane, cfg.params, maps)
     assert e.value.status == rt.RT_EUNSUPPORTED
+
+
+def test_transparent_and_opaque_walls():
+    """Degenerate slabs on the GPU: a zero-thickness ground passes every ray
+    (the map is the empty scene's), a metal sheet reflects every ray (the map
+    is the half-space specular one); one ray and depth 0 also work."""
+    tx = sg.Tx((3.0, -2.0, 12.0))
+    pl = sg.Plane(1.5, -40.0, -40.0, 2.0, 2.0, 40, 40)
+    p = sg.Params(3.5e9, 200_000, 3, refraction=1, seed=3)
+    clear = sg.Config(sg.with_thickness(sg.ground_quad(100.0), [0.0]), tx, pl, p)
+    empty = sg.Config(sg.empty_scene(), tx, pl, sg.Params(3.5e9, 200_000, 3))
+    a, b = gpu_radio_map(clear), gpu_radio_map(empty)
+    np.testing.assert_allclose(a.map, b.map, rtol=1e-5, atol=0)
+    metal = sg.ground_quad(100.0, sg.METAL)
+    c = gpu_radio_map(sg.Config(sg.with_thickness(metal), tx, pl, p))
+    d = gpu_radio_map(sg.Config(metal, tx, pl, sg.Params(3.5e9, 200_000, 3)))
+    assert np.array_equal(c.hits, d.hits)
+    np.testing.assert_allclose(c.map, d.map, rtol=1e-5, atol=0)
+    one = _tiny()
+    one.params.n_rays, one.params.max_depth = 1, 0
+    g = gpu_radio_map(one)
+    o = oracle.radio_map(one.scene, one.tx, one.plane, one.params, want_hits=True)
+    assert np.array_equal(g.hits, o.hits)
