@@ -243,8 +243,10 @@ typedef struct {
      *   seed            key of the per-ray random stream (Philox4x32-10 at
      *                   counter (ray index, l))
      * ||E||^2 is the distance-normalised gain of polarisation 0 (times
-     * |alpha|^2 with a transmit array).  Not available with a tape or in
-     * rt_radio_map_batched (RT_EUNSUPPORTED). */
+     * |alpha|^2 with a transmit array).  A taped call records the surviving
+     * paths (a dropped path's tape ends at its last traced segment) for
+     * rt_radio_map_backward.  Not available in rt_radio_map_batched
+     * (RT_EUNSUPPORTED). */
     int32_t rr_depth;
     float rr_p_max;
     float gain_threshold;
@@ -327,7 +329,9 @@ rt_status rt_tape_destroy(rt_tape* tape);
  * eq. eta (d eta/d eps_r = 1, d eta/d sigma = -j/(eps0 omega)) and
  * eq. rotation; with slab walls, eq. fresnel_slab (quotient and chain rules
  * through x = exp(-j q)); with refraction, the sampled branch (a transmitted
- * segment keeps its direction) with its probability held constant.  Partial
+ * segment keeps its direction) with its probability held constant; with
+ * Russian roulette, the surviving paths with their 1/sqrt(p) factors, p held
+ * constant (the factor is recovered from the taped transfer matrices).  Partial
  * sums are reduced in a fixed order, so results are run-to-run
  * deterministic.
  * Errors: RT_EINVAL if the tape was not filled by a matching forward call;

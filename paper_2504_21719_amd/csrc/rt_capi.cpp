@@ -261,6 +261,9 @@ static uint64_t call_key(const rt_scene* s, rt_materials m, const rt_tx* tx, con
     h = mix(h, &m.thickness, sizeof(m.thickness));
     h = mix(h, &p->refraction, sizeof(int32_t));
     h = mix(h, &p->seed, sizeof(uint32_t));
+    h = mix(h, &p->rr_depth, sizeof(int32_t));
+    h = mix(h, &p->rr_p_max, sizeof(float));
+    h = mix(h, &p->gain_threshold, sizeof(float));
     h = mix(h, tx, sizeof(rt_tx));
     h = mix(h, pl, sizeof(rt_plane));
     h = mix(h, &p->freq_hz, sizeof(double));
@@ -375,8 +378,6 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
         const double lam = RT_C0 / params->freq_hz;
         f.gain_scale = (float)(lam * lam / (16.0 * RT_PI * RT_PI));
     }
-    if (tape && (f.rr_p_max > 0.0f || f.gain_threshold > 0.0f))
-        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map: early termination cannot be recorded on a tape");
     f.thickness = materials.thickness;
     f.scattering = materials.scattering;
     f.xpd = materials.xpd;
@@ -473,6 +474,8 @@ extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials m
     bl.thickness = materials.thickness;
     bl.refraction = params->refraction;
     bl.k0 = (float)(2.0 * RT_PI * params->freq_hz / RT_C0);
+    bl.rr_depth = std::max(1, params->rr_depth);
+    bl.rr_p_max = params->rr_p_max;
     return rt_launch_backward(bl, (hipStream_t)stream);
 }
 

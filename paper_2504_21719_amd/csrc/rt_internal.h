@@ -205,6 +205,8 @@ struct BwdLaunch {
     const float* thickness;  // slab thickness per material (m), or null
     int32_t refraction;
     float k0;                // 2 pi / lambda
+    int32_t rr_depth;        // Russian roulette in the forward before segments l >= rr_depth
+    float rr_p_max;          // (0 = off)
 };
 rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st);
 

@@ -63,6 +63,8 @@ struct BwdArgs {
     const float* thickness;  // slab thickness per material (m), or null
     int refraction;          // 1: the forward sampled reflection or transmission
     float k0;                // 2 pi / lambda
+    int rr_depth;            // Russian roulette before segments l >= rr_depth
+    float rr_p_max;          // (0 = off)
 };
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -142,6 +144,22 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                         dkpe = cscale(transmit ? dtp : F.drperp, sc);
                         dkpa = cscale(transmit ? dtl : F.drpar, sc);
                     }
+                }
+                if (a.rr_p_max > 0.0f && l >= a.rr_depth) {
+                    // a surviving path carries 1/sqrt(p), p held constant: the
+                    // factor is the ratio of the recorded T_l to R_l T_{l-1}
+                    const cf x0 = cadd(cscale(cf{p2.x, p2.y}, b.w00), cscale(cf{p3.x, p3.y}, b.w01));
+                    const cf x1 = cadd(cscale(cf{p2.z, p2.w}, b.w00), cscale(cf{p3.z, p3.w}, b.w01));
+                    const cf y0 = cadd(cscale(cf{p2.x, p2.y}, b.w10), cscale(cf{p3.x, p3.y}, b.w11));
+                    const cf y1 = cadd(cscale(cf{p2.z, p2.w}, b.w10), cscale(cf{p3.z, p3.w}, b.w11));
+                    const float pre = cabs2(kpe) * (cabs2(x0) + cabs2(x1)) + cabs2(kpa) * (cabs2(y0) + cabs2(y1));
+                    const float rec = s2.x * s2.x + s2.y * s2.y + s2.z * s2.z + s2.w * s2.w + s3.x * s3.x +
+                                      s3.y * s3.y + s3.z * s3.z + s3.w * s3.w;
+                    const float sc = pre > 0.0f ? sqrtf(rec / pre) : 1.0f;
+                    kpe = cscale(kpe, sc);
+                    kpa = cscale(kpa, sc);
+                    dkpe = cscale(dkpe, sc);
+                    dkpa = cscale(dkpa, sc);
                 }
                 // u = W E_{l-1}
                 cf f0 = cadd(cscale(cf{p2.x, p2.y}, ct), cscale(cf{p2.z, p2.w}, cp));
@@ -249,6 +267,8 @@ rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
     a.thickness = b.thickness;
     a.refraction = b.refraction;
     a.k0 = b.k0;
+    a.rr_depth = b.rr_depth;
+    a.rr_p_max = b.rr_p_max;
     a.grad_map = b.grad_map;
     a.map_stride = (int64_t)b.pl.W * b.pl.H;
     a.n_mat = s->n_mat;

@@ -694,7 +694,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                             drop = true;
                         }
                     }
-                    if (drop) active = false;
+                    if (drop) {
+                        active = false;
+                        if (a.tape_nseg) a.tape_nseg[rid] = l;   // segments 0..l-1 were traced
+                    }
                 }
             }
         }
