@@ -59,6 +59,9 @@
  * quotient rule on eq. fresnel_vac with d(eta)/d(eps_r) = 1 and
  * d(eta)/d(sigma) = -j/(eps0 omega) from eq. eta; transmitter-angle
  * derivatives use dual numbers through eq. rotation and eq. theta_phi_prime.
+ * Sampling probabilities (interaction type, Russian roulette) are held
+ * constant.  At a diffuse point the tangent includes the change of Gamma^2,
+ * which depends on the coefficients and on the incident field itself.
  *
  * Readings where the paper is silent (stated once here, used throughout):
  *   - by default only specular reflection is enabled, so q(R) = 1 and
@@ -584,7 +587,6 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                 if (pp[0] == 2.0 && !(pp[2] >= 1.0 && pp[2] <= 64.0 && pp[2] == floor(pp[2]) &&
                                       pp[3] >= 0.0 && pp[3] <= 1.0)) return 1;
             }
-        if (out->grad_map && out->grad) return 1;
     }
     for (int64_t i = 0; i < n_tri; i++) {
         for (int j = 0; j < 3; j++)
@@ -805,6 +807,34 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                     /* 2 pi f_s S^2 Gamma^2 / q(S) */
                     double fs = scatter_pattern(pattern ? pattern + 4 * (int64_t)m : NULL, k, k_new, nrm, kr);
                     double sc = sqrt(2.0 * OR_PI * fs * Sm * Sm * g2) * inv_sqrt_q;
+                    if (want_grad) {
+                        /* E' = sc(E, eta) X P E with sc^2 = cf Gamma^2 and cf =
+                         * 2 pi f_s S^2 / q(S) held constant: dE' = dsc X P E +
+                         * sc X P dE, where dGamma^2 takes both the change of
+                         * the coefficients (d eta) and of the incident field
+                         * (Gamma^2 is a ratio of its powers) */
+                        const double cf = 2.0 * OR_PI * fs * Sm * Sm / qk;
+                        for (int q = 0; q < P; q++) {
+                            const cvec3 dq = dE[p][q];
+                            cplx deta = 0.0;
+                            if (q == m) deta = 1.0;
+                            else if (q == n_mat + m) deta = deta_dsigma;
+                            const cplx dap = r_perp * cv_dot_real(e_perp, dq) + dr_perp * deta * a_perp;
+                            const cplx dal = r_par * cv_dot_real(e_par, dq) + dr_par * deta * a_par;
+                            double dg2 = 0.0;
+                            if (en2 > 0.0)
+                                dg2 = (2.0 * creal(conj(r_perp * a_perp) * dap) + 2.0 * creal(conj(r_par * a_par) * dal) -
+                                       g2 * 2.0 * cv_re_inner(E[p], dq)) / en2;
+                            const double dsc = sc > 0.0 ? cf * dg2 / (2.0 * sc) : 0.0;
+                            const cplx dth = cv_dot_real(thi, dq), dph = cv_dot_real(phi_i, dq);
+                            const cplx dsth = e1 * (sqrt(1.0 - K) * dth - sqrt(K) * dph);
+                            const cplx dsph = e2 * (sqrt(K) * dth + sqrt(1.0 - K) * dph);
+                            cvec3 nd = cv_zero();
+                            nd = cv_axpy(nd, dsc * sth + sc * dsth, ths);
+                            nd = cv_axpy(nd, dsc * sph + sc * dsph, phs_v);
+                            dE[p][q] = nd;
+                        }
+                    }
                     cvec3 En = cv_zero();
                     En = cv_axpy(En, sc * sth, ths);
                     En = cv_axpy(En, sc * sph, phs_v);

@@ -12,6 +12,11 @@ eq. path-solver-used-dist-event with R = sqrt(1 - S^2), eq. R).
   ground -> ceiling -> plane paths weigh |r_par|^2 (K_x = 0) or |r_perp|^2
   (K_x = 1) of the ceiling, against the same integral seen from the image of
   the plane point, and every crossing for K_x = 1/2 is the mean of the two.
+* Gradients: over a fully diffuse ground an H-polarised crossing weighs
+  Gamma^2 = |r_perp|^2 of its incidence angle, so d w = w d ln|r_perp|^2 from
+  eq. fresnel; on a two-material scene without refraction the draws do not
+  depend on the parameters and the forward-mode gradient equals central
+  differences of the oracle's own map.
 * Shares: with S = 0.6 a ray reflects specularly iff its draw is below
   q(R) = 1 - S^2, and then its weights equal those of a non-diffuse ground
   (R^2 / q(R) = 1); S = 0 changes nothing.
@@ -130,9 +135,6 @@ def test_diffuse_inputs_validated(oracle_lib):
     for S, K in ((1.5, 0.0), (0.5, -0.1), (0.5, 2.0)):
         with pytest.raises(ValueError):
             oracle_lib.radio_map(sg.with_diffuse(cfg.scene, S, K), cfg.tx, cfg.plane, cfg.params)
-    with pytest.raises(ValueError):          # no adjoint of the diffuse bounce
-        oracle_lib.radio_map(sg.with_diffuse(cfg.scene, 0.5), cfg.tx, cfg.plane, cfg.params,
-                             grad_map=np.ones((1, cfg.plane.H, cfg.plane.W)))
     with pytest.raises(ValueError):          # Gamma depends on the field: one polarisation only
         oracle_lib.radio_map(sg.with_diffuse(cfg.scene, 0.5), sg.Tx((0.0, 0.0, 10.0), pol=sg.POL_DUAL),
                              cfg.plane, cfg.params)
@@ -201,3 +203,67 @@ def test_directive_ground_matches_scattering_integral(oracle_lib, pp):
     z = (s1 - ref) / np.sqrt(s2)
     assert n.min() >= 100 and np.abs(z).max() <= 4.5, np.abs(z).max()
     assert abs(s1.sum() / ref.sum() - 1) <= 5e-3, s1.sum() / ref.sum()
+
+
+def _dlog_rperp2(eps, sig, cos_t, which, h=1e-6):
+    """d ln|r_perp|^2 / d eps_r (which = 0) or d sigma (which = 1), eq. fresnel,
+    central differences."""
+    def r2(e, g):
+        return np.abs(cf.fresnel_general(cf.eta(e, g, FREQ), cos_t)[0]) ** 2
+    if which == 0:
+        return (r2(eps + h, sig) - r2(eps - h, sig)) / (2 * h * r2(eps, sig))
+    return (r2(eps, sig + h) - r2(eps, sig - h)) / (2 * h * r2(eps, sig))
+
+
+def test_diffuse_gradient_of_a_single_scatter(oracle_lib):
+    """H-pol over a fully diffuse ground (S = 1, so q(S) = 1) is pure TE:
+    a depth-1 crossing weighs w = kappa 2 pi f_s Gamma^2 ||E||^2 / |k_z'| with
+    Gamma^2 = |r_perp|^2 at the launch angle; the cross-polarisation matrix
+    (K_x = 0.3) is unitary and the draws are fixed, so dw = w d ln|r_perp|^2."""
+    tx = sg.Tx((0.0, 0.0, 10.0), pol=sg.POL_H)
+    pl = sg.Plane(1.5, -30.0, -30.0, 4.0, 4.0, 15, 15)
+    N = 200_000
+    g = sg.with_diffuse(sg.ground_quad(100.0), 1.0, 0.3)
+    r = oracle_lib.radio_map(g, tx, pl, sg.Params(FREQ, N, 1, seed=8), want_records=True,
+                             grad_map=np.ones((1, pl.H, pl.W)))
+    sel = r.records["depth"] == 1
+    assert sel.sum() > 1000
+    kz = np.abs(np.array([oracle_lib.lattice(n, N)[2] for n in r.records["ray"][sel]]))
+    w = r.records["w"][sel]
+    for which in (0, 1):
+        expect = np.sum(w * _dlog_rperp2(*sg.CONCRETE, kz, which))
+        assert r.grad[which] == pytest.approx(expect, rel=2e-5), (which, r.grad[which], expect)
+
+
+def test_diffuse_gradient_matches_central_differences(oracle_lib):
+    """Ground (concrete, S = 0.7, K_x = 0.25) and a box (glass, S = 0.4,
+    K_x = 0.1), directional V-pol source at yaw/pitch/roll (0.3, 0.2, -0.1),
+    depth 3, no refraction: q(R) = 1 - S^2 and q(S) = S^2, the draws and the
+    directions do not depend on (eps_r, sigma, yaw, pitch, roll), so
+    sum(G * map) is smooth in them.  The forward-mode gradient, which carries
+    the field dependence of Gamma^2 through every diffuse point, must equal
+    FP64 central differences of the map along two random directions."""
+    import dataclasses
+    mb = sg._MeshBuilder()
+    mb.quad((-100.0, -100.0, 0.0), (100.0, -100.0, 0.0), (100.0, 100.0, 0.0), (-100.0, 100.0, 0.0), 0)
+    mb.box((30.0, -10.0, 0.0), (50.0, 10.0, 30.0), 1, bottom=False)
+    scene = sg.with_diffuse(mb.build([sg.CONCRETE, sg.GLASS], "ground+box"), [0.7, 0.4], [0.25, 0.1])
+    pl = sg.Plane(1.5, -100.0, -100.0, 4.0, 4.0, 50, 50)
+    prm = sg.Params(FREQ, 20_000, 3, seed=21)
+    rng = np.random.default_rng(5)
+    G = rng.standard_normal((1, pl.H, pl.W))
+    theta0 = np.array([*scene.eps_r, *scene.sigma, 0.3, 0.2, -0.1])
+
+    def run(theta, grad=False):
+        sc = dataclasses.replace(scene, eps_r=theta[0:2].copy(), sigma=theta[2:4].copy())
+        tx = sg.Tx((0.0, 0.0, 10.0), yaw=theta[4], pitch=theta[5], roll=theta[6],
+                   pattern=sg.PATTERN_DIRECTIONAL)
+        return oracle_lib.radio_map(sc, tx, pl, prm, grad_map=G if grad else None)
+
+    res = run(theta0, grad=True)
+    assert res.map[0, :, :].sum() > 0
+    for _ in range(2):
+        v = rng.uniform(-1.0, 1.0, theta0.size) * np.maximum(np.abs(theta0), 0.1)
+        h = 1e-4
+        fd = (np.sum(G * run(theta0 + h * v).map) - np.sum(G * run(theta0 - h * v).map)) / (2 * h)
+        assert res.grad @ v == pytest.approx(fd, rel=1e-5), (res.grad @ v, fd)
