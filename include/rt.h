@@ -132,8 +132,9 @@ rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
  * theta/phi bases of the two directions, mixed by the matrix of
  * eq. scattered_field with phases 2 pi times words 2 and 3, times
  * sqrt(2 cos(theta_s) S^2 Gamma^2 / q(S)).  One polarisation per call
- * (Gamma depends on the field): dual polarisation, a tape and
- * rt_radio_map_batched give RT_EUNSUPPORTED.  Entries outside [0, 1] give
+ * (Gamma depends on the field): dual polarisation and rt_radio_map_batched
+ * give RT_EUNSUPPORTED.  A taped call is differentiable: the backward takes
+ * the same scattering and xpd arrays.  Entries outside [0, 1] give
  * undefined results.
  * scatter_pattern (optional, needs scattering; NULL = Lambertian for every
  * material): device float32 [n_materials][4] = (kind, alpha_R, alpha_I,
@@ -331,11 +332,15 @@ rt_status rt_tape_destroy(rt_tape* tape);
  * through x = exp(-j q)); with refraction, the sampled branch (a transmitted
  * segment keeps its direction) with its probability held constant; with
  * Russian roulette, the surviving paths with their 1/sqrt(p) factors, p held
- * constant (the factor is recovered from the taped transfer matrices).  Partial
+ * constant (the factor is recovered from the taped transfer matrices); with
+ * diffuse reflection, eq. scattered_field with the direction and phases
+ * redrawn from the forward's streams, q(S) held constant and Gamma^2
+ * differentiated through both the coefficients and the incident field.  Partial
  * sums are reduced in a fixed order, so results are run-to-run
  * deterministic.
- * Errors: RT_EINVAL if the tape was not filled by a matching forward call;
- * RT_EUNSUPPORTED with diffuse reflection.
+ * Errors: RT_EINVAL if the tape was not filled by a matching forward call
+ * (same scene, material arrays including thickness, scattering and xpd,
+ * transmitter, plane and parameters).
  */
 rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials materials,
                                 const rt_tx* tx, const rt_plane* plane,

@@ -284,14 +284,16 @@ def rt_tape_create(params, **pkw) -> RtTape:
 
 
 def rt_radio_map_backward(scene: RtScene, eps_r, sigma, tx, plane, params, tape: RtTape, grad_map,
-                          grad_eps_r=None, grad_sigma=None, grad_orient=None, stream=None, thickness=None, **pkw):
+                          grad_eps_r=None, grad_sigma=None, grad_orient=None, stream=None, thickness=None,
+                          scattering=None, xpd=None, scatter_pattern=None, **pkw):
     """Adjoint of a forward call recorded on ``tape`` (same materials,
-    thickness, transmitter, plane and parameters)."""
+    thickness, scattering, transmitter, plane and parameters)."""
     p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
     t = tx if isinstance(tx, rt_tx) else make_tx(tx)
     pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
-    _check(lib().rt_radio_map_backward(scene.handle, materials(eps_r, sigma, thickness), C.byref(t), C.byref(pl),
-                                       C.byref(p),
+    _check(lib().rt_radio_map_backward(scene.handle, materials(eps_r, sigma, thickness, scattering, xpd,
+                                                                   scatter_pattern),
+                                       C.byref(t), C.byref(pl), C.byref(p),
                                        tape.handle, _ptr(grad_map), _ptr(grad_eps_r), _ptr(grad_sigma),
                                        _ptr(grad_orient), _stream(stream)))
 

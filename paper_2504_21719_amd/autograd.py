@@ -21,10 +21,12 @@ from . import RtScene, make_params, rt_radio_map, rt_radio_map_backward, rt_tape
 
 class RadioMapFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, eps_r, sigma, orient, scene: RtScene, tx, plane, params, thickness=None):
+    def forward(ctx, eps_r, sigma, orient, scene: RtScene, tx, plane, params, thickness=None, scattering=None,
+                xpd=None, scatter_pattern=None):
         """eps_r, sigma: device f32 [n_mat]; orient: (yaw, pitch, roll), any
-        device; thickness: optional device f32 [n_mat] slab thickness (not
-        differentiated)."""
+        device; thickness: optional device f32 [n_mat] slab thickness;
+        scattering, xpd (and scatter_pattern): optional diffuse reflection
+        (none of these four is differentiated)."""
         ypr = [float(v) for v in orient.detach().cpu().tolist()]
         txo = dataclasses.replace(tx, yaw=ypr[0], pitch=ypr[1], roll=ypr[2])
         npol = 2 if int(tx.pol) == 2 else 1
@@ -32,26 +34,30 @@ class RadioMapFn(torch.autograd.Function):
         p = make_params(params)
         need_grad = any(ctx.needs_input_grad[:3])
         tape = rt_tape_create(p) if need_grad else None
+        diffuse = dict(scattering=scattering, xpd=xpd, scatter_pattern=scatter_pattern)
         rt_radio_map(scene, eps_r.contiguous(), sigma.contiguous(), txo, plane, p, out, tape=tape,
-                     thickness=thickness)
+                     thickness=thickness, **diffuse)
         ctx.save_for_backward(eps_r, sigma)
-        ctx.state = (scene, txo, plane, p, tape, orient.device, orient.dtype, thickness)
+        ctx.state = (scene, txo, plane, p, tape, orient.device, orient.dtype, thickness, diffuse)
         return out
 
     @staticmethod
     def backward(ctx, grad_map):
         eps_r, sigma = ctx.saved_tensors
-        scene, txo, plane, p, tape, odev, odt, thickness = ctx.state
+        scene, txo, plane, p, tape, odev, odt, thickness, diffuse = ctx.state
         n_mat = eps_r.shape[0]
         ge = torch.empty(n_mat, dtype=torch.float32, device=eps_r.device)
         gs = torch.empty(n_mat, dtype=torch.float32, device=eps_r.device)
         go = torch.empty(3, dtype=torch.float32, device=eps_r.device)
         rt_radio_map_backward(scene, eps_r.contiguous(), sigma.contiguous(), txo, plane, p, tape,
-                              grad_map.contiguous().to(torch.float32), ge, gs, go, thickness=thickness)
-        return ge, gs, go.to(device=odev, dtype=odt), None, None, None, None, None
+                              grad_map.contiguous().to(torch.float32), ge, gs, go, thickness=thickness,
+                              **diffuse)
+        return (ge, gs, go.to(device=odev, dtype=odt)) + (None,) * 8
 
 
-def radio_map(eps_r, sigma, orient, scene, tx, plane, params, thickness=None):
+def radio_map(eps_r, sigma, orient, scene, tx, plane, params, thickness=None, scattering=None, xpd=None,
+              scatter_pattern=None):
     """Differentiable radio map [npol][H][W] (slab walls and refraction with a
-    thickness tensor)."""
-    return RadioMapFn.apply(eps_r, sigma, orient, scene, tx, plane, params, thickness)
+    thickness tensor, diffuse reflection with scattering and xpd tensors)."""
+    return RadioMapFn.apply(eps_r, sigma, orient, scene, tx, plane, params, thickness, scattering, xpd,
+                            scatter_pattern)

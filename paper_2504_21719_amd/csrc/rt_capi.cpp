@@ -259,6 +259,8 @@ static uint64_t call_key(const rt_scene* s, rt_materials m, const rt_tx* tx, con
     h = mix(h, &m.eps_r, sizeof(m.eps_r));
     h = mix(h, &m.sigma, sizeof(m.sigma));
     h = mix(h, &m.thickness, sizeof(m.thickness));
+    h = mix(h, &m.scattering, sizeof(m.scattering));
+    h = mix(h, &m.xpd, sizeof(m.xpd));
     h = mix(h, &p->refraction, sizeof(int32_t));
     h = mix(h, &p->seed, sizeof(uint32_t));
     h = mix(h, &p->rr_depth, sizeof(int32_t));
@@ -343,9 +345,8 @@ extern "C" rt_status rt_radio_map(const rt_scene* scene, rt_materials materials,
               "rt_radio_map: scattering and xpd must both be given or both be NULL");
     CHECK_ARG(!materials.scatter_pattern || materials.scattering,
               "rt_radio_map: scatter_pattern needs scattering and xpd");
-    if (materials.scattering && (tape || tx->pol == RT_POL_DUAL))
-        return rt_fail(RT_EUNSUPPORTED,
-                       "rt_radio_map: diffuse reflection takes one polarisation and cannot be recorded on a tape");
+    if (materials.scattering && tx->pol == RT_POL_DUAL)
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map: diffuse reflection takes one polarisation");
     if ((r = check_device(scene)) != RT_OK) return r;
     FwdLaunch f{};
     f.scene = scene;
@@ -445,8 +446,6 @@ extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials m
                                            float* grad_sigma, float* grad_orient, void* stream) {
     CHECK_ARG(scene != nullptr, "rt_radio_map_backward: scene is NULL");
     CHECK_ARG(tape != nullptr, "rt_radio_map_backward: tape is NULL");
-    if (materials.scattering)
-        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_backward: diffuse reflection has no adjoint here");
     CHECK_ARG(grad_map != nullptr, "rt_radio_map_backward: grad_map is NULL");
     CHECK_ARG(materials.eps_r && materials.sigma, "rt_radio_map_backward: material pointers are NULL");
     rt_status r;
@@ -476,6 +475,9 @@ extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials m
     bl.k0 = (float)(2.0 * RT_PI * params->freq_hz / RT_C0);
     bl.rr_depth = std::max(1, params->rr_depth);
     bl.rr_p_max = params->rr_p_max;
+    bl.scattering = materials.scattering;
+    bl.xpd = materials.xpd;
+    bl.seed = params->seed;
     return rt_launch_backward(bl, (hipStream_t)stream);
 }
 

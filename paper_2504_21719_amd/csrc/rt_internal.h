@@ -207,6 +207,9 @@ struct BwdLaunch {
     float k0;                // 2 pi / lambda
     int32_t rr_depth;        // Russian roulette in the forward before segments l >= rr_depth
     float rr_p_max;          // (0 = off)
+    const float* scattering; // diffuse reflection: S and K_x per material, or null
+    const float* xpd;
+    uint32_t seed;           // key of the forward's random streams
 };
 rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st);
 

@@ -65,6 +65,9 @@ struct BwdArgs {
     float k0;                // 2 pi / lambda
     int rr_depth;            // Russian roulette before segments l >= rr_depth
     float rr_p_max;          // (0 = off)
+    const float* scattering; // diffuse reflection: S and K_x per material, or null
+    const float* xpd;
+    unsigned seed;           // key of the forward's random streams
 };
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -126,6 +129,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 // change) divided by sqrt(q), the sampling probability held
                 // constant
                 cf kpe = F.rperp, kpa = F.rpar, dkpe = F.drperp, dkpa = F.drpar;
+                const bool transmit = a.refraction && s0.x == p0.x && s0.y == p0.y && s0.z == p0.z;
                 if (a.thickness) {
                     cf tp, tl, dtp, dtl;
                     slab_grad(F, a.k0 * a.thickness[mat], tp, tl, dtp, dtl);
@@ -136,7 +140,6 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                     if (a.refraction) {
                         const float ar = cabs2(F.rperp) + cabs2(F.rpar), at = cabs2(tp) + cabs2(tl);
                         const float tot = ar + at;
-                        const bool transmit = s0.x == p0.x && s0.y == p0.y && s0.z == p0.z;
                         const float q = transmit ? (tot > 0.0f ? at / tot : 0.0f) : (tot > 0.0f ? ar / tot : 1.0f);
                         const float sc = __builtin_amdgcn_rsqf(q);
                         kpe = cscale(transmit ? tp : F.rperp, sc);
@@ -145,7 +148,24 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                         dkpa = cscale(transmit ? dtl : F.drpar, sc);
                     }
                 }
-                if (a.rr_p_max > 0.0f && l >= a.rr_depth) {
+                // a diffuse reflection: the taped direction of segment l is
+                // the one drawn from stream 2 at this interaction (a specular
+                // direction meets it with probability ~1e-9)
+                bool diffuse = false;
+                float dc1 = 0.f, ds1 = 0.f, dc2 = 0.f, ds2 = 0.f;
+                if (a.scattering && !transmit && a.scattering[mat] > 0.0f) {
+                    const uint4 w = philox4(a.seed, ray, l - 1, 2u);
+                    const float cs = word_uniform(w.x), ss = sqrtf(fmaxf(0.0f, 1.0f - cs * cs));
+                    float sph, cph;
+                    sincospif(2.0f * word_uniform(w.y), &sph, &cph);
+                    float3 nd = f3(nm.x, nm.y, nm.z);
+                    if (dot3(f3(p0.x, p0.y, p0.z), nd) > 0.0f) nd = nd * -1.0f;
+                    const float3 kd = diffuse_direction(nd, cs, ss, cph, sph) - f3(s0.x, s0.y, s0.z);
+                    diffuse = dot3(kd, kd) < 1e-8f;
+                    sincospif(2.0f * word_uniform(w.z), &ds1, &dc1);
+                    sincospif(2.0f * word_uniform(w.w), &ds2, &dc2);
+                }
+                if (!diffuse && a.rr_p_max > 0.0f && l >= a.rr_depth) {
                     // a surviving path carries 1/sqrt(p), p held constant: the
                     // factor is the ratio of the recorded T_l to R_l T_{l-1}
                     const cf x0 = cadd(cscale(cf{p2.x, p2.y}, b.w00), cscale(cf{p3.x, p3.y}, b.w01));
@@ -167,6 +187,63 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 cf u0 = cadd(cscale(f0, b.w00), cscale(f1, b.w01));
                 cf u1 = cadd(cscale(f0, b.w10), cscale(f1, b.w11));
                 int j = mat - a.mat0;
+                if (diffuse) {
+                    // E_l = sc N E with N = diag(x1, x2) [[ck, -sk], [sk, ck]] P
+                    // unitary and sc^2 = c Gamma^2, Gamma^2 = ||D W E||^2 / ||E||^2
+                    // (c, and a roulette factor, held constant).  Then
+                    //   dL = 2 Re(lambda^H sc N dE) + (nu / Gamma^2) dGamma^2,
+                    // nu = Re(lambda^H E_l), dGamma^2 = 2 Re((Q E - Gamma^2 E)^H dE) /
+                    // ||E||^2 + 2 Re(Z d eta), Q = W^T |D|^2 W,
+                    // Z = (conj(r_perp) dr_perp |u_0|^2 + conj(r_par) dr_par |u_1|^2) / ||E||^2
+                    const float en2 = cabs2(f0) + cabs2(f1);
+                    const float rp2 = cabs2(F.rperp), rl2 = cabs2(F.rpar);
+                    const float g2 = en2 > 0.0f ? (rp2 * cabs2(u0) + rl2 * cabs2(u1)) / en2 : 0.0f;
+                    const float tp = p2.x * p2.x + p2.y * p2.y + p2.z * p2.z + p2.w * p2.w + p3.x * p3.x +
+                                     p3.y * p3.y + p3.z * p3.z + p3.w * p3.w;
+                    const float tl = s2.x * s2.x + s2.y * s2.y + s2.z * s2.z + s2.w * s2.w + s3.x * s3.x +
+                                     s3.y * s3.y + s3.z * s3.z + s3.w * s3.w;
+                    if (g2 > 0.0f && tp > 0.0f) {
+                        const float sc = sqrtf(tl / tp);   // ||N T||_F = ||T||_F
+                        const cf el0 = cadd(cscale(cf{s2.x, s2.y}, ct), cscale(cf{s2.z, s2.w}, cp));
+                        const cf el1 = cadd(cscale(cf{s3.x, s3.y}, ct), cscale(cf{s3.z, s3.w}, cp));
+                        const float nu = cmulc(lam0, el0).re + cmulc(lam1, el1).re;
+                        const float ig = nu / g2;
+                        if (j >= 0 && j < kMatChunk) {
+                            const cf Z = cscale(cadd(cscale(cmulc(F.rperp, F.drperp), cabs2(u0)),
+                                                     cscale(cmulc(F.rpar, F.drpar), cabs2(u1))),
+                                                1.0f / en2);
+#pragma unroll
+                            for (int jj = 0; jj < kMatChunk; jj++) {
+                                if (jj == j) {
+                                    ge[jj] += 2.0f * ig * Z.re;
+                                    gs[jj] += 2.0f * ig * Z.im * a.pl.inv_eps0_omega;
+                                }
+                            }
+                        }
+                        // N from the incident basis (es, k x es) to (theta, phi)
+                        const float3 kk = f3(p0.x, p0.y, p0.z), es = f3(p1.x, p1.y, p1.z);
+                        float3 thi, phi_i;
+                        sph_basis(kk, thi, phi_i);
+                        const float3 ep = cross3(kk, es);
+                        const float p00 = dot3(thi, es), p01 = dot3(thi, ep);
+                        const float p10 = dot3(phi_i, es), p11 = dot3(phi_i, ep);
+                        const float K = a.xpd[mat], sk = sqrtf(K), ck = sqrtf(1.0f - K);
+                        const float a0 = ck * p00 - sk * p10, a1 = ck * p01 - sk * p11;
+                        const float b0 = sk * p00 + ck * p10, b1 = sk * p01 + ck * p11;
+                        // v = conj(diag(x1, x2)) lambda, then sc [[a0, b0], [a1, b1]] v
+                        const cf v0 = cmulc(cf{dc1, ds1}, lam0), v1 = cmulc(cf{dc2, ds2}, lam1);
+                        const float h = ig / en2;
+                        // (Q E - Gamma^2 E) with Q E = W^T (|r_perp|^2 u0, |r_par|^2 u1)
+                        const cf q0 = cadd(cscale(u0, rp2 * b.w00), cscale(u1, rl2 * b.w10));
+                        const cf q1 = cadd(cscale(u0, rp2 * b.w01), cscale(u1, rl2 * b.w11));
+                        lam0 = cadd(cscale(cadd(cscale(v0, a0), cscale(v1, b0)), sc), cscale(csub(q0, cscale(f0, g2)), h));
+                        lam1 = cadd(cscale(cadd(cscale(v0, a1), cscale(v1, b1)), sc), cscale(csub(q1, cscale(f1, g2)), h));
+                    } else {
+                        lam0 = cf{0.0f, 0.0f};
+                        lam1 = cf{0.0f, 0.0f};
+                    }
+                    continue;
+                }
                 if (j >= 0 && j < kMatChunk) {
                     // z = lambda^H dD/deta u, dD/deta = diag(dr_perp, -dr_par)
                     cf z = csub(cmulc(lam0, cmul(dkpe, u0)), cmulc(lam1, cmul(dkpa, u1)));
@@ -269,6 +346,9 @@ rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
     a.k0 = b.k0;
     a.rr_depth = b.rr_depth;
     a.rr_p_max = b.rr_p_max;
+    a.scattering = b.scattering;
+    a.xpd = b.xpd;
+    a.seed = b.seed;
     a.grad_map = b.grad_map;
     a.map_stride = (int64_t)b.pl.W * b.pl.H;
     a.n_mat = s->n_mat;

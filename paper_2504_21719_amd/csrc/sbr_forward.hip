@@ -133,38 +133,6 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011), written from its
-// definition: ten rounds, each multiplying words 0 and 2 by two odd constants,
-// keeping the low halves and XORing the high halves with words 1, 3 and the
-// round key, which advances by two Weyl constants.  Counter (n_lo, n_hi, l,
-// stream), key (seed, 0); stream 0 decides early termination before segment
-// l, stream 1 the interaction type at the end of segment l, stream 2 the
-// direction and phases of a diffuse reflection there.
-__device__ __forceinline__ uint4 philox4(unsigned seed, int64_t n, int l, unsigned stream) {
-    unsigned c0 = (unsigned)((uint64_t)n & 0xffffffffu), c1 = (unsigned)((uint64_t)n >> 32), c2 = (unsigned)l,
-             c3 = stream;
-    unsigned k0 = seed, k1 = 0u;
-#pragma unroll
-    for (int round = 0; round < 10; round++) {
-        const unsigned lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const unsigned lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        c0 = hi1 ^ c1 ^ k0;
-        c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return make_uint4(c0, c1, c2, c3);
-}
-
-// Uniform in [0, 1) from the top 24 bits of a word (exact in FP32).
-__device__ __forceinline__ float word_uniform(unsigned w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
-
-__device__ __forceinline__ float philox_uniform(unsigned seed, int64_t n, int l, unsigned stream) {
-    return word_uniform(philox4(seed, n, l, stream).x);
-}
-
 // Per-lane traversal stack: the first RT_STACK_LDS entries {node, entry
 // distance} live in LDS, laid out [entry][lane] (8 bytes each, so a
 // wavefront's pushes are contiguous); deeper entries (node only) go to a
