@@ -99,9 +99,22 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
             const float ct = cth.v, cp = cph.v;
             const float* G = a.grad_map + (int64_t)p * a.map_stride;
             cf lam0 = {0, 0}, lam1 = {0, 0};
+            // records of segment l (s*) and of segment l-1 (p*); each is read
+            // once, the step to l-1 carries p* over into s*
+            float4 s0, s1, s2, s3, p0 = {}, p1 = {}, p2 = {}, p3 = {};
             for (int l = ns - 1; l >= 0; l--) {
-                const float4* s = a.seg + (int64_t)l * 4 * n + r;
-                float4 s0 = s[0], s1 = s[n], s2 = s[2 * n], s3 = s[3 * n];
+                if (l == ns - 1) {
+                    const float4* s = a.seg + (int64_t)l * 4 * n + r;
+                    s0 = s[0];
+                    s1 = s[n];
+                    s2 = s[2 * n];
+                    s3 = s[3 * n];
+                } else {
+                    s0 = p0;
+                    s1 = p1;
+                    s2 = p2;
+                    s3 = p3;
+                }
                 int cell = __float_as_int(s1.w);
                 if (cell >= 0) {
                     float g = G[cell];
@@ -117,7 +130,10 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 if (l == 0) break;
                 // bounce at the end of segment l-1
                 const float4* q = a.seg + (int64_t)(l - 1) * 4 * n + r;
-                float4 p0 = q[0], p1 = q[n], p2 = q[2 * n], p3 = q[3 * n];
+                p0 = q[0];
+                p1 = q[n];
+                p2 = q[2 * n];
+                p3 = q[3 * n];
                 int slot = __float_as_int(p0.w);
                 float4 nm = a.normals[slot];
                 int mat = __float_as_int(nm.w);
