@@ -40,7 +40,10 @@ namespace {
 
 constexpr int kMatChunk = 8;
 constexpr int kBwdBlock = 256;
-constexpr int kBwdBlocks = 1024;
+// One round of resident waves: both variants hold 2 waves per SIMD (their
+// VGPR counts), so 256 CUs x 4 SIMDs x 2 waves = 512 workgroups of 4 waves.
+// A second, partly filled round cost 1.7x in the adjoint's time.
+constexpr int kBwdBlocks = 512;
 
 struct BwdArgs {
     const float4* seg;
@@ -75,6 +78,9 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
+// EXT: the forward used slab walls, refraction, diffuse reflection or early
+// termination; the plain variant carries none of their code (and registers).
+template <bool EXT>
 __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
     float ge[kMatChunk], gs[kMatChunk];
 #pragma unroll
@@ -145,8 +151,8 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 // change) divided by sqrt(q), the sampling probability held
                 // constant
                 cf kpe = F.rperp, kpa = F.rpar, dkpe = F.drperp, dkpa = F.drpar;
-                const bool transmit = a.refraction && s0.x == p0.x && s0.y == p0.y && s0.z == p0.z;
-                if (a.thickness) {
+                const bool transmit = EXT && a.refraction && s0.x == p0.x && s0.y == p0.y && s0.z == p0.z;
+                if (EXT && a.thickness) {
                     cf tp, tl, dtp, dtl;
                     slab_grad(F, a.k0 * a.thickness[mat], tp, tl, dtp, dtl);
                     kpe = F.rperp;
@@ -169,7 +175,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 // direction meets it with probability ~1e-9)
                 bool diffuse = false;
                 float dc1 = 0.f, ds1 = 0.f, dc2 = 0.f, ds2 = 0.f;
-                if (a.scattering && !transmit && a.scattering[mat] > 0.0f) {
+                if (EXT && a.scattering && !transmit && a.scattering[mat] > 0.0f) {
                     const uint4 w = philox4(a.seed, ray, l - 1, 2u);
                     const float cs = word_uniform(w.x), ss = sqrtf(fmaxf(0.0f, 1.0f - cs * cs));
                     float sph, cph;
@@ -181,7 +187,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                     sincospif(2.0f * word_uniform(w.z), &ds1, &dc1);
                     sincospif(2.0f * word_uniform(w.w), &ds2, &dc2);
                 }
-                if (!diffuse && a.rr_p_max > 0.0f && l >= a.rr_depth) {
+                if (EXT && !diffuse && a.rr_p_max > 0.0f && l >= a.rr_depth) {
                     // a surviving path carries 1/sqrt(p), p held constant: the
                     // factor is the ratio of the recorded T_l to R_l T_{l-1}
                     const cf x0 = cadd(cscale(cf{p2.x, p2.y}, b.w00), cscale(cf{p3.x, p3.y}, b.w01));
@@ -203,7 +209,7 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
                 cf u0 = cadd(cscale(f0, b.w00), cscale(f1, b.w01));
                 cf u1 = cadd(cscale(f0, b.w10), cscale(f1, b.w11));
                 int j = mat - a.mat0;
-                if (diffuse) {
+                if (EXT && diffuse) {
                     // E_l = sc N E with N = diag(x1, x2) [[ck, -sk], [sk, ck]] P
                     // unitary and sc^2 = c Gamma^2, Gamma^2 = ||D W E||^2 / ||E||^2
                     // (c, and a roulette factor, held constant).  Then
@@ -370,10 +376,14 @@ rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
     a.n_mat = s->n_mat;
     a.P = P;
     a.partials = (double*)s->grad_ws;
+    const bool ext = a.thickness || a.refraction || a.scattering || a.rr_p_max > 0.0f;
     for (int m0 = 0; m0 < std::max(1, s->n_mat); m0 += kMatChunk) {
         a.mat0 = m0;
         a.write_orient = (m0 == 0) ? 1 : 0;
-        hipLaunchKernelGGL(k_backward, dim3(kBwdBlocks), dim3(kBwdBlock), 0, st, a);
+        if (ext)
+            hipLaunchKernelGGL(k_backward<true>, dim3(kBwdBlocks), dim3(kBwdBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_backward<false>, dim3(kBwdBlocks), dim3(kBwdBlock), 0, st, a);
         hipLaunchKernelGGL(k_backward_final, dim3(1), dim3(64), 0, st, (const double*)s->grad_ws, kBwdBlocks,
                            s->n_mat, m0, a.write_orient, b.grad_eps, b.grad_sigma, b.grad_orient);
     }
