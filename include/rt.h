@@ -2,8 +2,11 @@
  * rt.h -- C ABI of librtmap.so, the MI355X (gfx950) SBR radio-map library.
  *
  * What the library computes: the radio map of a point source over a
- * horizontal measurement plane by shooting and bouncing rays (SBR), for
- * specular reflection only.  Citations are to "Sionna RT: Technical Report"
+ * horizontal measurement plane by shooting and bouncing rays (SBR), by
+ * default for specular reflection only; the optional extensions (slab walls
+ * and refraction, diffuse reflection, transmit arrays, early termination)
+ * are described with the fields that enable them.  Citations are to
+ * "Sionna RT: Technical Report"
  * (arXiv 2504.21719, v2.1):
  *   - rays leave the source on a spherical Fibonacci lattice of N_S points
  *     (Sec. "Sampling Initial Ray Directions");
@@ -16,7 +19,9 @@
  *   - every traced segment l = 0..L that crosses the plane adds
  *         lambda^2 ||T C_T||^2 / (4 pi N_S |M_i| |k_z|)
  *     to its cell i: this is the estimator eq. radio-map-solver-ci-all-2-
- *     estimator with no diffuse reflection (interaction probability 1), where
+ *     estimator for specular chains (interaction probability 1; with the
+ *     extensions, T also carries the 1/sqrt(Pr) sampling factors and the
+ *     per-diffuse-point scale), where
  *     the squared ray-tube length of the change of variables dA = r^2/|n^T k|
  *     d(omega) cancels the spherical spreading of the path gain eq. radio-map-
  *     solver-path-gain (Sec. "Definition of Radio Map").
