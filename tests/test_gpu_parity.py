@@ -208,6 +208,57 @@ def test_manhattan_full_size_sampled():
             assert abs(float(g.weights[r_, l_]) - w_) <= 1e-5 * w_
 
 
+@pytest.mark.parametrize("case", ["refraction", "diffuse", "roulette"])
+def test_extension_workloads_full_size_sampled(case):
+    """The extension workloads at full size (1e7 rays, L = 5, 1 m cells), as
+    the benchmark times them: slab walls with refraction on the Manhattan
+    scene without building bottoms (seed 1); Lambertian diffuse reflection
+    with S = 0.4 / 0.2 and K_x = 0.1 / 0.3 (seed 1); Russian roulette from
+    depth 2 (p_max 0.5) with gain thresholding.  The map equals the sum of
+    the per-segment weights, and a strided sample of 1,500 rays matches the
+    oracle ray by ray (hits outside flagged rays, cells off borders, weights
+    within 5e-5 for slabs and diffuse points, 1e-5 otherwise)."""
+    cfg = sg.manhattan_config()
+    cfg.params.seed = 1
+    w_rel = 5e-5
+    if case == "refraction":
+        cfg.scene = sg.with_thickness(sg.manhattan_scene(bottoms=False))
+        cfg.params.refraction = 1
+    elif case == "diffuse":
+        cfg.scene = sg.with_diffuse(cfg.scene, [0.4, 0.2], [0.1, 0.3])
+    else:
+        cfg.params.rr_p_max, cfg.params.rr_depth, cfg.params.gain_threshold = 0.5, 2, 1e-13
+        w_rel = 1e-5
+    g = gpu_radio_map(cfg, records=True)
+    N = cfg.params.n_rays
+    c = g.cells.ravel()
+    w = g.weights.ravel().astype(np.float64)
+    m = c >= 0
+    acc = np.bincount(c[m], weights=w[m], minlength=cfg.plane.W * cfg.plane.H).reshape(cfg.plane.H, cfg.plane.W)
+    big = acc > 1e-12 * acc.max()
+    np.testing.assert_allclose(g.map[0][big], acc[big], rtol=1e-4)
+    assert int(g.stats[4]) == 0
+    ids = np.arange(7, N, N // 1500, dtype=np.int64)
+    o = oracle.radio_map(cfg.scene, cfg.tx, cfg.plane, cfg.params, ray_ids=ids, want_records=True)
+    rep, bad = compare_hits(g.hits[ids], o.hits, o.flags, ids.size, max_frac=1.0)
+    print(case, rep)
+    assert not rep["unexplained"], rep
+    assert rep["mismatched"] <= 3, rep
+    ok = np.ones(ids.size, bool)
+    ok[bad] = False
+    rec = o.records
+    pos = {int(n): i for i, n in enumerate(ids)}
+    n_checked = 0
+    for r_, l_, cell_, w_, b_, len_ in zip(rec["ray"], rec["depth"], rec["cell"], rec["w"], rec["border"], rec["length"]):
+        if not ok[pos[int(r_)]]:
+            continue
+        if b_ > 1e-6 * (len_ + 1500.0):
+            assert int(g.cells[r_, l_]) == cell_, (r_, l_, int(g.cells[r_, l_]), cell_)
+            assert abs(float(g.weights[r_, l_]) - w_) <= w_rel * w_, (r_, l_, float(g.weights[r_, l_]), w_)
+            n_checked += 1
+    assert n_checked > 1000
+
+
 _LARGE = None
 
 
