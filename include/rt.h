@@ -120,7 +120,8 @@ rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
  * completes; a negative or non-finite entry gives undefined results.  A tape
  * and rt_radio_map_backward take it (the backward needs the same array; the
  * sampling probabilities of refraction are held constant in the gradient);
- * rt_radio_map_batched does not (RT_EUNSUPPORTED).
+ * rt_radio_map_batched takes it with one material sample and no gradients
+ * (RT_EUNSUPPORTED otherwise).
  * scattering, xpd (optional, both or neither; NULL = no diffuse reflection):
  * scattering coefficient S in [0, 1] and cross-polarisation share K_x in
  * [0, 1] (eq. xpd) per material.  A hit on a material with S > 0 samples a
@@ -137,8 +138,8 @@ rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
  * theta/phi bases of the two directions, mixed by the matrix of
  * eq. scattered_field with phases 2 pi times words 2 and 3, times
  * sqrt(2 cos(theta_s) S^2 Gamma^2 / q(S)).  One polarisation per call
- * (Gamma depends on the field): dual polarisation and rt_radio_map_batched
- * give RT_EUNSUPPORTED.  A taped call is differentiable: the backward takes
+ * (Gamma depends on the field): dual polarisation gives RT_EUNSUPPORTED, and
+ * so does rt_radio_map_batched with several material samples or gradients.  A taped call is differentiable: the backward takes
  * the same scattering and xpd arrays.  Entries outside [0, 1] give
  * undefined results.
  * scatter_pattern (optional, needs scattering; NULL = Lambertian for every
@@ -187,7 +188,8 @@ typedef struct {
      *              in metres, global frame (not rotated with the antenna)
      *   precoding  device float32 [n_ant][2]: u_i as (re, im)
      * Both arrays are read by the kernels of the call and must stay valid
-     * until it completes.  Not supported by rt_radio_map_batched. */
+     * until it completes.  rt_radio_map_batched takes arrays with one
+     * material sample and no gradients (RT_EUNSUPPORTED otherwise). */
     int32_t n_ant;
     const double* ant_pos;
     const float* precoding;
@@ -251,8 +253,8 @@ typedef struct {
      * ||E||^2 is the distance-normalised gain of polarisation 0 (times
      * |alpha|^2 with a transmit array).  A taped call records the surviving
      * paths (a dropped path's tape ends at its last traced segment) for
-     * rt_radio_map_backward.  Not available in rt_radio_map_batched
-     * (RT_EUNSUPPORTED). */
+     * rt_radio_map_backward.  rt_radio_map_batched takes it with one
+     * material sample and no gradients (RT_EUNSUPPORTED otherwise). */
     int32_t rr_depth;
     float rr_p_max;
     float gain_threshold;
@@ -269,7 +271,8 @@ typedef struct {
      * with Scene Objects") and its TE/TM basis.  Needs materials.thickness
      * (RT_EINVAL otherwise).  A tape records the sampled branches; the
      * adjoint differentiates the sampled coefficients with q held constant.
-     * Not available in rt_radio_map_batched (RT_EUNSUPPORTED). */
+     * rt_radio_map_batched takes it with one material sample and no
+     * gradients (RT_EUNSUPPORTED otherwise). */
     int32_t refraction;
 } rt_sbr_params;
 
@@ -372,6 +375,13 @@ rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials materials,
  * Every ray is traced once and serves all material samples.  Work over
  * (transmitter, ray) is scheduled from a device work counter by a persistent
  * kernel.
+ * With one material sample and no gradients the call runs the
+ * single-transmitter kernel over all transmitters and takes what
+ * rt_radio_map takes: transmit arrays, materials.thickness, scattering, xpd
+ * and scatter_pattern, and params' refraction, early termination and seed.
+ * A ray draws from the random streams of its own lattice index, so each
+ * transmitter's map is the one rt_radio_map gives for it.  Several material
+ * samples or gradients take none of these (RT_EUNSUPPORTED).
  */
 rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials materials,
                                int32_t n_samples, const rt_tx* txs,

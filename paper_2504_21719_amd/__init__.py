@@ -299,17 +299,27 @@ def rt_radio_map_backward(scene: RtScene, eps_r, sigma, tx, plane, params, tape:
 
 
 def rt_radio_map_batched(scene: RtScene, eps_r, sigma, txs: Sequence, rays_per_tx: Sequence[int], plane, params,
-                         out_maps, grad_maps=None, grads=None, stream=None, **pkw):
-    """eps_r/sigma: device f32 [S][n_mat]; out_maps [T][S][H][W]; grads [T][S][2 n_mat + 3]."""
+                         out_maps, grad_maps=None, grads=None, stream=None, thickness=None, scattering=None, xpd=None,
+                         scatter_pattern=None, **pkw):
+    """eps_r/sigma: device f32 [S][n_mat]; out_maps [T][S][H][W]; grads [T][S][2 n_mat + 3].
+
+    With one material set (S = 1) and no gradients the transmitters may carry
+    arrays, and ``thickness``, ``scattering``/``xpd``/``scatter_pattern`` and
+    the early-termination and refraction fields of ``params`` apply as in
+    ``rt_radio_map``."""
     n_tx = len(txs)
-    arr = (rt_tx * n_tx)(*[tx if isinstance(tx, rt_tx) else make_tx(tx) for tx in txs])
+    # the descriptors keep the transmit-array tensors alive for the call
+    descs = [tx if isinstance(tx, rt_tx) else make_tx(tx) for tx in txs]
+    arr = (rt_tx * n_tx)(*descs)
     budgets = (C.c_int64 * n_tx)(*[int(b) for b in rays_per_tx])
     p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
     pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
     S = int(eps_r.shape[0]) if eps_r.dim() == 2 else 1
-    _check(lib().rt_radio_map_batched(scene.handle, materials(eps_r, sigma), S, arr, C.cast(budgets, C.c_void_p),
+    mats = materials(eps_r, sigma, thickness, scattering, xpd, scatter_pattern)
+    _check(lib().rt_radio_map_batched(scene.handle, mats, S, arr, C.cast(budgets, C.c_void_p),
                                       n_tx, C.byref(pl), C.byref(p), _ptr(out_maps), _ptr(grad_maps), _ptr(grads),
                                       _stream(stream)))
+    del descs
     return out_maps
 
 

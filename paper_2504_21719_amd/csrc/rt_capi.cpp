@@ -495,10 +495,15 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     CHECK_ARG((grad_maps == nullptr) == (grads == nullptr),
               "rt_radio_map_batched: grad_maps and grads must both be given or both be NULL");
     rt_status r;
+    // one material set without gradients runs the single-transmitter kernel
+    // over all transmitters and takes its extensions; material samples and
+    // gradients share one traversal per ray and take none
+    const bool plain_only = n_samples > 1 || grad_maps != nullptr;
     for (int i = 0; i < n_tx; i++) {
         if ((r = check_tx(&txs[i], false)) != RT_OK) return r;
-        if (txs[i].n_ant != 0)
-            return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: transmit arrays are not supported here");
+        if (plain_only && txs[i].n_ant != 0)
+            return rt_fail(RT_EUNSUPPORTED,
+                           "rt_radio_map_batched: transmit arrays need one material sample and no gradients");
         CHECK_ARG(rays_per_tx[i] >= 1 && rays_per_tx[i] <= ((int64_t)1 << 40),
                   "rt_radio_map_batched: rays_per_tx must be in [1, 2^40]");
     }
@@ -509,11 +514,17 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     p.ray_begin = 0;
     p.ray_end = 0;
     if ((r = check_params(&p, &b, &e)) != RT_OK) return r;
-    if (p.rr_p_max > 0.0f || p.gain_threshold > 0.0f)
-        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: early termination is not supported here");
-    if (p.refraction || materials.thickness || materials.scattering || materials.xpd || materials.scatter_pattern)
-        return rt_fail(RT_EUNSUPPORTED,
-                       "rt_radio_map_batched: slab walls, refraction and diffuse reflection are not supported here");
+    const bool extended = p.rr_p_max > 0.0f || p.gain_threshold > 0.0f || p.refraction || materials.thickness ||
+                          materials.scattering || materials.xpd || materials.scatter_pattern;
+    if (plain_only && extended)
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: early termination, slab walls, refraction and "
+                                        "diffuse reflection need one material sample and no gradients");
+    CHECK_ARG(!p.refraction || materials.thickness,
+              "rt_radio_map_batched: refraction needs the slab thickness of every material");
+    CHECK_ARG((materials.scattering == nullptr) == (materials.xpd == nullptr),
+              "rt_radio_map_batched: scattering and xpd must both be given or both be NULL");
+    CHECK_ARG(!materials.scatter_pattern || materials.scattering,
+              "rt_radio_map_batched: scatter_pattern needs scattering and xpd");
     if ((r = check_device(scene)) != RT_OK) return r;
     rt_scene* s = const_cast<rt_scene*>(scene);
     hipStream_t hs = (hipStream_t)stream;
@@ -569,12 +580,32 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     bl.maps = out_maps;
     bl.grad_maps = grad_maps;
     bl.grads = grads;
+    bl.ext.thickness = materials.thickness;
+    bl.ext.scattering = materials.scattering;
+    bl.ext.xpd = materials.xpd;
+    bl.ext.pattern = materials.scatter_pattern;
+    bl.ext.refraction = params->refraction;
+    bl.ext.k0 = (float)(2.0 * RT_PI * params->freq_hz / RT_C0);
+    bl.ext.rr_depth = std::max(1, params->rr_depth);
+    bl.ext.rr_p_max = params->rr_p_max;
+    bl.ext.gain_threshold = params->gain_threshold;
+    {
+        const double lam = RT_C0 / params->freq_hz;
+        bl.ext.gain_scale = (float)(lam * lam / (16.0 * RT_PI * RT_PI));
+    }
+    bl.ext.seed = params->seed;
     // identity of the whole step: descriptors, pointers (including the
     // library workspaces the captured kernels read) and sizes
     uint64_t key = 1469598103934665603ull;
     key = mix(key, hb.data(), hb.size());
-    const void* ptrs[5] = {materials.eps_r, materials.sigma, out_maps, grad_maps, grads};
+    const void* ptrs[9] = {materials.eps_r, materials.sigma, out_maps, grad_maps, grads, materials.thickness,
+                           materials.scattering, materials.xpd, materials.scatter_pattern};
     key = mix(key, ptrs, sizeof(ptrs));
+    key = mix(key, &bl.ext.refraction, sizeof(bl.ext.refraction));
+    key = mix(key, &bl.ext.rr_depth, sizeof(bl.ext.rr_depth));
+    key = mix(key, &bl.ext.rr_p_max, sizeof(bl.ext.rr_p_max));
+    key = mix(key, &bl.ext.gain_threshold, sizeof(bl.ext.gain_threshold));
+    key = mix(key, &bl.ext.seed, sizeof(bl.ext.seed));
     key = mix(key, plane, sizeof(rt_plane));
     key = mix(key, &bl.L, sizeof(bl.L));
     key = mix(key, &bl.t_min, sizeof(bl.t_min));

@@ -213,6 +213,23 @@ struct BwdLaunch {
 };
 rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st);
 
+// The extensions of the single-transmitter forward (slab walls, refraction,
+// diffuse reflection, early termination) for a launch over several
+// transmitters with one material set.
+struct FwdExt {
+    const float* thickness;  // slab thickness per material (m), or null
+    const float* scattering; // S per material, or null
+    const float* xpd;        // K_x per material (with scattering)
+    const float* pattern;    // [n_mat][4] scattering patterns, or null (Lambertian)
+    int32_t refraction;
+    float k0;                // 2 pi / lambda
+    int32_t rr_depth;        // early termination before segments l >= rr_depth (>= 1)
+    float rr_p_max;          // Russian roulette (0 = off)
+    float gain_threshold;    // (0 = off)
+    float gain_scale;        // lambda^2 / (16 pi^2)
+    uint32_t seed;
+};
+
 struct BatchLaunch {
     const rt_scene* scene;
     const float* eps_r;      // [S][n_mat]
@@ -234,6 +251,7 @@ struct BatchLaunch {
     float* maps;             // [n_tx][S][H][W]
     const float* grad_maps;  // [n_tx][S][H][W] or null
     float* grads;            // [n_tx][S][2 n_mat + 3] or null
+    FwdExt ext;              // one material set without gradients only
 };
 rt_status rt_batched_workspace(const BatchLaunch& b, hipStream_t st);
 rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st);
@@ -243,7 +261,7 @@ rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const f
                                   const rt_scene::OrderTable* order, int64_t max_chunks, const TxDesc* txs,
                                   const int64_t* prefix, const int32_t* slots, int n_tx, int64_t total_rays,
                                   bool geom_only, float* maps, int64_t slot_stride, int64_t zero_floats,
-                                  float4* geom_seg, int* geom_nseg, hipStream_t st);
+                                  float4* geom_seg, int* geom_nseg, const FwdExt* ext, hipStream_t st);
 
 int rt_persistent_blocks(int block, int device);
 

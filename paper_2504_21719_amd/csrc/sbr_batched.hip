@@ -299,7 +299,7 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
     if (S == 1 && !grad) {
         return rt_launch_forward_multi(s, b.eps_r, b.sigma, b.pl, b.L, b.t_min, b.block, b.deposit, b.refill,
                                        b.order, b.max_chunks, b.tx_dev, b.prefix_dev, b.tx_slot_dev, b.n_tx,
-                                       b.total_rays, false, b.maps, HW, HW * b.n_tx, nullptr, nullptr, st);
+                                       b.total_rays, false, b.maps, HW, HW * b.n_tx, nullptr, nullptr, &b.ext, st);
     }
     size_t need = sizeof(float4) * 2 * (size_t)(b.L + 1) * (size_t)b.total_rays + sizeof(int) * (size_t)b.total_rays;
     const int P = 2 * s->n_mat + 3;
@@ -314,7 +314,7 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
     }
     rt_status r = rt_launch_forward_multi(s, b.eps_r, b.sigma, b.pl, b.L, b.t_min, b.block, b.deposit, b.refill,
                                           b.order, b.max_chunks, b.tx_dev, b.prefix_dev, b.tx_slot_dev, b.n_tx,
-                                          b.total_rays, true, b.maps, HW, HW * b.n_tx * S, geom, nseg, st);
+                                          b.total_rays, true, b.maps, HW, HW * b.n_tx * S, geom, nseg, nullptr, st);
     if (r != RT_OK) return r;
     SampArgs a;
     a.geom = geom;

@@ -336,6 +336,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     float kap = a.tx.kappa;   // lambda^2 / (4 pi N_S |M|) of the lane's transmitter
     float rlen = 0.0f;        // unfolded length to the last interaction (early termination only)
     float* mapb = a.map;      // map of the lane's transmitter
+    // several transmitters: lattice index of the lane's ray within its
+    // transmitter (the counter of its random streams, as in a single call)
+    // and 1 / kappa of that transmitter
+    int64_t nlat = 0;
+    float ikap = a.inv_kappa;
 
     while (true) {
         // ---- refill lanes without a ray: from this wavefront's reservoir of
@@ -413,6 +418,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                             }
                             kap = td.kappa;
                             mapb = a.map + (int64_t)a.slots[t] * a.slot_stride;
+                            nlat = n;
+                            ikap = 1.0f / td.kappa;
                         }
                         Launch Lr = fib_launch(n, td.n_rays);
                         if (MODE != MODE_GEOM) {
@@ -567,7 +574,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                             s2 = Sm * Sm;
                             const float qr = (1.0f - s2) * fa;
                             qs = s2 * fa;
-                            const float u = philox_uniform(a.seed, a.ray_begin + rid, l, 1u);
+                            const float u = philox_uniform(a.seed, MODE == MODE_SINGLE ? a.ray_begin + rid : nlat, l, 1u);
                             kind = u < qr ? 0 : (u < qr + qs ? 1 : 2);
                             if (kind != 1) {
                                 const float q = kind == 0 ? qr : (tot > 0.0f ? at / tot : 0.0f);
@@ -591,7 +598,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                         const cf al = cadd(cscale(e0, b.w10), cscale(e1, b.w11));
                         const float en2 = cabs2(e0) + cabs2(e1);
                         const float g2 = en2 > 0.0f ? (cabs2(cmul(F.rperp, ap)) + cabs2(cmul(F.rpar, al))) / en2 : 0.0f;
-                        const uint4 w = philox4(a.seed, a.ray_begin + rid, l, 2u);
+                        const uint4 w = philox4(a.seed, MODE == MODE_SINGLE ? a.ray_begin + rid : nlat, l, 2u);
                         const float cs = word_uniform(w.x), ss = sqrtf(fmaxf(0.0f, 1.0f - cs * cs));
                         float sph, cph, s1, c1, s2p, c2p;
                         sincospif(2.0f * word_uniform(w.y), &sph, &cph);
@@ -646,13 +653,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                     // gain ||T C||^2 of polarisation 0 (times |alpha|^2)
                     const cf e0 = cadd(cscale(Ta, c0t), cscale(Tb, c0p));
                     const cf e1 = cadd(cscale(Tc, c0t), cscale(Td, c0p));
-                    const float gn = (cabs2(e0) + cabs2(e1)) * (kap * a.inv_kappa);
+                    const float gn = (cabs2(e0) + cabs2(e1)) * (kap * (MODE == MODE_SINGLE ? a.inv_kappa : ikap));
                     bool drop = false;
                     if (a.gain_threshold > 0.0f && rlen > 0.0f)
                         drop = a.gain_scale * gn * __builtin_amdgcn_rcpf(rlen * rlen) < a.gain_threshold;
                     if (!drop && a.rr_p_max > 0.0f) {
                         const float p = fminf(gn, a.rr_p_max);
-                        if (philox_uniform(a.seed, a.ray_begin + rid, l, 0u) < p) {
+                        if (philox_uniform(a.seed, MODE == MODE_SINGLE ? a.ray_begin + rid : nlat, l, 0u) < p) {
                             const float sc = __builtin_amdgcn_rsqf(p);   // survivors carry 1/sqrt(p)
                             Ta = cscale(Ta, sc);
                             Tb = cscale(Tb, sc);
@@ -767,11 +774,15 @@ static void launch_mode(const FwdArgs& args, int accel, bool wide, int blocks, i
     if (const char* env = getenv("RTMAP_CLAIM"))
         a.claim = std::max(64, std::min(4096, atoi(env)));
     size_t lds = sizeof(int2) * RT_STACK_LDS * block;   // {node, entry distance} per entry
-    if constexpr (MODE == MODE_SINGLE) {
+    if constexpr (MODE != MODE_GEOM) {
         if (ext) {
-            if (accel == RT_ACCEL_BRUTE)
-                hipLaunchKernelGGL((k_forward<true, MODE, false, true>), dim3(blocks), dim3(block), lds, st, a);
-            else if (wide)
+            if constexpr (MODE == MODE_SINGLE) {
+                if (accel == RT_ACCEL_BRUTE) {
+                    hipLaunchKernelGGL((k_forward<true, MODE, false, true>), dim3(blocks), dim3(block), lds, st, a);
+                    return;
+                }
+            }
+            if (wide)
                 hipLaunchKernelGGL((k_forward<false, MODE, true, true>), dim3(blocks), dim3(block), lds, st, a);
             else
                 hipLaunchKernelGGL((k_forward<false, MODE, false, true>), dim3(blocks), dim3(block), lds, st, a);
@@ -856,7 +867,7 @@ rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const f
                                   const rt_scene::OrderTable* order, int64_t max_chunks, const TxDesc* txs,
                                   const int64_t* prefix, const int32_t* slots, int n_tx, int64_t total_rays,
                                   bool geom_only, float* maps, int64_t slot_stride, int64_t zero_floats,
-                                  float4* geom_seg, int* geom_nseg, hipStream_t st) {
+                                  float4* geom_seg, int* geom_nseg, const FwdExt* ext, hipStream_t st) {
     FwdArgs a;
     base_args(a, s, block, eps_r, sigma, pl, L, t_min);
     a.ray_begin = 0;
@@ -887,9 +898,25 @@ rt_status rt_launch_forward_multi(const rt_scene* s, const float* eps_r, const f
     int g = (int)std::min<int64_t>(4096, std::max<int64_t>(2, (zero_floats + 255) / 256));
     hipLaunchKernelGGL(k_prepare, dim3(g), dim3(256), 0, st, maps, zero_floats, s->counters);
     if (order) rt_order_shifts_multi(order, txs, n_tx, max_chunks, s->shifts, st);
+    bool use_ext = false;
+    if (ext && !geom_only) {
+        a.rr_depth = ext->rr_depth;
+        a.rr_p_max = ext->rr_p_max;
+        a.gain_threshold = ext->gain_threshold;
+        a.gain_scale = ext->gain_scale;
+        a.seed = ext->seed;
+        a.thickness = ext->thickness;
+        a.scattering = ext->scattering;
+        a.xpd = ext->xpd;
+        a.pattern = ext->pattern;
+        a.refraction = ext->refraction;
+        a.k0 = ext->k0;
+        use_ext = ext->rr_p_max > 0.0f || ext->gain_threshold > 0.0f || ext->thickness != nullptr ||
+                  ext->scattering != nullptr;
+    }
     if (total_rays > 0) {
         if (geom_only) launch_mode<MODE_GEOM>(a, RT_ACCEL_BVH, use_wide(s), blocks, block, st);
-        else launch_mode<MODE_MULTI>(a, RT_ACCEL_BVH, use_wide(s), blocks, block, st);
+        else launch_mode<MODE_MULTI>(a, RT_ACCEL_BVH, use_wide(s), blocks, block, st, use_ext);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rt_hip_fail(e, "batched forward launch");

@@ -118,3 +118,48 @@ def test_material_samples_fwd_bwd_match_plain_adjoint():
             a, b = out[t, k].cpu().numpy(), m[0].cpu().numpy()
             big = b > 1e-9 * b.max()
             np.testing.assert_allclose(a[big], b[big], rtol=2e-5)
+
+
+@pytest.mark.parametrize("case", ["arrays", "slab_refraction_roulette", "diffuse_threshold"])
+def test_multi_transmitter_extensions_match_single_calls(case):
+    """One material set, no gradients: transmit arrays (two of six
+    transmitters), slab walls with refraction and Russian roulette, or
+    diffuse reflection (directive pattern) with gain thresholding, batched
+    over uneven budgets.  Every transmitter's map equals its rt_radio_map map:
+    each ray draws from the streams of its own lattice index, as in a single
+    call.  The two kernels may round a multiply-add differently, so a
+    decision that falls exactly on its threshold may go the other way: a few
+    cells may differ; the totals agree within 1e-4."""
+    import dataclasses
+    rt, torch, scene, s, txs, budgets, plane, params = _setup()
+    kw = {}
+    if case == "arrays":
+        txs = [dataclasses.replace(t, array=sg.random_array(6, 0.15, seed=20 + i)) if i in (1, 3) else t
+               for i, t in enumerate(txs)]
+    elif case == "slab_refraction_roulette":
+        scene = sg.with_thickness(sg.manhattan_scene(bottoms=False))
+        s = rt.scene_from_mesh(scene)
+        params = sg.Params(3.5e9, 1, 5, refraction=1, rr_p_max=0.5, rr_depth=2, seed=7)
+        kw["thickness"] = torch.tensor(scene.thickness, dtype=torch.float32, device="cuda")
+    else:
+        scene = sg.with_diffuse(scene, [0.4, 0.2], [0.1, 0.3], (1, 3, 1, 1.0))
+        params = sg.Params(3.5e9, 1, 5, gain_threshold=1e-13, seed=11)
+        for name, v in (("scattering", scene.scattering), ("xpd", scene.xpd),
+                        ("scatter_pattern", scene.scatter_pattern)):
+            kw[name] = torch.tensor(v, dtype=torch.float32, device="cuda")
+    eps = torch.tensor(scene.eps_r, dtype=torch.float32, device="cuda")
+    sig = torch.tensor(scene.sigma, dtype=torch.float32, device="cuda")
+    T = len(txs)
+    out = torch.full((T, 1, plane.H, plane.W), float("nan"), dtype=torch.float32, device="cuda")
+    rt.rt_radio_map_batched(s, eps[None], sig[None], txs, budgets, plane, params, out, **kw)
+    torch.cuda.synchronize()
+    for t in range(T):
+        ref = torch.empty((1, plane.H, plane.W), dtype=torch.float32, device="cuda")
+        p = dataclasses.replace(params, n_rays=int(budgets[t]))
+        rt.rt_radio_map(s, eps, sig, txs[t], plane, p, ref, **kw)
+        torch.cuda.synchronize()
+        a, b = out[t, 0].cpu().numpy().astype(np.float64), ref[0].cpu().numpy().astype(np.float64)
+        assert np.isfinite(a).all() and b.max() > 0
+        off = ~np.isclose(a, b, rtol=1e-4, atol=1e-7 * b.max())
+        assert off.sum() <= 20, (t, int(off.sum()))
+        assert a.sum() == pytest.approx(b.sum(), rel=1e-4)

@@ -99,9 +99,11 @@ def test_refraction_rejections():
     with pytest.raises(rt.RtError) as e:             # the backward needs the same thickness
         rt.rt_radio_map_backward(s, eps, sig, cfg.tx, cfg.plane, cfg.params, tape, g, ge)
     assert e.value.status == rt.RT_EINVAL
-    maps = torch.empty((1, 1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device="cuda")
+    # several material samples share one traversal and take no extensions
+    maps = torch.empty((1, 2, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device="cuda")
     with pytest.raises(rt.RtError) as e:
-        rt.rt_radio_map_batched(s, eps[None], sig[None], [cfg.tx], [10_000], cfg.plane, cfg.params, maps)
+        rt.rt_radio_map_batched(s, torch.stack([eps, eps]), torch.stack([sig, sig]), [cfg.tx], [10_000], cfg.plane,
+                                cfg.params, maps)
     assert e.value.status == rt.RT_EUNSUPPORTED
 
 

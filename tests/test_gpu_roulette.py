@@ -50,9 +50,9 @@ def test_termination_after_last_depth_changes_nothing():
     np.testing.assert_allclose(b.weights, a.weights, rtol=4e-7, atol=0)
 
 
-def test_termination_with_tape_and_rejected_batched():
-    """A taped call with early termination gives the untaped map; the batched
-    entry point has no termination and rejects it."""
+def test_termination_with_tape_and_rejected_batched_samples():
+    """A taped call with early termination gives the untaped map; batched
+    material samples have no termination and reject it."""
     import torch
     import paper_2504_21719_amd as rt
     cfg = sg.tiny_config(n_rays=10_000)
@@ -69,7 +69,9 @@ def test_termination_with_tape_and_rejected_batched():
     torch.cuda.synchronize()
     # same rays and weights; only the order of the atomic deposits may differ
     torch.testing.assert_close(out, ref, rtol=1e-4, atol=0)
-    maps = torch.empty((1, 1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device="cuda")
+    # several material samples share one traversal and take no extensions
+    maps = torch.empty((1, 2, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device="cuda")
     with pytest.raises(rt.RtError) as e:
-        rt.rt_radio_map_batched(s, eps[None], sig[None], [cfg.tx], [10_000], cfg.plane, cfg.params, maps)
+        rt.rt_radio_map_batched(s, torch.stack([eps, eps]), torch.stack([sig, sig]), [cfg.tx], [10_000], cfg.plane,
+                                cfg.params, maps)
     assert e.value.status == rt.RT_EUNSUPPORTED
