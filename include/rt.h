@@ -120,8 +120,8 @@ rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
  * completes; a negative or non-finite entry gives undefined results.  A tape
  * and rt_radio_map_backward take it (the backward needs the same array; the
  * sampling probabilities of refraction are held constant in the gradient);
- * rt_radio_map_batched takes it with one material sample and no gradients
- * (RT_EUNSUPPORTED otherwise).
+ * rt_radio_map_batched takes it (one array shared by the material samples;
+ * with refraction, one material sample and no gradients only).
  * scattering, xpd (optional, both or neither; NULL = no diffuse reflection):
  * scattering coefficient S in [0, 1] and cross-polarisation share K_x in
  * [0, 1] (eq. xpd) per material.  A hit on a material with S > 0 samples a
@@ -188,8 +188,8 @@ typedef struct {
      *              in metres, global frame (not rotated with the antenna)
      *   precoding  device float32 [n_ant][2]: u_i as (re, im)
      * Both arrays are read by the kernels of the call and must stay valid
-     * until it completes.  rt_radio_map_batched takes arrays with one
-     * material sample and no gradients (RT_EUNSUPPORTED otherwise). */
+     * until it completes.  rt_radio_map_batched takes arrays, also with
+     * material samples and gradients. */
     int32_t n_ant;
     const double* ant_pos;
     const float* precoding;
@@ -381,7 +381,10 @@ rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials materials,
  * and scatter_pattern, and params' refraction, early termination and seed.
  * A ray draws from the random streams of its own lattice index, so each
  * transmitter's map is the one rt_radio_map gives for it.  Several material
- * samples or gradients take none of these (RT_EUNSUPPORTED).
+ * samples or gradients share one traversal per ray, so they take only what
+ * leaves the paths unchanged: transmit arrays and slab walls without
+ * refraction (one thickness array for all samples); refraction, diffuse
+ * reflection and early termination give RT_EUNSUPPORTED there.
  */
 rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials materials,
                                int32_t n_samples, const rt_tx* txs,

@@ -496,14 +496,13 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
               "rt_radio_map_batched: grad_maps and grads must both be given or both be NULL");
     rt_status r;
     // one material set without gradients runs the single-transmitter kernel
-    // over all transmitters and takes its extensions; material samples and
-    // gradients share one traversal per ray and take none
-    const bool plain_only = n_samples > 1 || grad_maps != nullptr;
+    // over all transmitters and takes all its extensions; material samples
+    // and gradients share one traversal per ray, so they take only what
+    // leaves the path unchanged (transmit arrays, slab walls without
+    // refraction)
+    const bool shared_paths = n_samples > 1 || grad_maps != nullptr;
     for (int i = 0; i < n_tx; i++) {
         if ((r = check_tx(&txs[i], false)) != RT_OK) return r;
-        if (plain_only && txs[i].n_ant != 0)
-            return rt_fail(RT_EUNSUPPORTED,
-                           "rt_radio_map_batched: transmit arrays need one material sample and no gradients");
         CHECK_ARG(rays_per_tx[i] >= 1 && rays_per_tx[i] <= ((int64_t)1 << 40),
                   "rt_radio_map_batched: rays_per_tx must be in [1, 2^40]");
     }
@@ -514,11 +513,11 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     p.ray_begin = 0;
     p.ray_end = 0;
     if ((r = check_params(&p, &b, &e)) != RT_OK) return r;
-    const bool extended = p.rr_p_max > 0.0f || p.gain_threshold > 0.0f || p.refraction || materials.thickness ||
-                          materials.scattering || materials.xpd || materials.scatter_pattern;
-    if (plain_only && extended)
-        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: early termination, slab walls, refraction and "
-                                        "diffuse reflection need one material sample and no gradients");
+    const bool path_changes = p.rr_p_max > 0.0f || p.gain_threshold > 0.0f || p.refraction ||
+                              materials.scattering || materials.xpd || materials.scatter_pattern;
+    if (shared_paths && path_changes)
+        return rt_fail(RT_EUNSUPPORTED, "rt_radio_map_batched: early termination, refraction and diffuse "
+                                        "reflection need one material sample and no gradients");
     CHECK_ARG(!p.refraction || materials.thickness,
               "rt_radio_map_batched: refraction needs the slab thickness of every material");
     CHECK_ARG((materials.scattering == nullptr) == (materials.xpd == nullptr),
@@ -594,6 +593,8 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
         bl.ext.gain_scale = (float)(lam * lam / (16.0 * RT_PI * RT_PI));
     }
     bl.ext.seed = params->seed;
+    bl.has_arrays = false;
+    for (int i = 0; i < n_tx; i++) bl.has_arrays = bl.has_arrays || txs[i].n_ant > 0;
     // identity of the whole step: descriptors, pointers (including the
     // library workspaces the captured kernels read) and sizes
     uint64_t key = 1469598103934665603ull;

@@ -251,7 +251,9 @@ struct BatchLaunch {
     float* maps;             // [n_tx][S][H][W]
     const float* grad_maps;  // [n_tx][S][H][W] or null
     float* grads;            // [n_tx][S][2 n_mat + 3] or null
-    FwdExt ext;              // one material set without gradients only
+    FwdExt ext;              // all of it for one material set without gradients;
+                             // thickness alone for material samples and gradients
+    bool has_arrays;         // a transmitter has a transmit array
 };
 rt_status rt_batched_workspace(const BatchLaunch& b, hipStream_t st);
 rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st);

@@ -16,7 +16,9 @@
 //    (eq. fresnel_vac, eq. eta), deposits into the sample's map, and, given
 //    upstream gradients, runs the same reverse sweep as the plain adjoint
 //    (dJ/dp = 2 Re(lambda^H dR/dp E)) with the fields of the forward pass
-//    kept in registers.
+//    kept in registers.  Slab walls without refraction (eq. fresnel_slab)
+//    and transmit arrays fit this split: neither changes a ray's path, only
+//    its coefficients or its weight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,6 +51,8 @@ struct SampArgs {
     const float* grad_maps; // [n_tx][S][H][W] or null
     double* gws;            // [n_tx][S][P] FP64 accumulators (gradient mode)
     int P;                  // 2 n_mat + 3
+    const float* thickness; // slab thickness per material (m, shared by the samples), or null
+    float k0;               // 2 pi / lambda
 };
 
 __device__ __forceinline__ int find_tx_s(const int64_t* __restrict__ prefix, int n_tx, int64_t g) {
@@ -70,7 +74,7 @@ __device__ __forceinline__ double wsum(double v) {
 // (basis change W, cos(theta_1), material, crossed cell, deposit factor) are
 // computed once and kept in registers; the loop over material samples then
 // only evaluates Fresnel coefficients and 2-vector field updates.
-template <bool GRAD>
+template <bool GRAD, bool SLAB, bool ARR>
 __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
     const int lane = threadIdx.x & 63;
     const int64_t HW = (int64_t)a.pl.W * a.pl.H;
@@ -96,13 +100,15 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
             } else {
                 tx_pattern<float>(Lr, td, td.pol == 1 ? 1 : 0, cth.v, cph.v);
             }
+            // |alpha|^2 of a transmit array depends on the direction only
+            const float kap = ARR && td.n_ant > 0 ? td.kappa * array_gain(Lr, td) : td.kappa;
 #pragma unroll
             for (int l = 0; l < kMaxSeg; l++) {
                 if (l >= ns) break;
                 const float4* sp = a.geom + (int64_t)l * 2 * T + g;
                 float4 s0 = sp[0], s1 = sp[T];
                 cell[l] = __float_as_int(s1.w);
-                gk[l] = td.kappa * __builtin_amdgcn_rcpf(fabsf(s0.z));
+                gk[l] = kap * __builtin_amdgcn_rcpf(fabsf(s0.z));
                 if (l + 1 < ns) {
                     float4 nm = a.normals[__float_as_int(s0.w)];
                     matl[l] = __float_as_int(nm.w);
@@ -137,6 +143,10 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                     if (l + 1 < ns) {
                         int m = matl[l];
                         Fresnel F = fresnel<false>(cth1[l], cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
+                        if (SLAB) {
+                            cf tp, tl;
+                            slab(F, a.k0 * a.thickness[m], tp, tl);
+                        }
                         cf u0 = cadd(cscale(e0, w00[l]), cscale(e1, w01[l]));
                         cf u1 = cadd(cscale(e0, w10[l]), cscale(e1, w11[l]));
                         e0 = cmul(F.rperp, u0);
@@ -158,6 +168,10 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                         const int k = l - 1;      // the bounce that ends segment l-1
                         int m = matl[k];
                         Fresnel F = fresnel<true>(cth1[k], cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
+                        if (SLAB) {
+                            cf tp, tl, dtp, dtl;
+                            slab_grad(F, a.k0 * a.thickness[m], tp, tl, dtp, dtl);
+                        }
                         cf u0 = cadd(cscale(E0[k], w00[k]), cscale(E1[k], w01[k]));
                         cf u1 = cadd(cscale(E0[k], w10[k]), cscale(E1[k], w11[k]));
                         cf z = csub(cmulc(lam0, cmul(F.drperp, u0)), cmulc(lam1, cmul(F.drpar, u1)));
@@ -227,17 +241,22 @@ __global__ void __launch_bounds__(kSampBlock) k_samples_deep(const SampArgs a) {
         Launch Lr = fib_launch(g - a.prefix[t], td.n_rays);
         float ct, cp;
         tx_pattern<float>(Lr, td, td.pol == 1 ? 1 : 0, ct, cp);
+        const float kap = td.n_ant > 0 ? td.kappa * array_gain(Lr, td) : td.kappa;
         cf e0 = {ct, 0.f}, e1 = {cp, 0.f};
         for (int l = 0; l < ns; l++) {
             const float4* sp = a.geom + (int64_t)l * 2 * T + g;
             float4 s0 = sp[0], s1 = sp[T];
             int cell = __float_as_int(s1.w);
-            if (cell >= 0) unsafeAtomicAdd(map + cell, td.kappa * __builtin_amdgcn_rcpf(fabsf(s0.z)) * (cabs2(e0) + cabs2(e1)));
+            if (cell >= 0) unsafeAtomicAdd(map + cell, kap * __builtin_amdgcn_rcpf(fabsf(s0.z)) * (cabs2(e0) + cabs2(e1)));
             if (l + 1 < ns) {
                 float4 nm = a.normals[__float_as_int(s0.w)];
                 int m = __float_as_int(nm.w);
                 Bounce b = bounce_geometry(f3(s0.x, s0.y, s0.z), f3(s1.x, s1.y, s1.z), f3(nm.x, nm.y, nm.z));
                 Fresnel F = fresnel<false>(b.c, cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
+                if (a.thickness) {
+                    cf tp, tl;
+                    slab(F, a.k0 * a.thickness[m], tp, tl);
+                }
                 cf u0 = cadd(cscale(e0, b.w00), cscale(e1, b.w01));
                 cf u1 = cadd(cscale(e0, b.w10), cscale(e1, b.w11));
                 e0 = cmul(F.rperp, u0);
@@ -334,12 +353,25 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
     a.grad_maps = b.grad_maps;
     a.gws = (double*)s->bgrad_ws;
     a.P = P;
+    a.thickness = b.ext.thickness;
+    a.k0 = b.ext.k0;
     unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1 << 20, (b.total_rays + kSampBlock - 1) / kSampBlock));
     if (b.total_rays > 0) {
-        if (grad) {
-            hipLaunchKernelGGL(k_samples<true>, dim3(bx), dim3(kSampBlock), 0, st, a);
-        } else if (b.L + 1 <= kMaxSeg) {
-            hipLaunchKernelGGL(k_samples<false>, dim3(bx), dim3(kSampBlock), 0, st, a);
+        // slab walls and transmit arrays each get their own variant, so that
+        // the plain one keeps its registers
+        const bool slab_walls = a.thickness != nullptr, arrays = b.has_arrays;
+        if (grad || b.L + 1 <= kMaxSeg) {
+            const int v = (grad ? 4 : 0) + (slab_walls ? 2 : 0) + (arrays ? 1 : 0);
+            switch (v) {
+            case 0: hipLaunchKernelGGL((k_samples<false, false, false>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
+            case 1: hipLaunchKernelGGL((k_samples<false, false, true>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
+            case 2: hipLaunchKernelGGL((k_samples<false, true, false>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
+            case 3: hipLaunchKernelGGL((k_samples<false, true, true>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
+            case 4: hipLaunchKernelGGL((k_samples<true, false, false>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
+            case 5: hipLaunchKernelGGL((k_samples<true, false, true>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
+            case 6: hipLaunchKernelGGL((k_samples<true, true, false>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_samples<true, true, true>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
+            }
         } else {
             unsigned by = (unsigned)std::min<int64_t>(65535, (b.total_rays + kSampBlock - 1) / kSampBlock);
             hipLaunchKernelGGL(k_samples_deep, dim3(by, S), dim3(kSampBlock), 0, st, a);

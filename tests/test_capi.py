@@ -158,22 +158,22 @@ def test_batched_argument_checks():
                                 C.byref(_params()), C.cast(out, C.c_void_p), None, None, None)
     assert st == rt.RT_EINVAL        # dual pol not allowed here
     txs[0].pol = 0
-    mt = rt.rt_materials(C.cast(out, C.c_void_p), C.cast(out, C.c_void_p), C.cast(out, C.c_void_p))
-    st = L.rt_radio_map_batched(C.cast(dummy, C.c_void_p), mt, 2, txs, C.cast(budgets, C.c_void_p), 2, C.byref(pl),
+    ms = rt.rt_materials(C.cast(out, C.c_void_p), C.cast(out, C.c_void_p), None, C.cast(out, C.c_void_p),
+                         C.cast(out, C.c_void_p))
+    st = L.rt_radio_map_batched(C.cast(dummy, C.c_void_p), ms, 2, txs, C.cast(budgets, C.c_void_p), 2, C.byref(pl),
                                 C.byref(_params()), C.cast(out, C.c_void_p), None, None, None)
-    assert st == rt.RT_EUNSUPPORTED  # slab walls only with one material sample
+    assert st == rt.RT_EUNSUPPORTED  # diffuse reflection changes paths: one material sample only
     pr = _params()
     pr.refraction = 1
     st = L.rt_radio_map_batched(C.cast(dummy, C.c_void_p), m, 1, txs, C.cast(budgets, C.c_void_p), 2, C.byref(pl),
                                 C.byref(pr), C.cast(out, C.c_void_p), None, None, None)
     assert st == rt.RT_EINVAL        # refraction without a thickness
-    txs[0].n_ant = 2
-    txs[0].ant_pos = C.cast(out, C.c_void_p)
-    txs[0].precoding = C.cast(out, C.c_void_p)
+    pr.rr_p_max = 0.5
+    pr.refraction = 0
     st = L.rt_radio_map_batched(C.cast(dummy, C.c_void_p), m, 1, txs, C.cast(budgets, C.c_void_p), 2, C.byref(pl),
-                                C.byref(_params()), C.cast(out, C.c_void_p), C.cast(out, C.c_void_p),
+                                C.byref(pr), C.cast(out, C.c_void_p), C.cast(out, C.c_void_p),
                                 C.cast(out, C.c_void_p), None)
-    assert st == rt.RT_EUNSUPPORTED  # transmit arrays only without gradients
+    assert st == rt.RT_EUNSUPPORTED  # Russian roulette changes paths: no batched gradients
 
 
 def test_binding_refuses_host_tensors():

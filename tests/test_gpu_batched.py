@@ -120,6 +120,55 @@ def test_material_samples_fwd_bwd_match_plain_adjoint():
             np.testing.assert_allclose(a[big], b[big], rtol=2e-5)
 
 
+def test_material_samples_with_slab_walls_and_arrays():
+    """Slab walls without refraction and transmit arrays leave every path
+    unchanged, so material samples share one traversal with them too: maps
+    and gradients of three samples for two transmitters (one with an array)
+    equal per-sample rt_radio_map + rt_radio_map_backward with the same
+    thickness."""
+    import dataclasses
+    rt, torch, scene, s, txs, budgets, plane, params = _setup(n_tx=2)
+    scene = sg.with_thickness(sg.manhattan_scene(bottoms=False))
+    s = rt.scene_from_mesh(scene)
+    txs = [sg.Tx(t.pos, yaw=0.4 + 0.3 * i, pitch=-0.15, pattern=sg.PATTERN_DIRECTIONAL,
+                 array=sg.random_array(5, 0.12, seed=31) if i == 1 else None) for i, t in enumerate(txs)]
+    thk = torch.tensor(scene.thickness, dtype=torch.float32, device="cuda")
+    S = 3
+    E, Sg = sg.random_materials(scene, S, seed=7)
+    eps = torch.tensor(E, dtype=torch.float32, device="cuda")
+    sig = torch.tensor(Sg, dtype=torch.float32, device="cuda")
+    T = len(txs)
+    g = torch.randn((T, S, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    g = torch.nn.functional.avg_pool2d(g.view(T * S, 1, plane.H, plane.W), 9, 1, 4).view_as(g).contiguous()
+    out = torch.empty((T, S, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    fwd_only = torch.empty_like(out)
+    nm = scene.n_materials
+    grads = torch.empty((T, S, 2 * nm + 3), dtype=torch.float32, device="cuda")
+    rt.rt_radio_map_batched(s, eps, sig, txs, budgets, plane, params, out, grad_maps=g, grads=grads, thickness=thk)
+    rt.rt_radio_map_batched(s, eps, sig, txs, budgets, plane, params, fwd_only, thickness=thk)
+    torch.cuda.synchronize()
+    for t in range(T):
+        p = dataclasses.replace(params, n_rays=int(budgets[t]))
+        for k in range(S):
+            m = torch.empty((1, plane.H, plane.W), dtype=torch.float32, device="cuda")
+            tape = rt.rt_tape_create(p)
+            e_k, s_k = eps[k].contiguous(), sig[k].contiguous()
+            rt.rt_radio_map(s, e_k, s_k, txs[t], plane, p, m, tape=tape, thickness=thk)
+            ge = torch.empty(nm, device="cuda")
+            gs = torch.empty(nm, device="cuda")
+            go = torch.empty(3, device="cuda")
+            rt.rt_radio_map_backward(s, e_k, s_k, txs[t], plane, p, tape, g[t, k].contiguous()[None], ge, gs, go,
+                                     thickness=thk)
+            torch.cuda.synchronize()
+            ref = torch.cat([ge, gs, go]).cpu().numpy().astype(np.float64)
+            got = grads[t, k].cpu().numpy().astype(np.float64)
+            assert np.all(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-6 * np.abs(ref).max()), (t, k, got, ref)
+            b = m[0].cpu().numpy()
+            big = b > 1e-9 * b.max()
+            for a in (out[t, k].cpu().numpy(), fwd_only[t, k].cpu().numpy()):
+                np.testing.assert_allclose(a[big], b[big], rtol=2e-5)
+
+
 @pytest.mark.parametrize("case", ["arrays", "slab_refraction_roulette", "diffuse_threshold"])
 def test_multi_transmitter_extensions_match_single_calls(case):
     """One material set, no gradients: transmit arrays (two of six
