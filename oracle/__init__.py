@@ -87,6 +87,9 @@ def lib():
             L.or_fresnel.argtypes = [C.c_double] * 4 + [C.POINTER(C.c_double)] * 4
             L.or_fresnel_slab.restype = None
             L.or_fresnel_slab.argtypes = [C.c_double] * 5 + [C.c_void_p]
+            L.or_path_field.restype = C.c_int
+            L.or_path_field.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                        C.c_void_p, C.c_void_p]
             L.or_scatter_pattern.restype = C.c_double
             L.or_scatter_pattern.argtypes = [C.c_void_p] * 4
             L.or_uniform.restype = C.c_double
@@ -246,6 +249,24 @@ def fresnel(eps_r, sigma, freq, cos_theta):
     a, b, c, d = (C.c_double(), C.c_double(), C.c_double(), C.c_double())
     L.or_fresnel(eps_r, sigma, freq, cos_theta, C.byref(a), C.byref(b), C.byref(c), C.byref(d))
     return complex(a.value, b.value), complex(c.value, d.value)
+
+
+def path_field(points, normals, eps_r, sigma, freq, E0):
+    """Field at the end of a specular chain (source, reflection points, end
+    point) carried with the radio map's interaction step; returns (E, k) with
+    E complex [3] and k the direction of the last segment."""
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    nr = np.ascontiguousarray(normals, dtype=np.float64).reshape(-1, 3)
+    er = np.ascontiguousarray(eps_r, dtype=np.float64).ravel()
+    sg_ = np.ascontiguousarray(sigma, dtype=np.float64).ravel()
+    if nr.shape[0] != pts.shape[0] - 2 or er.size != nr.shape[0] or sg_.size != nr.shape[0]:
+        raise ValueError("path_field: one normal and one material per reflection point")
+    e0 = np.ascontiguousarray(np.stack([np.real(E0), np.imag(E0)], axis=1).ravel(), dtype=np.float64)
+    out = np.zeros(9)
+    if lib().or_path_field(pts.ctypes.data, pts.shape[0], nr.ctypes.data, er.ctypes.data, sg_.ctypes.data,
+                           float(freq), e0.ctypes.data, out.ctypes.data) != 0:
+        raise ValueError("path_field: bad sizes")
+    return out[0:6:2] + 1j * out[1:6:2], out[6:9]
 
 
 def fresnel_slab(eps_r, sigma, freq, cos_theta, d):

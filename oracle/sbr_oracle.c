@@ -151,6 +151,64 @@ static double cv_re_inner(cvec3 E, cvec3 dE) {
     return creal(conj(E.x) * dE.x + conj(E.y) * dE.y + conj(E.z) * dE.z);
 }
 
+/* ------------------------------------------------ one specular interaction */
+/* eq. fresnel_vac: r_perp and r_par at incidence cos(theta_1) = c on a
+ * medium of relative permittivity eta (vacuum on the incident side), their
+ * eta-derivatives (quotient rule, ds/deta = 1/(2 s)), and
+ * s = sqrt(eta - sin^2 theta_1) (principal branch). */
+static void fresnel_half_space(cplx eta, double c, cplx* s_out, cplx* r_perp, cplx* r_par,
+                               cplx* dr_perp, cplx* dr_par)
+{
+    double s2 = 1.0 - c * c;                  /* sin^2(theta_1) */
+    cplx s = csqrt(eta - s2);
+    cplx den_p = c + s, den_l = eta * c + s;
+    *r_perp = (c - s) / den_p;
+    *r_par = (eta * c - s) / den_l;
+    cplx ds = 1.0 / (2.0 * s);
+    *dr_perp = ((-ds) * den_p - (c - s) * ds) / (den_p * den_p);
+    *dr_par = ((c - ds) * den_l - (eta * c - s) * (c + ds)) / (den_l * den_l);
+    *s_out = s;
+}
+
+/* eq. fresnel_in_vectors, eq. fresnel_out_vectors: the TE direction e_perp
+ * (any unit vector normal to k at normal incidence: k x a, a the axis least
+ * aligned with k), the incident TM direction e_par = e_perp x k, the
+ * reflected direction k_r and its TM direction er_par = e_perp x k_r.  The
+ * normal n points to the incident side. */
+static void reflection_bases(vec3 k, vec3 nrm, vec3* e_perp_out, vec3* e_par, vec3* kr_out, vec3* er_par)
+{
+    vec3 kn = vcross(k, nrm);
+    vec3 e_perp;
+    if (vnorm(kn) > 1e-12) {
+        e_perp = vunit(kn);
+    } else {
+        double ax = fabs(k.x), ay = fabs(k.y), az = fabs(k.z);
+        vec3 a = (ax <= ay && ax <= az) ? mk(1, 0, 0) : (ay <= az ? mk(0, 1, 0) : mk(0, 0, 1));
+        e_perp = vunit(vcross(k, a));
+    }
+    *e_par = vcross(e_perp, k);
+    vec3 kr = vsub(k, vscale(nrm, 2.0 * vdot(k, nrm)));
+    kr = vunit(kr);
+    *er_par = vunit(vcross(e_perp, kr));
+    *e_perp_out = e_perp;
+    *kr_out = kr;
+}
+
+/* The field leaving an interaction (eq. fresnel_out_vectors): the TE part
+ * e_perp^T E scaled by c_perp along e_perp, the TM part e_par^T E scaled by
+ * c_par along out_par (real basis vectors, no conjugation), both times
+ * inv_sqrt_q. */
+static cvec3 specular_field(cvec3 E, vec3 e_perp, vec3 e_par, vec3 out_par, cplx c_perp, cplx c_par,
+                            double inv_sqrt_q)
+{
+    cplx a_perp = cv_dot_real(e_perp, E);
+    cplx a_par = cv_dot_real(e_par, E);
+    cvec3 En = cv_zero();
+    En = cv_axpy(En, c_perp * a_perp * inv_sqrt_q, e_perp);
+    En = cv_axpy(En, c_par * a_par * inv_sqrt_q, out_par);
+    return En;
+}
+
 /* ------------------------------------------------------- dual numbers (3) */
 /* value + derivatives w.r.t. (yaw, pitch, roll) */
 typedef struct { double v, d[3]; } dual;
@@ -718,15 +776,8 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             int m = tri_mat[h.prim];
             cplx eta = eps_r[m] - I * sigma[m] / (OR_EPS0 * omega);
             double c = -vdot(nrm, k);                 /* cos(theta_1) >= 0 */
-            double s2 = 1.0 - c * c;                  /* sin^2(theta_1) */
-            cplx s = csqrt(eta - s2);
-            cplx den_p = c + s, den_l = eta * c + s;
-            cplx r_perp = (c - s) / den_p;
-            cplx r_par = (eta * c - s) / den_l;
-            /* derivatives w.r.t. eta (quotient rule; ds/deta = 1/(2 s)) */
-            cplx ds = 1.0 / (2.0 * s);
-            cplx dr_perp = ((-ds) * den_p - (c - s) * ds) / (den_p * den_p);
-            cplx dr_par = ((c - ds) * den_l - (eta * c - s) * (c + ds)) / (den_l * den_l);
+            cplx s, r_perp, r_par, dr_perp, dr_par;
+            fresnel_half_space(eta, c, &s, &r_perp, &r_par, &dr_perp, &dr_par);
 
             cplx t_perp = 0.0, t_par = 0.0, dt_perp = 0.0, dt_par = 0.0;
             if (thickness) {
@@ -739,19 +790,8 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                 slab(s, k_d, &r_perp, &r_par, &t_perp, &t_par);
             }
 
-            vec3 kn = vcross(k, nrm);
-            vec3 e_perp;
-            if (vnorm(kn) > 1e-12) {
-                e_perp = vunit(kn);
-            } else {
-                double ax = fabs(k.x), ay = fabs(k.y), az = fabs(k.z);
-                vec3 a = (ax <= ay && ax <= az) ? mk(1, 0, 0) : (ay <= az ? mk(0, 1, 0) : mk(0, 0, 1));
-                e_perp = vunit(vcross(k, a));
-            }
-            vec3 e_par = vcross(e_perp, k);
-            vec3 kr = vsub(k, vscale(nrm, 2.0 * vdot(k, nrm)));
-            kr = vunit(kr);
-            vec3 er_par = vunit(vcross(e_perp, kr));
+            vec3 e_perp, e_par, kr, er_par;
+            reflection_bases(k, nrm, &e_perp, &e_par, &kr, &er_par);
 
             /* interaction type (eq. path-solver-used-dist-event with
              * q(D) = 0): with A = |r_perp|^2 + |r_par|^2 and B = |t_perp|^2 +
@@ -871,10 +911,7 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                             dE[p][q] = nd;
                         }
                     }
-                    cvec3 En = cv_zero();
-                    En = cv_axpy(En, c_perp * a_perp * inv_sqrt_q, e_perp);
-                    En = cv_axpy(En, c_par * a_par * inv_sqrt_q, out_par);
-                    E[p] = En;
+                    E[p] = specular_field(E[p], e_perp, e_par, out_par, c_perp, c_par, inv_sqrt_q);
                 }
             }
             o = vadd(o, vscale(k, h.t));
@@ -914,6 +951,42 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
             }
         }
     }
+    return 0;
+}
+
+/* Field transport along a given specular chain, for tests (reciprocity):
+ * pts [n_pts][3] are the source, the reflection points and the end point;
+ * nrms [n_pts-2][3], eps_r and sigma [n_pts-2] describe the surface at each
+ * reflection point.  The complex field E0 (E0[2 i], E0[2 i + 1] = Re, Im of
+ * component i), transverse to the first segment, is carried through every
+ * reflection with the interaction step of the radio map (half-space
+ * eq. fresnel_vac, the bases of eq. fresnel_in_vectors and
+ * eq. fresnel_out_vectors); the directions after each reflection are the
+ * reflected ones, not re-derived from the points.  out[0..5] is the field at
+ * the end point, out[6..8] the direction of the last segment.
+ * Returns 1 for bad sizes. */
+int or_path_field(const double* pts, int32_t n_pts, const double* nrms, const double* eps_r,
+                  const double* sigma, double freq, const double* E0, double* out)
+{
+    if (n_pts < 2) return 1;
+    const double omega = 2.0 * OR_PI * freq;
+    vec3 k = vunit(vsub(mk(pts[3], pts[4], pts[5]), mk(pts[0], pts[1], pts[2])));
+    cvec3 E = {E0[0] + I * E0[1], E0[2] + I * E0[3], E0[4] + I * E0[5]};
+    for (int32_t i = 0; i + 2 < n_pts; i++) {
+        vec3 nrm = vunit(mk(nrms[3 * i], nrms[3 * i + 1], nrms[3 * i + 2]));
+        if (vdot(nrm, k) > 0.0) nrm = vscale(nrm, -1.0);
+        const cplx eta = eps_r[i] - I * sigma[i] / (OR_EPS0 * omega);
+        cplx sq, r_perp, r_par, dr_perp, dr_par;
+        fresnel_half_space(eta, -vdot(nrm, k), &sq, &r_perp, &r_par, &dr_perp, &dr_par);
+        vec3 e_perp, e_par, kr, er_par;
+        reflection_bases(k, nrm, &e_perp, &e_par, &kr, &er_par);
+        E = specular_field(E, e_perp, e_par, er_par, r_perp, r_par, 1.0);
+        k = kr;
+    }
+    out[0] = creal(E.x); out[1] = cimag(E.x);
+    out[2] = creal(E.y); out[3] = cimag(E.y);
+    out[4] = creal(E.z); out[5] = cimag(E.z);
+    out[6] = k.x; out[7] = k.y; out[8] = k.z;
     return 0;
 }
 

@@ -309,6 +309,85 @@ def test_reciprocity_dual_pol(oracle_lib):
     assert abs(ga / gb - 1) <= 3 / math.sqrt(n)
 
 
+def _mirror(p, q, n):
+    return p - 2.0 * np.dot(p - q, n) * n
+
+
+def _image_chain(A, B, planes):
+    """Reflection points of the specular path A -> planes[0] -> ... -> B by
+    the image method (planes: (point, unit normal)); None if a reflection
+    point falls outside its segment."""
+    imgs = [None] * len(planes)
+    img = B
+    for i in range(len(planes) - 1, -1, -1):
+        img = _mirror(img, *planes[i])
+        imgs[i] = img
+    pts, cur = [A], A
+    for i, (q, n) in enumerate(planes):
+        d = imgs[i] - cur
+        den = np.dot(d, n)
+        if abs(den) < 1e-12:
+            return None
+        t = np.dot(q - cur, n) / den
+        if not 1e-6 < t < 1 - 1e-6:
+            return None
+        cur = cur + t * d
+        pts.append(cur)
+    pts.append(B)
+    return np.array(pts)
+
+
+def _transfer(oracle_lib, pts, planes, mats):
+    """3x2 transfer matrix of the chain on the two transverse unit fields at
+    the source, and the direction of the last segment."""
+    k0 = (pts[1] - pts[0]) / np.linalg.norm(pts[1] - pts[0])
+    u1 = np.cross(k0, [0.3, 0.5, 0.8])
+    u1 /= np.linalg.norm(u1)
+    u2 = np.cross(k0, u1)
+    nrm = [n for _, n in planes]
+    cols = []
+    for u in (u1, u2):
+        E, k = oracle_lib.path_field(pts, nrm, [m[0] for m in mats], [m[1] for m in mats], 3.5e9,
+                                     u.astype(complex))
+        cols.append(E)
+    return np.stack(cols, axis=1), k
+
+
+def test_reciprocity_exact_per_path(oracle_lib):
+    """Reciprocity of the field transport, path by path: for specular chains
+    of one to three reflections on a ground (z = 0) and two walls (x = 30,
+    y = 40), built by the image method between random points A and B with
+    random materials, the transfer matrix of A -> B and that of the reverse
+    chain B -> A have the same singular values (so the same Frobenius norm)
+    to 1e-12; every reflected direction of the oracle reproduces the image
+    geometry, and the field stays transverse to it."""
+    rng = np.random.default_rng(3)
+    ground = (np.zeros(3), np.array([0.0, 0.0, 1.0]))
+    wall_x = (np.array([30.0, 0.0, 0.0]), np.array([-1.0, 0.0, 0.0]))
+    wall_y = (np.array([0.0, 40.0, 0.0]), np.array([0.0, -1.0, 0.0]))
+    sequences = [[ground], [wall_x], [ground, wall_x], [wall_x, ground], [wall_x, ground, wall_y],
+                 [ground, wall_y, wall_x], [wall_y, wall_x, ground]]
+    n_checked = 0
+    for trial in range(60):
+        seq = sequences[trial % len(sequences)]
+        A = np.array([rng.uniform(-20, 25), rng.uniform(-20, 35), rng.uniform(1, 30)])
+        B = np.array([rng.uniform(-20, 25), rng.uniform(-20, 35), rng.uniform(1, 30)])
+        pts = _image_chain(A, B, seq)
+        if pts is None:
+            continue
+        mats = [(rng.uniform(2.0, 10.0), 10 ** rng.uniform(-3, 0)) for _ in seq]
+        M, k = _transfer(oracle_lib, pts, seq, mats)
+        Mr, kr = _transfer(oracle_lib, pts[::-1].copy(), seq[::-1], mats[::-1])
+        last = (pts[-1] - pts[-2]) / np.linalg.norm(pts[-1] - pts[-2])
+        assert np.allclose(k, last, atol=1e-12) and np.allclose(kr, -(pts[1] - pts[0]) / np.linalg.norm(pts[1] - pts[0]),
+                                                                 atol=1e-12)
+        assert np.abs(k @ M).max() <= 1e-12 and np.abs(kr @ Mr).max() <= 1e-12
+        sv, svr = np.linalg.svd(M, compute_uv=False), np.linalg.svd(Mr, compute_uv=False)
+        assert np.allclose(sv, svr, rtol=0, atol=1e-12 * sv.max()), (seq, sv, svr)
+        n_checked += 1
+    assert n_checked >= 30
+
+
 # ------------------------------------------------------------- gradients
 def test_forward_mode_gradient_matches_central_fd(oracle_lib):
     """Oracle tangents vs FP64 central finite differences (h = 1e-4 relative) on a
