@@ -556,7 +556,8 @@ def diffuse_leg(rt, sg, cfg, scene, eps, sig, dev, out):
     """Diffuse reflection: the Manhattan workload (1e7 rays, L = 5) with
     scattering coefficients S = 0.4 (concrete) and 0.2 (glass) and
     cross-polarisation shares K_x = 0.1 and 0.3, Lambertian pattern; every
-    hit samples specular or diffuse reflection."""
+    hit samples specular or diffuse reflection.  Also forward + adjoint over
+    forward for the differentiation transmitter with the same materials."""
     import torch
     sca = torch.tensor([0.4, 0.2], dtype=torch.float32, device=dev)
     xpd = torch.tensor([0.1, 0.3], dtype=torch.float32, device=dev)
@@ -565,8 +566,31 @@ def diffuse_leg(rt, sg, cfg, scene, eps, sig, dev, out):
     rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, p, out, stats=stats, scattering=sca, xpd=xpd)
     seg = int(stats[0])
     ms = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, p, out, scattering=sca, xpd=xpd), 5, 1)
-    return {"workload": "manhattan, 1e7 rays, L = 5, Lambertian S = 0.4 / 0.2, K_x = 0.1 / 0.3 (concrete / glass)",
-            "ms": round(ms, 3), "segments": seg, "M ray-bounces/s": round(seg / (ms * 1e-3) / 1e6, 1)}
+    res = {"workload": "manhattan, 1e7 rays, L = 5, Lambertian S = 0.4 / 0.2, K_x = 0.1 / 0.3 (concrete / glass)",
+           "ms": round(ms, 3), "segments": seg, "M ray-bounces/s": round(seg / (ms * 1e-3) / 1e6, 1)}
+    # forward with a tape + adjoint over forward: the differentiation
+    # transmitter (directional, yaw 30 deg, pitch -10 deg), 1e6 rays, L = 4
+    dc = sg.diff_config()
+    pd = sg.Params(dc.params.freq_hz, dc.params.n_rays, dc.params.max_depth, seed=1)
+    m = torch.empty((1, dc.plane.H, dc.plane.W), dtype=torch.float32, device=dev)
+    tape = rt.rt_tape_create(pd)
+    g = torch.randn((1, dc.plane.H, dc.plane.W), dtype=torch.float32, device=dev)
+    ge = torch.empty(2, dtype=torch.float32, device=dev)
+    gs = torch.empty(2, dtype=torch.float32, device=dev)
+    go = torch.empty(3, dtype=torch.float32, device=dev)
+
+    def fwd():
+        rt.rt_radio_map(scene, eps, sig, dc.tx, dc.plane, pd, m, scattering=sca, xpd=xpd)
+
+    def fwdbwd():
+        rt.rt_radio_map(scene, eps, sig, dc.tx, dc.plane, pd, m, tape=tape, scattering=sca, xpd=xpd)
+        rt.rt_radio_map_backward(scene, eps, sig, dc.tx, dc.plane, pd, tape, g, ge, gs, go, scattering=sca, xpd=xpd)
+
+    t_f = _time(fwd, 5)
+    t_fb = _time(fwdbwd, 5)
+    res["fwd_bwd_over_fwd"] = {"workload": "same materials, directional Tx (yaw 30, pitch -10 deg), 1e6 rays, L = 4",
+                               "fwd_ms": round(t_f, 4), "fwd_bwd_ms": round(t_fb, 4), "ratio": round(t_fb / t_f, 3)}
+    return res
 
 
 def _time(fn, reps=10, warm=2):
