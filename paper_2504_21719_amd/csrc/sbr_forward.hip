@@ -341,6 +341,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     // and 1 / kappa of that transmitter
     int64_t nlat = 0;
     float ikap = a.inv_kappa;
+    int tslot = 0;            // output slot of the lane's transmitter (several transmitters)
 
     while (true) {
         // ---- refill lanes without a ray: from this wavefront's reservoir of
@@ -420,6 +421,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                             mapb = a.map + (int64_t)a.slots[t] * a.slot_stride;
                             nlat = n;
                             ikap = 1.0f / td.kappa;
+                            tslot = a.slots[t];
                         }
                         Launch Lr = fib_launch(n, td.n_rays);
                         if (MODE != MODE_GEOM) {
@@ -523,6 +525,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                 int leader = __ffsll((long long)pend) - 1;
                 int lc = __shfl(cell, leader);
                 bool mine = !done && cell == lc;
+                if (MODE == MODE_MULTI) {
+                    // lanes of other transmitters deposit into other maps
+                    const int ls = __shfl(tslot, leader);
+                    mine = mine && tslot == ls;
+                }
                 unsigned long long grp = __ballot(mine);
                 float v0 = wave_sum(mine ? w0 : 0.0f);
                 float v1 = 0.0f;

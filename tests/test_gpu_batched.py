@@ -212,3 +212,35 @@ def test_multi_transmitter_extensions_match_single_calls(case):
         off = ~np.isclose(a, b, rtol=1e-4, atol=1e-7 * b.max())
         assert off.sum() <= 20, (t, int(off.sum()))
         assert a.sum() == pytest.approx(b.sum(), rel=1e-4)
+
+
+@pytest.mark.parametrize("deposit", [1, 2])
+def test_multi_transmitter_deposits_stay_in_their_maps(deposit):
+    """A wavefront can hold rays of several transmitters, so its same-cell
+    sums must group lanes by transmitter as well as by cell.  256 iso
+    transmitters at the street intersection (0, 0, 30) with lattices of 2 or 4 rays
+    (per-ray weights differ twofold): one claim of work spans about twenty
+    transmitters, whose downward rays cross the 250 m cell below them in the
+    same iteration.  Every transmitter's batched map equals its single-call
+    map, with per-lane atomics and with wavefront sums."""
+    rt, torch, scene, s, txs, budgets, plane, params = _setup(n_tx=1)
+    pos = (0.0, 0.0, 30.0)
+    T = 256
+    txs = [sg.Tx(pos) for _ in range(T)]
+    budgets = [2 if i % 2 == 0 else 4 for i in range(T)]
+    plane = sg.Plane(1.5, pos[0] - 500.0, pos[1] - 500.0, 250.0, 250.0, 4, 4)
+    eps = torch.tensor(scene.eps_r, dtype=torch.float32, device="cuda")
+    sig = torch.tensor(scene.sigma, dtype=torch.float32, device="cuda")
+    out = torch.empty((T, 1, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    rt.rt_radio_map_batched(s, eps[None], sig[None], txs, budgets, plane, params, out, deposit=deposit)
+    torch.cuda.synchronize()
+    got = out[:, 0].cpu().numpy()
+    assert (got > 0).any()
+    for t in range(T):
+        ref = torch.empty((1, plane.H, plane.W), dtype=torch.float32, device="cuda")
+        p = sg.Params(params.freq_hz, int(budgets[t]), params.max_depth)
+        rt.rt_radio_map(s, eps, sig, txs[t], plane, p, ref, deposit=deposit)
+        torch.cuda.synchronize()
+        b = ref[0].cpu().numpy()
+        np.testing.assert_allclose(got[t], b, rtol=2e-5, atol=1e-7 * max(b.max(), 1e-30),
+                                   err_msg="transmitter %d" % t)
