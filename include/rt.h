@@ -41,6 +41,15 @@
  *     writes no output.
  *   - The library never takes ownership of caller memory.  Objects it creates
  *     (rt_scene, rt_tape) are released only by their destroy calls.
+ *   - Environment overrides of the launch configuration, for experiments
+ *     (each changes results only up to FP32 summation order):
+ *     RTMAP_WIDTH (2: binary tree, else 4-wide), RTMAP_ORDER (0: lattice
+ *     launch order, else coherent), RTMAP_REFILL (idle lanes a wavefront
+ *     waits for before it takes new rays, 1..64), RTMAP_QUEUES (number of
+ *     work queues, 1..256), RTMAP_CLAIM (rays per claim, 64..4096),
+ *     RTMAP_NO_GRAPH (set: rt_radio_map_batched launches its kernels instead
+ *     of replaying the captured graph).  They override rt_tune's choice and
+ *     rt_set_launch_config.
  */
 #ifndef RTMAP_RT_H
 #define RTMAP_RT_H
