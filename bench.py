@@ -549,6 +549,27 @@ def refraction_leg(rt, sg, cfg, dev, out, launch=""):
     res["fwd_bwd_over_fwd"] = {"workload": "same scene and slabs, refraction, directional Tx (yaw 30, pitch -10 "
                                            "deg), 1e6 rays, L = 4", "fwd_ms": round(t_f, 4),
                                "fwd_bwd_ms": round(t_fb, 4), "ratio": round(t_fb / t_f, 3)}
+    del tape
+    # batched transmitters with refraction: the 64 rooftop transmitters of the
+    # plain batched leg, one call against the per-transmitter loop
+    txs, budgets = sg.rooftop_transmitters(64, seed=5, buildings=sg.manhattan_buildings(sg.manhattan_scene()))
+    T = len(txs)
+    maps = torch.empty((T, 1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device=dev)
+    pb = sg.Params(cfg.params.freq_hz, 1, cfg.params.max_depth, refraction=1, seed=1)
+    plist = [sg.Params(cfg.params.freq_hz, int(b), cfg.params.max_depth, refraction=1, seed=1) for b in budgets]
+
+    def plain_loop():
+        for t in range(T):
+            rt.rt_radio_map(scene, eps, sig, txs[t], cfg.plane, plist[t], maps[t], thickness=thk)
+
+    def batched():
+        rt.rt_radio_map_batched(scene, eps[None], sig[None], txs, budgets, cfg.plane, pb, maps, thickness=thk)
+
+    t_plain = _time(plain_loop, 3, 1)
+    t_batch = _time(batched, 3, 1)
+    res["batched_tx_over_plain"] = {"workload": "64 rooftop Tx, %d rays, same slabs, refraction" % int(sum(budgets)),
+                                    "batched_ms": round(t_batch, 3), "plain_loop_ms": round(t_plain, 3),
+                                    "ratio": round(t_plain / t_batch, 3)}
     return res
 
 
