@@ -102,6 +102,10 @@ struct FwdArgs {
 // (records hit slots, cells, directions and bases for a later field pass).
 enum { MODE_SINGLE = 0, MODE_MULTI = 1, MODE_GEOM = 2 };
 
+// Wavefront deposit: same-cell groups summed before the atomics (4 measured
+// best against 1, 2 and no limit on the Manhattan and rooftop workloads).
+constexpr int kDepositGroups = 4;
+
 // Index of the transmitter whose ray range holds global ray g.
 __device__ __forceinline__ int find_tx(const int64_t* __restrict__ prefix, int n_tx, int64_t g) {
     int lo = 0, hi = n_tx;
@@ -519,9 +523,22 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
         if (MODE == MODE_GEOM) {
             // fields are computed later, per material sample
         } else if (a.deposit == 2) {
+            // at most kDepositGroups same-cell groups are summed across the
+            // wavefront; lanes left over add their own crossings (crossings
+            // scattered over many cells would otherwise cost one wavefront
+            // reduction per cell)
             unsigned long long pend = __ballot(cell >= 0);
             bool done = cell < 0;
+            int groups = 0;
             while (pend) {
+                if (groups == kDepositGroups) {
+                    if (!done) {
+                        unsafeAtomicAdd(mapb + cell, w0);
+                        if (a.npol == 2) unsafeAtomicAdd(mapb + a.map_stride + cell, w1);
+                    }
+                    break;
+                }
+                groups++;
                 int leader = __ffsll((long long)pend) - 1;
                 int lc = __shfl(cell, leader);
                 bool mine = !done && cell == lc;
