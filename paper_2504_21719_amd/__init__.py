@@ -126,17 +126,45 @@ def _stream(stream=None):
     return C.c_void_p(stream.cuda_stream)
 
 
-def _ptr(t):
+def _validate(t, name="tensor", dtype=None, numel=None):
+    """Check a tensor's type, dtype and that it holds at least ``numel``
+    elements (the kernels read or write that many; a smaller buffer would be
+    overrun on the device)."""
     if t is None:
-        return None
+        return
     import torch
     if not isinstance(t, torch.Tensor):
-        raise TypeError("expected a torch tensor")
-    if not t.is_cuda:
-        raise ValueError("expected a device tensor")
+        raise TypeError("%s: expected a torch tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s: expected dtype %s, got %s" % (name, dtype, t.dtype))
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s: needs at least %d elements, got %d" % (name, numel, t.numel()))
     if not t.is_contiguous():
-        raise ValueError("expected a contiguous tensor")
+        raise ValueError("%s: expected a contiguous tensor" % name)
+
+
+def _ptr(t, name="tensor", dtype=None, numel=None):
+    """Device pointer of a checked contiguous device tensor (None for None)."""
+    if t is None:
+        return None
+    _validate(t, name, dtype, numel)
+    if not t.is_cuda:
+        raise ValueError("%s: expected a device tensor" % name)
     return C.c_void_p(t.data_ptr())
+
+
+def _ptrs(*specs):
+    """Pointers of several (tensor, name, dtype, numel) specs: every dtype and
+    size is checked before any device check, so the first error names the
+    first wrong tensor."""
+    for sp in specs:
+        _validate(*sp)
+    return [_ptr(*sp) for sp in specs]
+
+
+def _f32spec(t, name, numel):
+    import torch
+    return (t, name, torch.float32, numel)
 
 
 # ----------------------------------------------------------------- structs
@@ -214,9 +242,12 @@ class RtScene:
 
 def rt_build_scene(vertices, triangles, tri_material, n_materials, stream=None) -> RtScene:
     """vertices f32 [n_v,3], triangles i32 [n_t,3], tri_material i32 [n_t] (device tensors)."""
+    import torch
+    n_v, n_t = int(vertices.shape[0]), int(triangles.shape[0])
+    pv, pf, pm = _ptrs((vertices, "vertices", torch.float32, 3 * n_v), (triangles, "triangles", torch.int32, 3 * n_t),
+                       (tri_material, "tri_material", torch.int32, n_t))
     h = C.c_void_p()
-    _check(lib().rt_build_scene(_ptr(vertices), int(vertices.shape[0]), _ptr(triangles), int(triangles.shape[0]),
-                                _ptr(tri_material), int(n_materials), _stream(stream), C.byref(h)))
+    _check(lib().rt_build_scene(pv, n_v, pf, n_t, pm, int(n_materials), _stream(stream), C.byref(h)))
     return RtScene(h, int(n_materials))
 
 
@@ -231,9 +262,33 @@ def scene_from_mesh(scene, device="cuda") -> RtScene:
     return rt_build_scene(V, F, M, len(scene.eps_r))
 
 
-def materials(eps_r, sigma, thickness=None, scattering=None, xpd=None, scatter_pattern=None) -> rt_materials:
-    return rt_materials(_ptr(eps_r), _ptr(sigma), _ptr(thickness), _ptr(scattering), _ptr(xpd),
-                        _ptr(scatter_pattern))
+def _material_specs(eps_r, sigma, thickness=None, scattering=None, xpd=None, scatter_pattern=None,
+                    n_materials=None, n_samples=1):
+    nm = None if n_materials is None else int(n_materials)
+    ns = None if nm is None else nm * int(n_samples)
+    p4 = None if nm is None else 4 * nm
+    return [_f32spec(eps_r, "eps_r", ns), _f32spec(sigma, "sigma", ns), _f32spec(thickness, "thickness", nm),
+            _f32spec(scattering, "scattering", nm), _f32spec(xpd, "xpd", nm),
+            _f32spec(scatter_pattern, "scatter_pattern", p4)]
+
+
+def materials(eps_r, sigma, thickness=None, scattering=None, xpd=None, scatter_pattern=None, *,
+              n_materials=None, n_samples=1) -> rt_materials:
+    """Material descriptor.  With ``n_materials`` every array is checked to be
+    float32 and long enough: eps_r and sigma [n_samples][n_materials], the
+    optional per-material arrays [n_materials], scatter_pattern [n_materials][4]."""
+    return rt_materials(*_ptrs(*_material_specs(eps_r, sigma, thickness, scattering, xpd, scatter_pattern,
+                                                n_materials, n_samples)))
+
+
+def _npol(tx):
+    return 2 if int(tx.pol) == RT_POL_DUAL else 1
+
+
+def _range_rays(p):
+    b = int(p.ray_begin)
+    e = int(p.ray_end) if int(p.ray_end) > 0 else int(p.n_rays)
+    return max(0, e - b)
 
 
 # ----------------------------------------------------------------- forward
@@ -247,15 +302,18 @@ def rt_radio_map(scene: RtScene, eps_r, sigma, tx, plane, params, out_map, *, ta
     ``scattering`` and ``xpd`` (device f32 [n_mat]) enable diffuse
     reflection, Lambertian unless ``scatter_pattern`` (device f32 [n_mat][4])
     selects directive or backscattering lobes."""
-    rec = rt_records(_ptr(hits), _ptr(cells), _ptr(weights), _ptr(stats))
+    import torch
     p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
-    t = tx if isinstance(tx, rt_tx) else make_tx(tx)
     pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
-    _check(lib().rt_radio_map(scene.handle, materials(eps_r, sigma, thickness, scattering, xpd, scatter_pattern),
-                              C.byref(t),
-                              C.byref(pl), C.byref(p),
-                              _ptr(out_map), tape.handle if tape is not None else None, C.byref(rec),
-                              _stream(stream)))
+    nrec = _range_rays(p) * (int(p.max_depth) + 1)
+    ptr = _ptrs(*_material_specs(eps_r, sigma, thickness, scattering, xpd, scatter_pattern, scene.n_materials),
+                _f32spec(out_map, "out_map", _npol(tx) * int(pl.W) * int(pl.H)),
+                (hits, "hits", torch.int32, nrec), (cells, "cells", torch.int32, nrec),
+                _f32spec(weights, "weights", nrec), (stats, "stats", torch.int64, 5))
+    mats, pmap, rec = rt_materials(*ptr[:6]), ptr[6], rt_records(*ptr[7:])
+    t = tx if isinstance(tx, rt_tx) else make_tx(tx)
+    _check(lib().rt_radio_map(scene.handle, mats, C.byref(t), C.byref(pl), C.byref(p), pmap,
+                              tape.handle if tape is not None else None, C.byref(rec), _stream(stream)))
     return out_map
 
 
@@ -289,13 +347,15 @@ def rt_radio_map_backward(scene: RtScene, eps_r, sigma, tx, plane, params, tape:
     """Adjoint of a forward call recorded on ``tape`` (same materials,
     thickness, scattering, transmitter, plane and parameters)."""
     p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
-    t = tx if isinstance(tx, rt_tx) else make_tx(tx)
     pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
-    _check(lib().rt_radio_map_backward(scene.handle, materials(eps_r, sigma, thickness, scattering, xpd,
-                                                                   scatter_pattern),
-                                       C.byref(t), C.byref(pl), C.byref(p),
-                                       tape.handle, _ptr(grad_map), _ptr(grad_eps_r), _ptr(grad_sigma),
-                                       _ptr(grad_orient), _stream(stream)))
+    nm = scene.n_materials
+    ptr = _ptrs(*_material_specs(eps_r, sigma, thickness, scattering, xpd, scatter_pattern, nm),
+                _f32spec(grad_map, "grad_map", _npol(tx) * int(pl.W) * int(pl.H)),
+                _f32spec(grad_eps_r, "grad_eps_r", nm), _f32spec(grad_sigma, "grad_sigma", nm),
+                _f32spec(grad_orient, "grad_orient", 3))
+    t = tx if isinstance(tx, rt_tx) else make_tx(tx)
+    _check(lib().rt_radio_map_backward(scene.handle, rt_materials(*ptr[:6]), C.byref(t), C.byref(pl), C.byref(p),
+                                       tape.handle, *ptr[6:], _stream(stream)))
 
 
 def rt_radio_map_batched(scene: RtScene, eps_r, sigma, txs: Sequence, rays_per_tx: Sequence[int], plane, params,
@@ -308,28 +368,37 @@ def rt_radio_map_batched(scene: RtScene, eps_r, sigma, txs: Sequence, rays_per_t
     the early-termination and refraction fields of ``params`` apply as in
     ``rt_radio_map``."""
     n_tx = len(txs)
+    if len(rays_per_tx) != n_tx:
+        raise ValueError("rays_per_tx: one budget per transmitter")
+    p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
+    pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
+    S = int(eps_r.shape[0]) if eps_r.dim() == 2 else 1
+    nm = scene.n_materials
+    nmap = n_tx * S * int(pl.W) * int(pl.H)
+    ptr = _ptrs(*_material_specs(eps_r, sigma, thickness, scattering, xpd, scatter_pattern, nm, S),
+                _f32spec(out_maps, "out_maps", nmap), _f32spec(grad_maps, "grad_maps", nmap),
+                _f32spec(grads, "grads", n_tx * S * (2 * nm + 3)))
+    mats, ptrs = rt_materials(*ptr[:6]), ptr[6:]
     # the descriptors keep the transmit-array tensors alive for the call
     descs = [tx if isinstance(tx, rt_tx) else make_tx(tx) for tx in txs]
     arr = (rt_tx * n_tx)(*descs)
     budgets = (C.c_int64 * n_tx)(*[int(b) for b in rays_per_tx])
-    p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
-    pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
-    S = int(eps_r.shape[0]) if eps_r.dim() == 2 else 1
-    mats = materials(eps_r, sigma, thickness, scattering, xpd, scatter_pattern)
     _check(lib().rt_radio_map_batched(scene.handle, mats, S, arr, C.cast(budgets, C.c_void_p),
-                                      n_tx, C.byref(pl), C.byref(p), _ptr(out_maps), _ptr(grad_maps), _ptr(grads),
-                                      _stream(stream)))
+                                      n_tx, C.byref(pl), C.byref(p), *ptrs, _stream(stream)))
     del descs
     return out_maps
 
 
 def rt_tune(scene: RtScene, eps_r, sigma, tx, plane, params, n_probe_rays, scratch_map, stream=None, **pkw):
     p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
-    t = tx if isinstance(tx, rt_tx) else make_tx(tx)
     pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
+    ptr = _ptrs(*_material_specs(eps_r, sigma, n_materials=scene.n_materials),
+                _f32spec(scratch_map, "scratch_map", _npol(tx) * int(pl.W) * int(pl.H)))
+    mats, pmap = rt_materials(*ptr[:6]), ptr[6]
+    t = tx if isinstance(tx, rt_tx) else make_tx(tx)
     b, d = C.c_int32(), C.c_int32()
-    _check(lib().rt_tune(scene.handle, materials(eps_r, sigma), C.byref(t), C.byref(pl), C.byref(p),
-                         int(n_probe_rays), _ptr(scratch_map), _stream(stream), C.byref(b), C.byref(d)))
+    _check(lib().rt_tune(scene.handle, mats, C.byref(t), C.byref(pl), C.byref(p),
+                         int(n_probe_rays), pmap, _stream(stream), C.byref(b), C.byref(d)))
     return b.value, d.value
 
 

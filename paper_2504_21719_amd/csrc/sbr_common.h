@@ -325,10 +325,13 @@ __device__ __forceinline__ void box2(const Ray& r, float4 q0, float4 q1, float4 
 }
 
 // Buffer resource over the 4-wide node array: loads are range-checked by
-// the hardware against `bytes` (an offset outside reads zeros), so a bad node
-// reference can never read outside the array.
+// the hardware against the array's byte size (an offset outside reads
+// zeros), so a bad node reference can never read outside the array.  The
+// size is a 32-bit unsigned count: the build keeps n_wide below 2^25, so
+// 128 n_wide stays below 2^32, and so do the node offsets node << 7.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t wide_rsrc(const float4* wide, int n_wide) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)wide, (short)0, n_wide * 128, 0x00020000);
+    const unsigned bytes = (unsigned)n_wide * 128u;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)wide, (short)0, (int)bytes, 0x00020000);
 }
 
 __device__ __forceinline__ float4 ld16(__amdgpu_buffer_rsrc_t rs, unsigned off) {

@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 import scenegen as sg
-from gpu_helpers import compare_hits, gpu_radio_map, gpu_scene, scene_diag
+from gpu_helpers import compare_hits, compare_sampled, gpu_radio_map, gpu_scene, scene_diag
 
 pytestmark = pytest.mark.gpu
 LAM = 299792458.0 / 3.5e9
@@ -39,7 +39,7 @@ def _check(cfg, tx):
     rec, rec1 = o.records, o1.records
     assert np.array_equal(rec["ray"], rec1["ray"]) and np.array_equal(rec["depth"], rec1["depth"])
     S2 = float(np.sum(np.abs(tx.array.precoding.astype(np.complex128)))) ** 2
-    hr, bad = compare_hits(g.hits, o.hits, o.flags, cfg.params.n_rays)
+    hr, bad, _ = compare_hits(g.hits, o.hits, o.flags)
     assert hr["ok"], hr
     keep = ~np.isin(rec["ray"], bad)
     r, l = rec["ray"][keep], rec["depth"][keep]
@@ -110,19 +110,24 @@ def test_large_ula_full_lattice_sampled():
     big = acc > 1e-9 * acc.max()
     np.testing.assert_allclose(g.map[0][big], acc[big], rtol=1e-4)
     N = cfg.params.n_rays
-    ids = np.arange(11, N, N // 800, dtype=np.int64)
+    ids = np.arange(11, N, N // 100_000, dtype=np.int64)[:100_000]
     o = oracle.radio_map(cfg.scene, tx, cfg.plane, cfg.params, ray_ids=ids, want_records=True)
-    o1 = oracle.radio_map(cfg.scene, sg.Tx(cfg.tx.pos), cfg.plane, cfg.params, ray_ids=ids, want_records=True)
-    rep, bad = compare_hits(g.hits[ids], o.hits, o.flags, ids.size, max_frac=1.0)
-    assert not rep["unexplained"], rep
     S2 = float(np.sum(np.abs(tx.array.precoding.astype(np.complex128)))) ** 2
-    badrays = set(ids[bad].tolist())
-    n_checked = 0
-    for r_, l_, w_, w1_, b_, len_ in zip(o.records["ray"], o.records["depth"], o.records["w"], o1.records["w"],
-                                        o.records["border"], o.records["length"]):
-        if int(r_) in badrays or b_ <= 1e-6 * (len_ + 1500.0):
-            continue
-        gw = float(g.weights[r_, l_])
-        assert abs(gw - w_) <= 1e-5 * w_ + 1e-5 * S2 * w1_ * 4, (r_, l_, gw, w_)
-        n_checked += 1
-    assert n_checked > 200
+    tx1 = sg.Tx(cfg.tx.pos)
+
+    def tol(recs, rids, rhits):
+        # 1e-5 (sum |u_i|)^2 w1 (times 4 at this array size), with w1 the
+        # single-element weight of the same crossing (same path: alpha
+        # changes no direction)
+        o1 = oracle.radio_map(cfg.scene, tx1, cfg.plane, cfg.params, ray_ids=rids, replay_hits=rhits,
+                              want_records=True)
+        k1 = o1.records["ray"].astype(np.int64) * 128 + o1.records["depth"]
+        k = recs["ray"].astype(np.int64) * 128 + recs["depth"]
+        i = np.searchsorted(k1, k)
+        assert np.array_equal(k1[i], k)
+        return 4e-5 * S2 * o1.records["w"][i]
+
+    d = compare_sampled(cfg, g.hits[ids], g.cells[ids], g.weights[ids], ids, o, 1e-5, tol_fn=tol)
+    print("ula 256", d)
+    assert d["ok"], d
+    assert d["n_checked"] > 50_000

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import scenegen as sg
-from gpu_helpers import assert_parity, compare_hits, compare_maps, gpu_radio_map, gpu_scene
+from gpu_helpers import assert_parity, compare_hits, compare_maps, compare_sampled, gpu_radio_map, gpu_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,7 @@ def test_tiny_ragged_range_and_brute_force():
         assert np.array_equal(a.cells, b.cells), accel
         assert np.array_equal(a.weights, b.weights), accel
     o = _oracle(cfg, 12_345, 12_345 + 4_999)
-    rep, _ = compare_hits(a.hits, o.hits, o.flags, cfg.params.n_rays)
+    rep, _, _ = compare_hits(a.hits, o.hits, o.flags)
     assert rep["ok"], rep
 
 
@@ -161,7 +161,7 @@ def test_degenerate_inputs():
     cfg1 = sg.Config(one, sg.Tx((0.3, 0.2, 10.0)), pl, sg.Params(3.5e9, 20_001, 3))
     g1 = gpu_radio_map(cfg1)
     o1 = _oracle(cfg1)
-    rep, _ = compare_hits(g1.hits, o1.hits, o1.flags, cfg1.params.n_rays)
+    rep, _, _ = compare_hits(g1.hits, o1.hits, o1.flags)
     assert rep["ok"], rep
     cfg2 = sg.Config(sg.tiny_scene(), sg.Tx((0.0, 0.0, 10.0)), pl, sg.Params(3.5e9, 1, 0))
     g2 = gpu_radio_map(cfg2)
@@ -169,43 +169,42 @@ def test_degenerate_inputs():
     assert g2.hits.shape == (1, 1) and int(g2.hits[0, 0]) == int(o2.hits[0, 0])
 
 
-def test_manhattan_full_size_sampled():
-    """Full Manhattan workload (1e7 rays, L = 5, 1 m cells) in the launch
-    configuration the benchmark times: the map equals the sum of the per-segment
-    weights, and a strided sample of rays matches the oracle ray by ray."""
-    import torch
+# launch configuration the benchmark's autotuner picks for the Manhattan
+# workload (tree width, order, workgroup, deposit, refill); results do not
+# depend on it beyond FP32 summation order
+BENCH_LAUNCH = (4, 1, 512, 2, 64)
+
+
+def test_manhattan_full_lattice_parity():
+    """The whole Manhattan workload (1e7 rays, L = 5, 1 m cells) in the
+    benchmark's launch configuration against the oracle over the whole
+    lattice (run on a process pool of host cores): hit sequences of every ray
+    (<= 0.01 % mismatched, all oracle-flagged), every crossing's cell and
+    weight, and every cell with >= 100 crossings against the replay-corrected
+    oracle map.  The map of a call without records equals the recorded one."""
+    import paper_2504_21719_amd as rt
     cfg = sg.manhattan_config()
     s = gpu_scene(cfg.scene)
+    rt.rt_set_launch_config(s, *BENCH_LAUNCH)
     bench = gpu_radio_map(cfg, scene_handle=s, records=False)
     g = gpu_radio_map(cfg, scene_handle=s, records=True)
-    N = cfg.params.n_rays
-    # map = sum of recorded weights (atomic order aside)
-    c = g.cells.ravel()
-    w = g.weights.ravel().astype(np.float64)
-    m = c >= 0
-    acc = np.bincount(c[m], weights=w[m], minlength=cfg.plane.W * cfg.plane.H).reshape(cfg.plane.H, cfg.plane.W)
-    big = acc > 1e-12 * acc.max()
-    np.testing.assert_allclose(g.map[0][big], acc[big], rtol=1e-4)
-    np.testing.assert_allclose(bench.map[0][big], acc[big], rtol=1e-4)
     assert int(g.stats[0]) == int((g.hits != -2).sum())
     assert int(g.stats[4]) == 0          # no stack overflow, no reference outside the tree
-    ids = np.arange(7, N, N // 1500, dtype=np.int64)
-    o = oracle.radio_map(cfg.scene, cfg.tx, cfg.plane, cfg.params, ray_ids=ids, want_records=True)
-    rep, bad = compare_hits(g.hits[ids], o.hits, o.flags, ids.size, max_frac=1.0)
-    assert not rep["unexplained"], rep
-    assert rep["mismatched"] <= 2, rep
-    ok = np.ones(ids.size, bool)
-    ok[bad] = False
-    rec = o.records
-    pos = {int(n): i for i, n in enumerate(ids)}
-    for r_, l_, cell_, w_, b_, len_ in zip(rec["ray"], rec["depth"], rec["cell"], rec["w"], rec["border"], rec["length"]):
-        i = pos[int(r_)]
-        if not ok[i]:
-            continue
-        gc = int(g.cells[r_, l_])
-        if b_ > 1e-6 * (len_ + 1500.0):
-            assert gc == cell_, (r_, l_, gc, cell_)
-            assert abs(float(g.weights[r_, l_]) - w_) <= 1e-5 * w_
+    big = g.map[0] > 1e-12 * g.map[0].max()
+    np.testing.assert_allclose(bench.map[0][big], g.map[0][big], rtol=1e-4)
+    print("gpu done", flush=True)
+    o = oracle.radio_map_parallel(cfg.scene, cfg.tx, cfg.plane, cfg.params, want_records=True,
+                                  workers=min(16, os.cpu_count() or 1), chunks_per_worker=2)
+    print("oracle done", o.segments, flush=True)
+    d = compare_maps(cfg, g, o, 0)
+    print("manhattan full lattice", d)
+    assert d["n_cells"] >= 10_000
+    assert_parity(d)
+    assert d["max_w_rel_replayed"] <= 1e-5, d
+
+
+def _strided(N, n, offset=7):
+    return np.arange(offset, N, N // n, dtype=np.int64)[:n]
 
 
 @pytest.mark.parametrize("case", ["refraction", "diffuse", "roulette"])
@@ -215,9 +214,10 @@ def test_extension_workloads_full_size_sampled(case):
     scene without building bottoms (seed 1); Lambertian diffuse reflection
     with S = 0.4 / 0.2 and K_x = 0.1 / 0.3 (seed 1); Russian roulette from
     depth 2 (p_max 0.5) with gain thresholding.  The map equals the sum of
-    the per-segment weights, and a strided sample of 1,500 rays matches the
-    oracle ray by ray (hits outside flagged rays, cells off borders, weights
-    within 5e-5 for slabs and diffuse points, 1e-5 otherwise)."""
+    the per-segment weights, and 100,000 strided rays match the oracle ray by
+    ray: at most 0.01 % mismatched (all oracle-flagged, and replayed along the
+    GPU's hits), cells off borders, weights within 5e-5 for slabs and diffuse
+    points, 1e-5 otherwise."""
     cfg = sg.manhattan_config()
     cfg.params.seed = 1
     w_rel = 5e-5
@@ -230,7 +230,6 @@ def test_extension_workloads_full_size_sampled(case):
         cfg.params.rr_p_max, cfg.params.rr_depth, cfg.params.gain_threshold = 0.5, 2, 1e-13
         w_rel = 1e-5
     g = gpu_radio_map(cfg, records=True)
-    N = cfg.params.n_rays
     c = g.cells.ravel()
     w = g.weights.ravel().astype(np.float64)
     m = c >= 0
@@ -238,25 +237,12 @@ def test_extension_workloads_full_size_sampled(case):
     big = acc > 1e-12 * acc.max()
     np.testing.assert_allclose(g.map[0][big], acc[big], rtol=1e-4)
     assert int(g.stats[4]) == 0
-    ids = np.arange(7, N, N // 1500, dtype=np.int64)
+    ids = _strided(cfg.params.n_rays, 100_000)
     o = oracle.radio_map(cfg.scene, cfg.tx, cfg.plane, cfg.params, ray_ids=ids, want_records=True)
-    rep, bad = compare_hits(g.hits[ids], o.hits, o.flags, ids.size, max_frac=1.0)
-    print(case, rep)
-    assert not rep["unexplained"], rep
-    assert rep["mismatched"] <= 3, rep
-    ok = np.ones(ids.size, bool)
-    ok[bad] = False
-    rec = o.records
-    pos = {int(n): i for i, n in enumerate(ids)}
-    n_checked = 0
-    for r_, l_, cell_, w_, b_, len_ in zip(rec["ray"], rec["depth"], rec["cell"], rec["w"], rec["border"], rec["length"]):
-        if not ok[pos[int(r_)]]:
-            continue
-        if b_ > 1e-6 * (len_ + 1500.0):
-            assert int(g.cells[r_, l_]) == cell_, (r_, l_, int(g.cells[r_, l_]), cell_)
-            assert abs(float(g.weights[r_, l_]) - w_) <= w_rel * w_, (r_, l_, float(g.weights[r_, l_]), w_)
-            n_checked += 1
-    assert n_checked > 1000
+    d = compare_sampled(cfg, g.hits[ids], g.cells[ids], g.weights[ids], ids, o, w_rel)
+    print(case, d)
+    assert d["ok"], d
+    assert d["n_checked"] > 50_000
 
 
 _LARGE = None
@@ -270,18 +256,20 @@ def _large_chunk(be):
 
 
 def test_large_mesh_strided_rays():
-    """~1.0 M-triangle terrain + buildings, full N_S = 1e8 lattice, L = 8:
-    40 chunks of 256 rays spread over the lattice (10,240 rays; the oracle is
-    brute force over every triangle, run on a process pool) match ray by ray:
-    hit sequences bit-exact except oracle-flagged rays (at most 2), crossing
-    cells equal away from cell borders, weights within 1e-5."""
+    """~1.0 M-triangle terrain + buildings, full N_S = 1e8 lattice, L = 8, in
+    the launch configuration the benchmark times: 80 chunks of 256 rays
+    spread over the lattice (20,480 rays; the oracle is brute force over
+    every triangle, run on a process pool) match ray by ray: at most 0.01 %
+    of the rays compared mismatched (all oracle-flagged, replayed along the
+    GPU's hits), crossing cells equal away from cell borders, weights within
+    1e-5."""
     import multiprocessing as mp
     global _LARGE
     cfg = sg.large_config()
     s = gpu_scene(cfg.scene)
     info = s.info()
     assert info.n_triangles == cfg.scene.n_triangles
-    starts = np.linspace(0, cfg.params.n_rays - 512, 40).astype(np.int64) // 64 * 64 + 5
+    starts = np.linspace(0, cfg.params.n_rays - 512, 80).astype(np.int64) // 64 * 64 + 5
     chunks = [(int(b), int(b) + 256) for b in starts]
     gh, gc, gw = [], [], []
     for b, e in chunks:
@@ -291,28 +279,22 @@ def test_large_mesh_strided_rays():
         gc.append(g.cells)
         gw.append(g.weights)
     hits, cells, weights = np.concatenate(gh), np.concatenate(gc), np.concatenate(gw)
+    ids = np.concatenate([np.arange(b, e, dtype=np.int64) for b, e in chunks])
+    print("gpu done", flush=True)
     _LARGE = cfg
     oracle.lib()
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
         parts = pool.map(_large_chunk, chunks)
-    o_hits = np.concatenate([p.hits for p in parts])
-    o_flags = np.concatenate([p.flags for p in parts])
-    rep, bad = compare_hits(hits, o_hits, o_flags, hits.shape[0], max_frac=1.0)
-    assert not rep["unexplained"], rep
-    assert rep["mismatched"] <= 2, rep
-    ok = np.ones(hits.shape[0], bool)
-    ok[bad] = False
-    base = 0
-    n_checked = 0
-    for (b, e), p in zip(chunks, parts):
-        rec = p.records
-        for r_, l_, cell_, w_, bd_, len_ in zip(rec["ray"], rec["depth"], rec["cell"], rec["w"], rec["border"],
-                                               rec["length"]):
-            i = base + int(r_) - b
-            if not ok[i] or bd_ <= 1e-6 * (len_ + 3000.0):
-                continue
-            assert int(cells[i, l_]) == int(cell_), (r_, l_)
-            assert abs(float(weights[i, l_]) - w_) <= 1e-5 * w_, (r_, l_, weights[i, l_], w_)
-            n_checked += 1
-        base += e - b
-    assert n_checked > 1000
+    print("oracle done", flush=True)
+
+    class _O:
+        pass
+    o = _O()
+    o.hits = np.concatenate([p.hits for p in parts])
+    o.flags = np.concatenate([p.flags for p in parts])
+    o.records = {k: np.concatenate([p.records[k] for p in parts]) for k in parts[0].records}
+    d = compare_sampled(cfg, hits, cells, weights, ids, o, 1e-5)
+    print("large", d)
+    assert d["ok"], d
+    assert d["hits"]["rays"] == 20_480
+    assert d["n_checked"] > 2_000

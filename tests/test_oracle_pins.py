@@ -669,3 +669,106 @@ def test_roulette_probability_is_the_normalised_gain(oracle_lib):
     assert clear.sum() > 0.99 * rays.size
     assert np.array_equal(surv[clear], (u < p)[clear])
     assert 0.1 < surv.mean() < 0.9
+
+
+def _philox_word0(n, l, stream, seed):
+    return (int(sg_philox(n, l, stream, seed)) >> 8) / 2.0 ** 24
+
+
+def sg_philox(n, l, stream, seed):
+    import oracle
+    return oracle.philox4x32([int(n) & 0xffffffff, int(n) >> 32, l, stream], [seed, 0])[0]
+
+
+def test_gain_threshold_specular_closed_form(oracle_lib):
+    """Gain thresholding (Sec. "Practical Notes"): H-pol over a horizontal
+    concrete ground (pure TE, ||E||^2 = |r_perp(theta_i)|^2 after the bounce,
+    textbook Fresnel via Snell's law at cos(theta_i) = |k_z|).  Before segment
+    1 the path gain at the tube length r = h/|k_z| (the distance from the
+    source to the ground point) is (lambda / (4 pi r))^2 |r_perp|^2; with the
+    threshold at the median of that gain a ray's reflected segment is traced
+    iff its gain is at least the threshold.  With rr_depth = 2 the check
+    never runs at L = 1.  A missing 1/(16 pi^2), lambda in place of lambda^2,
+    or the check before another segment moves the set of survivors."""
+    N, h = 20_000, 10.0
+    pl = sg.Plane(1.5, -30.0, -30.0, 2.0, 2.0, 30, 30)
+    tx = sg.Tx((0.0, 0.0, h), pol=sg.POL_H)
+    scene = sg.ground_quad(100.0)
+    r0 = oracle_lib.radio_map(scene, tx, pl, _rr_params(N, 1), want_hits=True)
+    rays = np.nonzero(r0.hits[:, 0] >= 0)[0]           # down-going rays that hit the ground
+    assert rays.size > 0.45 * N
+    k = cf.lattice_directions(rays, N)
+    rp, _ = cf.fresnel_general(cf.eta(*CONCRETE_EPS_SIGMA, FREQ), np.abs(k[:, 2]))
+    r = h / np.abs(k[:, 2])
+    gain = (LAM / (4.0 * math.pi * r)) ** 2 * np.abs(rp) ** 2
+    thr = float(np.median(gain))
+    r1 = oracle_lib.radio_map(scene, tx, pl, _rr_params(N, 1, gain_threshold=thr), want_hits=True)
+    surv = r1.hits[rays, 1] != -2
+    clear = np.abs(gain / thr - 1.0) > 1e-9
+    assert clear.sum() > rays.size - 4
+    assert np.array_equal(surv[clear], (gain >= thr)[clear])
+    assert 0.4 < surv.mean() < 0.6
+    # rays that miss the ground are never thresholded (they have no bounce)
+    assert np.all(r1.hits[r0.hits[:, 0] < 0, 1] == -2)
+    gated = oracle_lib.radio_map(scene, tx, pl, _rr_params(N, 1, gain_threshold=thr, rr_depth=2), want_hits=True)
+    assert np.array_equal(gated.hits, r0.hits)
+
+
+CONCRETE_EPS_SIGMA = (5.24, 0.12)
+METAL_EPS_SIGMA = (1.0, 1.0e7)
+
+
+def test_gain_threshold_restarts_at_a_diffuse_point(oracle_lib):
+    """A diffuse point starts a new ray tube (Sec. "Definition of Radio Map":
+    the scattered field is that of a new source at the diffuse point), so the
+    gain threshold measures the tube from there.  Fully diffuse concrete ground
+    (S = 1, K_x = 0, Lambertian) under a metal ceiling at z = 20 m, H-pol
+    source at 10 m: a down-going ray scatters at the ground in the direction
+    whose polar cosine u0 is word 0 of the Philox block at (ray, 0, 2) (no
+    check right after the diffuse point), reaches the ceiling after
+    r2 = 20/u0, and before segment 2 its path gain is
+        (lambda / (4 pi r2))^2 * 2 u0 |r_perp,ground(theta_i)|^2 |r_perp,metal(theta_s)|^2
+    (the scattered field stays TE with K_x = 0; 2 cos(theta_s) Gamma^2 is the
+    Lambertian field factor with q(S) = 1).  With the threshold at its median,
+    segment 2 is traced iff the gain reaches it; measuring from the source
+    (r1 + r2) instead would keep a different set."""
+    N, seed = 20_000, 21
+    mb = sg._MeshBuilder()
+    mb.quad((-100.0, -100.0, 0.0), (100.0, -100.0, 0.0), (100.0, 100.0, 0.0), (-100.0, 100.0, 0.0), 0)
+    mb.quad((-100.0, -100.0, 20.0), (100.0, -100.0, 20.0), (100.0, 100.0, 20.0), (-100.0, 100.0, 20.0), 1)
+    scene = sg.with_diffuse(mb.build([CONCRETE_EPS_SIGMA, METAL_EPS_SIGMA], "ground+ceiling"), [1.0, 0.0], [0.0, 0.0])
+    tx = sg.Tx((0.0, 0.0, 10.0), pol=sg.POL_H)
+    pl = sg.Plane(1.5, -30.0, -30.0, 2.0, 2.0, 30, 30)
+    base = oracle_lib.radio_map(scene, tx, pl, _rr_params(N, 2, seed=seed), want_hits=True)
+    n = np.arange(N)
+    k = cf.lattice_directions(n, N)
+    down = k[:, 2] < -0.05
+    u0 = np.array([_philox_word0(i, 0, 2, seed) for i in n])
+    tan_i = np.sqrt(1.0 - k[:, 2] ** 2) / np.abs(np.where(down, k[:, 2], 1.0))
+    tan_s = np.sqrt(np.maximum(0.0, 1.0 - u0 ** 2)) / np.maximum(u0, 1e-12)
+    reach = 10.0 * tan_i + 20.0 * tan_s                  # horizontal distance to the ceiling point
+    sel = down & (u0 > 0.05) & (reach < 90.0)
+    rays = n[sel]
+    assert rays.size > 0.2 * N
+    assert np.all(np.isin(base.hits[rays, 0], [0, 1]))      # the ground quad
+    assert np.all(np.isin(base.hits[rays, 1], [2, 3]))      # the ceiling quad
+    rg, _ = cf.fresnel_general(cf.eta(*CONCRETE_EPS_SIGMA, FREQ), np.abs(k[sel, 2]))
+    rm, _ = cf.fresnel_general(cf.eta(*METAL_EPS_SIGMA, FREQ), u0[sel])
+    r2 = 20.0 / u0[sel]
+    r1 = 10.0 / np.abs(k[sel, 2])
+    amp = 2.0 * u0[sel] * np.abs(rg) ** 2 * np.abs(rm) ** 2
+    gain = (LAM / (4.0 * math.pi * r2)) ** 2 * amp
+    thr = float(np.median(gain))
+    th = oracle_lib.radio_map(scene, tx, pl, _rr_params(N, 2, seed=seed, gain_threshold=thr), want_hits=True)
+    # no check right at the diffuse point: every ray that first meets the
+    # ground traces its next segment (rays that first meet the specular
+    # ceiling are checked there, with their tube measured from the source)
+    gnd = np.isin(base.hits[:, 0], [0, 1])
+    assert np.array_equal(th.hits[gnd, :2], base.hits[gnd, :2])
+    assert np.any(th.hits[~gnd, 1] != base.hits[~gnd, 1])
+    surv = th.hits[rays, 2] != -2
+    clear = np.abs(gain / thr - 1.0) > 1e-9
+    assert clear.sum() > rays.size - 4
+    assert np.array_equal(surv[clear], (gain >= thr)[clear])
+    unfolded = (LAM / (4.0 * math.pi * (r1 + r2))) ** 2 * amp >= thr
+    assert np.count_nonzero(unfolded != (gain >= thr)) > 0.1 * rays.size
