@@ -1,9 +1,11 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X SBR radio-map path (one GPU).
 
-Workload: the seeded Manhattan city (10 x 10 blocks, 1,202 triangles, concrete
-and glass), isotropic V-pol transmitter at (0, 0, 30) m, f = 3.5 GHz,
-N_S = 1e7 rays, max depth L = 5, 1000 x 1000 cells of 1 m at z = 1.5 m.
+Headline workload ("large"): seeded fBm terrain (513 x 513 vertices over
+2 x 2 km) plus 2,000 buildings with facades and roofs split into <= 4 m quads,
+1,021,074 triangles of concrete, glass and metal; isotropic V-pol transmitter
+40 m above the terrain at the origin, f = 3.5 GHz, N_S = 1e8 rays, max depth
+L = 8, 1000 x 1000 cells of 2 m at z = 1.5 m.
 
 One timed step = one rt_radio_map call: zero the map, launch every ray, trace
 all its segments through the LBVH, reflect, deposit.  The metric is traced
@@ -15,13 +17,17 @@ order, workgroup size, deposit strategy, refill threshold) on a spread sample
 of the same lattice; its time is reported separately.
 
 Printed: one JSON line with the metric, a roofline object for the forward
-kernel, and the FP64 oracle timed on a bounded sample of the same lattice on
-one host core.  Roofline: the Manhattan BVH and triangles (about 0.3 MB) stay
-in the L2 caches, so HBM does not bound this workload; the forward kernel is
-reported against the VALU issue rate (256 CUs x 64 lanes x 2.4 GHz = 39.3 T
-FP32 lane-operations/s) with an algorithmic operation count per segment
-(see ALU_OPS below); the algorithmic HBM byte model is reported beside it
-("hbm_model") and is meaningful on the 1 M-triangle scene ("large" leg).
+kernel, and the FP64 oracle timed on a strided sample of the same lattice on
+the host cores.  Roofline: the forward kernel issues VALU instructions on
+about 87 % of its cycles and moves about 1.5 % of the HBM peak (the 341 MB
+tree is served from the L2 caches and the 256 MB MALL), so it is reported
+against the VALU issue rate (256 CUs x 64 lanes x 2.4 GHz = 39.3 T FP32
+lane-operations/s) with an algorithmic operation count per segment (see
+ALU_OPS below); the algorithmic HBM byte model and the measured DRAM bytes
+are reported beside it ("hbm_model").  Side legs: the Manhattan city (1e7
+rays, L = 5), differentiation and batching ratios, transmit arrays, slab
+walls with refraction, diffuse reflection, Russian roulette, and 64 rooftop
+transmitters on both scenes.
 """
 from __future__ import annotations
 
@@ -72,11 +78,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="wall time budget of the oracle sample")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (default: min(16, host cores))")
     ap.add_argument("--no-extras", action="store_true", help="skip the fwd+bwd and batched ratio legs")
-    ap.add_argument("--no-large", action="store_true", help="skip the 1 M-triangle leg")
+    ap.add_argument("--no-manhattan", action="store_true", help="skip the Manhattan legs")
     ap.add_argument("--no-tune", action="store_true", help="use the untuned launch defaults")
-    ap.add_argument("--launch", default="", help="width,order,block,deposit,refill: apply instead of tuning")
+    ap.add_argument("--launch", default="", help="width,order,block,deposit,refill: apply to the headline "
+                                                 "workload instead of tuning")
     ap.add_argument("--calib-copy", action="store_true", help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run N forward steps (for rocprofv3)")
     ap.add_argument("--profile-large", type=int, default=0,
@@ -86,6 +94,9 @@ def parse():
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs of a --profile-steps --calib-copy "
                          "run into the per-launch traffic record, then exit")
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
+                    help="average duration of the headline's forward dispatches in a rocprofv3 kernel trace of "
+                         "a run with --no-extras --no-manhattan --no-cpu-baseline and the same --steps, then exit")
     return ap.parse_args()
 
 
@@ -124,8 +135,34 @@ def ingest_counters(fetch_csv, write_csv, large=False):
     print(json.dumps(out))
 
 
+def trace_summary(path, steps):
+    """Durations of the forward dispatches of the headline's timed steps.
+
+    In a run with --no-extras --no-manhattan --no-cpu-baseline the last
+    2 * steps forward dispatches are the timed steps followed by the
+    kernel-only timing (accumulate = 1); earlier ones are the autotuner's
+    candidates, the counting pass and the warm-up."""
+    import csv
+    with open(path) as f:
+        rows = [r for r in csv.DictReader(f) if "k_forward<false, 0, true, false>" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    if len(rows) < 2 * steps:
+        raise SystemExit("%s: %d forward dispatches, fewer than 2 x %d" % (path, len(rows), steps))
+    out = {"kernel": "k_forward<false, MODE_SINGLE, wide, not extended>", "dispatches": len(rows)}
+    for name, sel in (("timed_steps", rows[-2 * steps:-steps]), ("kernel_only", rows[-steps:])):
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
+        out[name] = {"n": len(d), "avg_us": round(sum(d) / len(d), 1), "min_us": round(min(d), 1),
+                     "max_us": round(max(d), 1), "grid": int(sel[0]["Grid_Size"]),
+                     "workgroup": int(sel[0]["Workgroup_Size"])}
+    print(json.dumps(out))
+    return out
+
+
 def main():
     args = parse()
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.steps)
+        return
     if args.ingest_counters:
         ingest_counters(*args.ingest_counters, large=args.large_counters)
         return
@@ -165,26 +202,10 @@ def main():
         print(json.dumps({"profile_large": args.profile_large, "launch": "%d,%d,%d,%d,%d" % (
             inf.tuned_width, inf.tuned_order, inf.tuned_block, inf.tuned_deposit, inf.tuned_refill)}))
         return
-    cfg = sg.manhattan_config()
-    scene = rt.scene_from_mesh(cfg.scene)
-    eps = torch.tensor(cfg.scene.eps_r, dtype=torch.float32, device=dev)
-    sig = torch.tensor(cfg.scene.sigma, dtype=torch.float32, device=dev)
-    H, W = cfg.plane.H, cfg.plane.W
-    out = torch.empty((1, H, W), dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream()
-
-    # launch configuration from the autotuner (its own timing, outside the steps)
-    t0 = time.perf_counter()
-    if args.launch:
-        rt.rt_set_launch_config(scene, *[int(x) for x in args.launch.split(",")])
-    elif not args.no_tune:
-        rt.rt_tune(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, 2_000_000, out)
-    torch.cuda.synchronize()
-    tune_s = time.perf_counter() - t0
-    info = scene.info()
-    width = info.tuned_width or 4
-
     if args.profile_steps:
+        # Manhattan forward steps only (for rocprofv3)
+        cfg = sg.manhattan_config()
+        scene, eps, sig, out, _ = setup_plain(rt, cfg, dev, args.launch, args.no_tune, 2_000_000)
         for _ in range(args.profile_steps):
             rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out)
         if args.calib_copy:
@@ -197,15 +218,15 @@ def main():
                           "calib_copy_bytes": CALIB_COPY_BYTES if args.calib_copy else 0}))
         return
 
-    # device counters of one pass: segments, crossings, node visits, triangle tests
-    stats = torch.zeros(8, dtype=torch.int64, device=dev)
-    rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out, stats=stats)
-    torch.cuda.synchronize()
-    st = stats.cpu().numpy().astype(np.int64)
-    n_seg, n_cross, n_node, n_tri = int(st[0]), int(st[1]), int(st[2]), int(st[3])
-
+    # ---- headline: the 1.02 M-triangle scene
+    lc = sg.large_config()
+    scene, eps, sig, out, tune_s = setup_plain(rt, lc, dev, args.launch, args.no_tune, 4_000_000)
+    info = scene.info()
+    width = info.tuned_width or 4
+    n_seg, n_cross, n_node, n_tri = device_counts(rt, scene, eps, sig, lc, out)
+    stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out)
+        rt.rt_radio_map(scene, eps, sig, lc.tx, lc.plane, lc.params, out)
     torch.cuda.synchronize()
     # timed region: exactly `steps` steps, synchronised on both sides
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -213,15 +234,25 @@ def main():
     t0 = time.perf_counter()
     for s, e in ev:
         s.record(stream)
-        rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out)
+        rt.rt_radio_map(scene, eps, sig, lc.tx, lc.plane, lc.params, out)
         e.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = [s.elapsed_time(e) for s, e in ev]
     ms_per_step = wall * 1e3 / args.steps
     value = n_seg / (ms_per_step * 1e-3) / 1e6
-
-    kern_ms = kernel_ms(rt, scene, eps, sig, cfg, out, stream, args.steps)
+    kern_ms = kernel_ms(rt, scene, eps, sig, lc, out, stream, args.steps)
+    tr = traffic_from_profile(PROFILE_COUNTERS_LARGE)
+    roof = rooflines(n_seg, n_cross, n_node, n_tri, width, kern_ms, tr,
+                     note="tree + triangles about %d MB: larger than the L2 caches, partly held in the 256 MB MALL"
+                     % (info.device_bytes >> 20))
+    if tr:
+        # bytes that crossed to DRAM per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE), against the HBM peak
+        mb = tr["fetch_bytes"] + tr["write_bytes"]
+        roof["hbm_model"]["measured_traffic"] = {"bytes_per_launch": mb,
+                                                 "GB/s": round(mb / (kern_ms * 1e-3) / 1e9, 1),
+                                                 "frac": round(mb / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                                 "source": tr["source"]}
     result = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -235,51 +266,104 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "manhattan: seeded 10x10-block city, 1,202 triangles, iso V-pol Tx at (0,0,30) m, "
-                               "3.5 GHz, 1e7 Fibonacci rays, max depth 5, 1000x1000 cells of 1 m at z=1.5 m",
-                   "n_rays": cfg.params.n_rays, "max_depth": cfg.params.max_depth,
-                   "n_triangles": cfg.scene.n_triangles, "cells": [H, W], "parallelism": "single GPU"},
+        "config": {"workload": "large: seeded fBm terrain + 2,000 subdivided buildings, %s triangles (concrete, "
+                               "glass, metal), iso V-pol Tx 40 m above the terrain at the origin, 3.5 GHz, 1e8 "
+                               "Fibonacci rays, max depth 8, 1000x1000 cells of 2 m at z=1.5 m"
+                               % format(lc.scene.n_triangles, ","),
+                   "n_rays": lc.params.n_rays, "max_depth": lc.params.max_depth,
+                   "n_triangles": lc.scene.n_triangles, "cells": [lc.plane.H, lc.plane.W],
+                   "parallelism": "single GPU"},
         "segments_per_step": n_seg,
         "crossings_per_step": n_cross,
         "event_ms_per_step_median": round(float(np.median(step_ms)), 4),
         "build_ms": round(info.build_ms, 3),
         "bvh_depth": info.bvh_depth,
-        "tuned": {"width": width, "order": "coherent" if info.tuned_order != 2 else "lattice",
-                  "block": info.tuned_block, "deposit": "wave" if info.tuned_deposit == 2 else "atomic",
-                  "refill": info.tuned_refill, "tune_s": round(tune_s, 3),
-                  "launch": "%d,%d,%d,%d,%d" % (info.tuned_width, info.tuned_order, info.tuned_block,
-                                                info.tuned_deposit, info.tuned_refill)},
-        "roofline": rooflines(n_seg, n_cross, n_node, n_tri, width, kern_ms, traffic_from_profile()),
+        "tuned": tuned_record(info, tune_s),
+        "roofline": roof,
     }
     result["hbm_model"] = result["roofline"].pop("hbm_model")
+    if not args.no_extras:
+        try:
+            result["large_extras"] = large_extras(rt, sg, lc, scene, eps, sig, dev, out)
+        except rt.RtError as e:
+            result["large_extras_error"] = str(e)
+    del scene, out
+    torch.cuda.empty_cache()
 
-    if not args.no_extras:
+    # ---- side legs on the Manhattan city
+    if not args.no_manhattan:
+        cfg = sg.manhattan_config()
         try:
-            result.update(extra_legs(rt, sg, cfg, scene, eps, sig, dev))
+            mscene, meps, msig, mout, mtune = setup_plain(rt, cfg, dev, "", args.no_tune, 2_000_000)
+            result["manhattan"] = manhattan_leg(rt, cfg, mscene, meps, msig, mout, mtune, dev)
+            if not args.no_extras:
+                result.update(extra_legs(rt, sg, cfg, mscene, meps, msig, dev))
+                result["array"] = array_leg(rt, sg, cfg, mscene, meps, msig, mout)
+                result["refraction"] = refraction_leg(rt, sg, cfg, dev, mout)
+                result["diffuse"] = diffuse_leg(rt, sg, cfg, mscene, meps, msig, dev, mout)
         except rt.RtError as e:
-            result["extras_error"] = str(e)
-    if not args.no_extras:
-        try:
-            result["array"] = array_leg(rt, sg, cfg, scene, eps, sig, out)
-        except rt.RtError as e:
-            result["array_error"] = str(e)
-        try:
-            result["refraction"] = refraction_leg(rt, sg, cfg, dev, out, args.launch)
-        except rt.RtError as e:
-            result["refraction_error"] = str(e)
-        try:
-            result["diffuse"] = diffuse_leg(rt, sg, cfg, scene, eps, sig, dev, out)
-        except rt.RtError as e:
-            result["diffuse_error"] = str(e)
-    if not args.no_large:
-        try:
-            result["large"] = large_leg(rt, sg, dev, args)
-        except rt.RtError as e:
-            result["large_error"] = str(e)
+            result["manhattan_error"] = str(e)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(lc, args.cpu_seconds, args.cpu_workers)
 
     print(json.dumps(result), flush=True)
+
+
+def setup_plain(rt, cfg, dev, launch, no_tune, tune_rays):
+    """Scene, materials and map of one workload, with the launch configuration
+    applied (``launch`` = "width,order,block,deposit,refill") or tuned."""
+    import torch
+    scene = rt.scene_from_mesh(cfg.scene)
+    eps = torch.tensor(cfg.scene.eps_r, dtype=torch.float32, device=dev)
+    sig = torch.tensor(cfg.scene.sigma, dtype=torch.float32, device=dev)
+    out = torch.empty((1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if launch:
+        rt.rt_set_launch_config(scene, *[int(x) for x in launch.split(",")])
+    elif not no_tune:
+        rt.rt_tune(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, tune_rays, out)
+    torch.cuda.synchronize()
+    return scene, eps, sig, out, time.perf_counter() - t0
+
+
+def device_counts(rt, scene, eps, sig, cfg, out):
+    """Segments, crossings, node visits and triangle tests of one pass."""
+    import numpy as np
+    import torch
+    stats = torch.zeros(8, dtype=torch.int64, device=out.device)
+    rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out, stats=stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy().astype(np.int64)
+    if st[4] != 0:
+        raise SystemExit("traversal stack overflow or bad node reference reported by the forward kernel")
+    return int(st[0]), int(st[1]), int(st[2]), int(st[3])
+
+
+def tuned_record(info, tune_s):
+    return {"width": info.tuned_width or 4, "order": "coherent" if info.tuned_order != 2 else "lattice",
+            "block": info.tuned_block, "deposit": "wave" if info.tuned_deposit == 2 else "atomic",
+            "refill": info.tuned_refill, "tune_s": round(tune_s, 3),
+            "launch": "%d,%d,%d,%d,%d" % (info.tuned_width, info.tuned_order, info.tuned_block,
+                                          info.tuned_deposit, info.tuned_refill)}
+
+
+def manhattan_leg(rt, cfg, scene, eps, sig, out, tune_s, dev, reps=20):
+    """The Manhattan city (10 x 10 blocks, 1,202 triangles, 1e7 rays, L = 5,
+    1 m cells): the tree stays in the L2 caches."""
+    import torch
+    info = scene.info()
+    width = info.tuned_width or 4
+    n_seg, n_cross, n_node, n_tri = device_counts(rt, scene, eps, sig, cfg, out)
+    t = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out), reps, 3)
+    kern = kernel_ms(rt, scene, eps, sig, cfg, out, torch.cuda.current_stream(), reps)
+    r = rooflines(n_seg, n_cross, n_node, n_tri, width, kern, traffic_from_profile())
+    return {"workload": "manhattan: seeded 10x10-block city, 1,202 triangles, iso V-pol Tx at (0,0,30) m, 3.5 GHz, "
+                        "1e7 Fibonacci rays, max depth 5, 1000x1000 cells of 1 m at z=1.5 m",
+            "value": round(n_seg / (t * 1e-3) / 1e6, 3), "unit": "M ray-bounces/s", "ms_per_step": round(t, 4),
+            "segments_per_step": n_seg, "crossings_per_step": n_cross, "build_ms": round(info.build_ms, 3),
+            "bvh_depth": info.bvh_depth, "tuned": tuned_record(info, tune_s),
+            "roofline": r}
 
 
 def kernel_ms(rt, scene, eps, sig, cfg, out, stream, steps):
@@ -305,7 +389,7 @@ def rooflines(n_seg, n_cross, n_node, n_tri, width, kern_ms, traffic,
     t = kern_ms * 1e-3
     alu = ops / t / 1e12
     hbm = alg_bytes / t / 1e9
-    return {"bound": "alu", "achieved": round(alu, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+    return {"bound": "alu", "achieved": round(alu, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "T lane-ops/s",
             "frac": round(alu / ALU_PEAK_TOPS, 4),
             "traffic": (traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None,
             "traffic_detail": traffic,
@@ -333,51 +417,46 @@ def traffic_from_profile(path=PROFILE_COUNTERS):
     return None
 
 
-def large_leg(rt, sg, dev, args, reps=3):
-    """1.02 M-triangle terrain + buildings, 1e8 rays, L = 8, 2 m cells: the
-    workload on which the tree no longer fits the L2 caches."""
+def large_extras(rt, sg, cfg, scene, eps, sig, dev, out, reps=3):
+    """Side legs on the 1.02 M-triangle scene: Russian roulette from depth 2
+    (p_max 0.5) against the plain run, and 64 rooftop transmitters with ray
+    budgets log-uniform in [1e5, 1e7] (L = 5, 64 x 1000 x 1000 maps) in one
+    batched call against the per-transmitter loop of rt_radio_map calls on one
+    stream (same outputs, one synchronisation)."""
+    import dataclasses
     import numpy as np
     import torch
-    cfg = sg.large_config()
-    scene = rt.scene_from_mesh(cfg.scene)
-    eps = torch.tensor(cfg.scene.eps_r, dtype=torch.float32, device=dev)
-    sig = torch.tensor(cfg.scene.sigma, dtype=torch.float32, device=dev)
-    out = torch.empty((1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device=dev)
-    if not args.no_tune:
-        rt.rt_tune(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, 4_000_000, out)
-    info = scene.info()
-    width = info.tuned_width or 4
-    stats = torch.zeros(8, dtype=torch.int64, device=dev)
-    rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out, stats=stats)
-    torch.cuda.synchronize()
-    st = stats.cpu().numpy().astype(np.int64)
+    res = {}
+    n_seg = device_counts(rt, scene, eps, sig, cfg, out)[0]
     t = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, cfg.params, out), reps, 1)
-    tr = traffic_from_profile(PROFILE_COUNTERS_LARGE)
-    r = rooflines(int(st[0]), int(st[1]), int(st[2]), int(st[3]), width, t, tr,
-                  note="tree + triangles about %d MB: larger than L2, partly held in the 256 MB MALL"
-                  % (info.device_bytes >> 20))
-    if tr:
-        # measured bytes that crossed the fabric per launch, against the HBM peak
-        mb = tr["fetch_bytes"] + tr["write_bytes"]
-        r["hbm_model"]["measured_traffic"] = {"bytes_per_launch": mb, "GB/s": round(mb / (t * 1e-3) / 1e9, 1),
-                                              "frac": round(mb / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                              "source": tr["source"]}
-    # early termination from depth 2: Russian roulette with p_max = 0.5
-    import dataclasses
     prr = dataclasses.replace(cfg.params, rr_depth=2, rr_p_max=0.5, seed=1)
-    stats.zero_()
-    rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, prr, out, stats=stats)
-    torch.cuda.synchronize()
-    seg_rr = int(stats[0])
+    seg_rr = device_counts(rt, scene, eps, sig, dataclasses.replace(cfg, params=prr), out)[0]
     t_rr = _time(lambda: rt.rt_radio_map(scene, eps, sig, cfg.tx, cfg.plane, prr, out), reps, 1)
-    return {"workload": "large: 1,021,074 triangles, 1e8 rays, max depth 8, 1000x1000 cells of 2 m",
-            "value": round(int(st[0]) / (t * 1e-3) / 1e6, 3), "unit": "M ray-bounces/s", "ms_per_step": round(t, 3),
-            "segments_per_step": int(st[0]), "build_ms": round(info.build_ms, 3), "bvh_depth": info.bvh_depth,
-            "tuned_width": width, "roofline_hbm_model": r["hbm_model"],
-            "roofline_alu": {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac")},
-            "roulette": {"setting": "Russian roulette from depth 2, p_max 0.5",
-                         "ms_per_step": round(t_rr, 3), "segments_per_step": seg_rr,
-                         "speedup": round(t / t_rr, 3)}}
+    res["roulette"] = {"setting": "Russian roulette from depth 2, p_max 0.5", "plain_ms": round(t, 3),
+                       "plain_segments": n_seg, "ms_per_step": round(t_rr, 3), "segments_per_step": seg_rr,
+                       "speedup": round(t / t_rr, 3)}
+    txs, budgets = sg.rooftop_transmitters(64, seed=5, buildings=sg.large_buildings())
+    T = len(txs)
+    maps = torch.empty((T, 1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device=dev)
+    params = sg.Params(cfg.params.freq_hz, 1, 5)
+    plist = [sg.Params(cfg.params.freq_hz, int(b), 5) for b in budgets]
+
+    def plain_loop():
+        for k in range(T):
+            rt.rt_radio_map(scene, eps, sig, txs[k], cfg.plane, plist[k], maps[k])
+
+    def batched():
+        rt.rt_radio_map_batched(scene, eps[None], sig[None], txs, budgets, cfg.plane, params, maps)
+
+    t_plain = _time(plain_loop, reps, 1)
+    t_batch = _time(batched, reps, 1)
+    res["batched_tx_over_plain"] = {"workload": "64 rooftop Tx (roof centre + 3 m), budgets log-uniform in "
+                                                "[1e5, 1e7], %d rays, L = 5" % int(np.sum(budgets)),
+                                    "batched_ms": round(t_batch, 3), "plain_loop_ms": round(t_plain, 3),
+                                    "ratio": round(t_plain / t_batch, 3)}
+    del maps
+    torch.cuda.empty_cache()
+    return res
 
 
 def extra_legs(rt, sg, cfg, scene, eps, sig, dev, reps=5):
@@ -630,33 +709,51 @@ def _time(fn, reps=10, warm=2):
     return s.elapsed_time(e) / reps
 
 
-def cpu_baseline(cfg, seconds):
-    """FP64 oracle on one host core over a bounded sample of the same lattice.
-
-    The sample is a run of interleaved strided chunks (chunk c = rays c, c+1000,
-    c+2000, ...), added until about `seconds` of wall time have been spent.
-    """
+def _oracle_chunks(job):
+    """One oracle process: strided chunks of the lattice until the deadline."""
     import numpy as np
     import oracle
-    N = cfg.params.n_rays
-    stride = 1000
-    oracle.lib()
-    segs = 0
-    rays = 0
-    chunks = 0
-    cpu0 = time.process_time()
-    w0 = time.perf_counter()
-    while chunks < stride and time.perf_counter() - w0 < seconds:
-        ids = np.arange(chunks, N, stride, dtype=np.int64)
+    cfg, offsets, stride, per_chunk, deadline = job
+    segs = rays = 0
+    for c in offsets:
+        if time.time() >= deadline:
+            break
+        ids = c + stride * np.arange(per_chunk, dtype=np.int64)
         r = oracle.radio_map(cfg.scene, cfg.tx, cfg.plane, cfg.params, ray_ids=ids)
         segs += r.segments
         rays += ids.size
-        chunks += 1
+    return segs, rays
+
+
+def cpu_baseline(cfg, seconds, workers=0):
+    """FP64 oracle over a strided sample of the same lattice on the host cores.
+
+    The sample is a set of chunks, chunk c holding rays c, c + 1e6, c + 2e6,
+    ... (100 rays spread over the whole 1e8-ray lattice); `workers` oracle
+    processes take interleaved chunks until `seconds` of wall time have
+    passed.  The oracle itself is single-threaded brute force: every segment
+    tests all 1.02 M triangles.
+    """
+    import multiprocessing as mp
+    import oracle
+    N = cfg.params.n_rays
+    per_chunk = 100
+    stride = N // per_chunk
+    workers = int(workers or min(16, os.cpu_count() or 1))
+    oracle.lib()   # built before forking
+    w0 = time.perf_counter()
+    deadline = time.time() + seconds
+    jobs = [(cfg, list(range(w, stride, workers)), stride, per_chunk, deadline) for w in range(workers)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_oracle_chunks, jobs)
     wall = time.perf_counter() - w0
-    cpu = time.process_time() - cpu0
-    return {"value": round(segs / wall / 1e6, 6), "unit": "M ray-bounces/s", "cores": 1, "kind": "oracle",
-            "sample": "%d rays (%d interleaved chunks of every 1000th ray of the 1e7-ray lattice), %d segments, "
-                      "%.1f s wall, %.1f s CPU, single-threaded FP64 brute force" % (rays, chunks, segs, wall, cpu),
+    segs = sum(p[0] for p in parts)
+    rays = sum(p[1] for p in parts)
+    return {"value": round(segs / wall / 1e6, 6), "unit": "M ray-bounces/s", "cores": workers, "kind": "oracle",
+            "sample": "%d rays of the 1e8-ray lattice (chunks of 100 rays 1e6 apart, interleaved over %d "
+                      "single-threaded FP64 brute-force oracle processes), %d segments, %.1f s wall"
+                      % (rays, workers, segs, wall),
+            "per_core_segments_per_s": round(segs / wall / workers, 2),
             "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
 
 

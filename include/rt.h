@@ -116,6 +116,36 @@ rt_status rt_scene_destroy(rt_scene* scene);
 /* Host-side description of a built scene. */
 rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
 
+/*
+ * rt_scene_export -- copy the built acceleration structure to caller-owned
+ * host memory, for structural checks of the builder (the LBVH is this
+ * library's own design; the paper delegates intersection to its renderer).
+ * Every buffer may be NULL to skip it:
+ *   morton  uint64 [n_triangles]    63-bit Morton codes of the triangle AABB
+ *                                   centres, in sorted (slot) order
+ *   nodes   float  [n_nodes][16]    binary internal nodes, four float4 each:
+ *                                   (L.lo.x, L.hi.x, L.lo.y, L.hi.y),
+ *                                   (R.lo.x, R.hi.x, R.lo.y, R.hi.y),
+ *                                   (L.lo.z, L.hi.z, R.lo.z, R.hi.z),
+ *                                   (left ref, right ref, -, -) as int bits;
+ *                                   a ref r >= 0 is an internal node, r < 0
+ *                                   the leaf of triangle slot ~r; node 0 is
+ *                                   the root
+ *   wide    float  [n_wide][32]     4-wide nodes, eight float4 each: x_lo,
+ *                                   x_hi, y_lo, y_hi, z_lo, z_hi of children
+ *                                   0..3, then the four child refs as int bits
+ *                                   (>= 0 wide node, < 0 leaf slot ~r,
+ *                                   0x7fffffff empty), then unused; node 0 is
+ *                                   the root
+ *   tris    float  [n_triangles][12] triangles in slot order: (v0, original
+ *                                   id bits), (v1, material bits), (v2, 0)
+ *   n_wide  out (may be NULL): number of 4-wide nodes, 0 if the scene has no
+ *           4-wide tree (call first with NULL buffers to size `wide`).
+ * Synchronises `stream`.  Errors: RT_EINVAL for a NULL scene; RT_EDEVICE.
+ */
+rt_status rt_scene_export(const rt_scene* scene, uint64_t* morton, float* nodes, float* wide, float* tris,
+                          int64_t* n_wide, void* stream);
+
 /* ------------------------------------------------------- call parameters */
 /*
  * Radio materials, device float32 arrays.  eps_r and sigma are the real

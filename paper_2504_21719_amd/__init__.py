@@ -25,7 +25,7 @@ RT_POL_V, RT_POL_H, RT_POL_DUAL = 0, 1, 2
 
 EXPORTED = ["rt_last_error", "rt_build_scene", "rt_scene_destroy", "rt_scene_info_get", "rt_radio_map",
             "rt_tape_bytes", "rt_tape_create", "rt_tape_destroy", "rt_radio_map_backward",
-            "rt_radio_map_batched", "rt_tune", "rt_set_launch_config"]
+            "rt_radio_map_batched", "rt_tune", "rt_set_launch_config", "rt_scene_export"]
 
 
 class RtError(RuntimeError):
@@ -110,6 +110,8 @@ def lib():
                           i64, vp, vp, C.POINTER(i32), C.POINTER(i32)]
     L.rt_set_launch_config.restype = C.c_int
     L.rt_set_launch_config.argtypes = [vp, i32, i32, i32, i32, i32]
+    L.rt_scene_export.restype = C.c_int
+    L.rt_scene_export.argtypes = [vp, vp, vp, vp, vp, C.POINTER(i64), vp]
     _lib = L
     return L
 
@@ -228,6 +230,25 @@ class RtScene:
         _check(lib().rt_scene_info_get(self.handle, C.byref(out)))
         return out
 
+    def export(self, stream=None):
+        """Host copies of the acceleration structure (rt_scene_export):
+        morton uint64 [n_tri], nodes float32 [n_tri - 1][16] (binary tree),
+        wide float32 [n_wide][32] (4-wide tree, empty if none) and tris
+        float32 [n_tri][12] in slot order."""
+        import numpy as np
+        L = lib()
+        n_wide = C.c_int64(0)
+        _check(L.rt_scene_export(self.handle, None, None, None, None, C.byref(n_wide), _stream(stream)))
+        info = self.info()
+        n = int(info.n_triangles)
+        morton = np.zeros(n, np.uint64)
+        nodes = np.zeros((max(0, n - 1), 16), np.float32)
+        wide = np.zeros((int(n_wide.value), 32), np.float32)
+        tris = np.zeros((n, 12), np.float32)
+        _check(L.rt_scene_export(self.handle, morton.ctypes.data, nodes.ctypes.data, wide.ctypes.data,
+                                 tris.ctypes.data, C.byref(n_wide), _stream(stream)))
+        return {"morton": morton, "nodes": nodes, "wide": wide, "tris": tris}
+
     def close(self):
         if self.handle:
             lib().rt_scene_destroy(self.handle)
@@ -321,6 +342,25 @@ class RtTape:
     def __init__(self, handle, nbytes):
         self.handle = handle
         self.nbytes = nbytes
+
+    def export(self, stream=None):
+        """Host copies of the acceleration structure (rt_scene_export):
+        morton uint64 [n_tri], nodes float32 [n_tri - 1][16] (binary tree),
+        wide float32 [n_wide][32] (4-wide tree, empty if none) and tris
+        float32 [n_tri][12] in slot order."""
+        import numpy as np
+        L = lib()
+        n_wide = C.c_int64(0)
+        _check(L.rt_scene_export(self.handle, None, None, None, None, C.byref(n_wide), _stream(stream)))
+        info = self.info()
+        n = int(info.n_triangles)
+        morton = np.zeros(n, np.uint64)
+        nodes = np.zeros((max(0, n - 1), 16), np.float32)
+        wide = np.zeros((int(n_wide.value), 32), np.float32)
+        tris = np.zeros((n, 12), np.float32)
+        _check(L.rt_scene_export(self.handle, morton.ctypes.data, nodes.ctypes.data, wide.ctypes.data,
+                                 tris.ctypes.data, C.byref(n_wide), _stream(stream)))
+        return {"morton": morton, "nodes": nodes, "wide": wide, "tris": tris}
 
     def close(self):
         if self.handle:

@@ -91,6 +91,7 @@ extern "C" rt_status rt_scene_destroy(rt_scene* s) {
     (void)hipFree(s->tris);
     (void)hipFree(s->normals);
     (void)hipFree(s->wide);
+    (void)hipFree(s->morton);
     (void)hipFree(s->counters);
     (void)hipFree(s->spill);
     (void)hipFree(s->tx_desc);
@@ -126,6 +127,26 @@ extern "C" rt_status rt_scene_info_get(const rt_scene* s, rt_scene_info* out) {
         out->lo[a] = s->lo[a];
         out->hi[a] = s->hi[a];
     }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_scene_export(const rt_scene* s, uint64_t* morton, float* nodes, float* wide, float* tris,
+                                     int64_t* n_wide, void* stream) {
+    CHECK_ARG(s != nullptr, "rt_scene_export: NULL scene");
+    if (n_wide) *n_wide = s->wide ? s->n_wide : 0;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = s->n_tri, n_int = std::max<int64_t>(0, n - 1);
+    hipError_t e = hipSuccess;
+    if (morton && n > 0 && e == hipSuccess)
+        e = hipMemcpyAsync(morton, s->morton, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, st);
+    if (nodes && n_int > 0 && e == hipSuccess)
+        e = hipMemcpyAsync(nodes, s->nodes, sizeof(float4) * 4 * n_int, hipMemcpyDeviceToHost, st);
+    if (wide && s->wide && s->n_wide > 0 && e == hipSuccess)
+        e = hipMemcpyAsync(wide, s->wide, sizeof(float4) * 8 * s->n_wide, hipMemcpyDeviceToHost, st);
+    if (tris && n > 0 && e == hipSuccess)
+        e = hipMemcpyAsync(tris, s->tris, sizeof(float4) * 3 * n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return rt_hip_fail(e, "rt_scene_export");
     return RT_OK;
 }
 

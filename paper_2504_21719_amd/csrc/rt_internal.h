@@ -57,6 +57,7 @@ struct rt_scene {
     // the far one at the byte offset XOR 16.
     float4* wide = nullptr;
     int64_t n_wide = 0;
+    uint64_t* morton = nullptr;   // sorted Morton codes (kept for rt_scene_export)
     int tuned_width = 0;      // 2 binary, 4 wide (0 = default)
     size_t bytes = 0;
     double build_ms = 0.0;

@@ -142,7 +142,8 @@ __global__ void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shif
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of `count` unsigned values in place, one block of 1024.
+// Exclusive scan of `count` unsigned values in place, one block of 1024
+// (used for the per-tile sums of the multi-block scan below).
 __global__ void k_scan1(unsigned* __restrict__ data, int64_t count) {
     __shared__ unsigned part[1024];
     const int T = 1024;
@@ -163,6 +164,69 @@ __global__ void k_scan1(unsigned* __restrict__ data, int64_t count) {
         unsigned v = data[i];
         data[i] = run;
         run += v;
+    }
+}
+
+// Multi-block exclusive scan: tiles of kScanTile values, one 256-thread block
+// each.  Pass 1 writes every tile's sum, the sums are scanned by k_scan1, and
+// pass 2 scans each tile from its offset.  A tile is staged in LDS with one
+// pad word per 32 so that a thread's 16 consecutive values sit in distinct
+// banks.
+constexpr int kScanTile = 4096;
+constexpr int kScanPer = kScanTile / kBlock;
+
+__device__ __forceinline__ int scan_pad(int j) { return j + (j >> 5); }
+
+__global__ void __launch_bounds__(kBlock) k_scan_sums(const unsigned* __restrict__ data, int64_t count,
+                                                      unsigned* __restrict__ sums) {
+    __shared__ unsigned red[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    unsigned s = 0;
+    for (int i = 0; i < kScanPer; i++) {
+        const int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
+        if (idx < count) s += data[idx];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_tiles(unsigned* __restrict__ data, int64_t count,
+                                                       const unsigned* __restrict__ offs) {
+    __shared__ unsigned tile[kScanTile + kScanTile / 32];
+    __shared__ unsigned part[kBlock];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int i = 0; i < kScanPer; i++) {
+        const int j = i * kBlock + t;
+        tile[scan_pad(j)] = base + j < count ? data[base + j] : 0u;
+    }
+    __syncthreads();
+    unsigned s = 0;
+    for (int i = 0; i < kScanPer; i++) s += tile[scan_pad(t * kScanPer + i)];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        unsigned v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned run = offs[blockIdx.x] + part[t] - s;
+    for (int i = 0; i < kScanPer; i++) {
+        const int j = scan_pad(t * kScanPer + i);
+        const unsigned v = tile[j];
+        tile[j] = run;
+        run += v;
+    }
+    __syncthreads();
+    for (int i = 0; i < kScanPer; i++) {
+        const int j = i * kBlock + t;
+        if (base + j < count) data[base + j] = tile[scan_pad(j)];
     }
 }
 
@@ -472,6 +536,26 @@ __global__ void k_order_shifts(const TxDesc* __restrict__ txs, int64_t N1, int l
 
 }  // namespace
 
+// Tile sums needed by scan_exclusive for `count` values.
+int64_t scan_sums_len(int64_t count) { return (count + kScanTile - 1) / kScanTile; }
+
+// In-place exclusive scan of `count` values; `sums` holds scan_sums_len(count)
+// values of scratch.
+void scan_exclusive(unsigned* data, int64_t count, unsigned* sums, hipStream_t st) {
+    const int64_t tiles = scan_sums_len(count);
+    if (tiles <= 0) return;
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)tiles), dim3(kBlock), 0, st, data, count, sums);
+    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, sums, tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kBlock), 0, st, data, count, sums);
+}
+
+// Histogram buffer of the radix sort for n keys: 256 digit counts per tile of
+// kRsTile keys, then the scan's tile sums.
+int64_t rs_hist_len(int64_t n) {
+    const int64_t cells = 256 * ((n + kRsTile - 1) / kRsTile);
+    return cells + scan_sums_len(cells);
+}
+
 // LSD radix sort of (key, value) pairs on the low `bits` bits of the keys.
 // Results end in (k0, v0) when the number of 8-bit passes is even, else in
 // (k1, v1); the return value says which (0 or 1).
@@ -483,7 +567,7 @@ int rt_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_
     int which = 0;
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3(rs_blocks), dim3(kBlock), 0, st, ka, n, shift, hist, rs_blocks);
-        hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * rs_blocks);
+        scan_exclusive(hist, (int64_t)256 * rs_blocks, hist + (int64_t)256 * rs_blocks, st);
         hipLaunchKernelGGL(k_rs_scatter, dim3(rs_blocks), dim3(kBlock), 0, st, ka, va, kb, vb, n, shift, hist,
                            rs_blocks);
         std::swap(ka, kb);
@@ -531,7 +615,7 @@ rt_status rt_order_table(rt_scene* s, int log2m, hipStream_t st, const rt_scene:
     HIPCHK(hipMalloc(&v0, sizeof(uint32_t) * M));
     HIPCHK(hipMalloc(&v1, sizeof(uint32_t) * M));
     HIPCHK(hipMalloc(&az, sizeof(unsigned) * M));
-    HIPCHK(hipMalloc(&hist, sizeof(unsigned) * 256 * (size_t)rs_blocks));
+    HIPCHK(hipMalloc(&hist, sizeof(unsigned) * (size_t)rs_hist_len(M)));
     hipLaunchKernelGGL(k_order_keys, dim3(grid_for(M, kBlock)), dim3(kBlock), 0, st, M, M, k0, v0);
     int which = rt_radix_sort(k0, v0, k1, v1, M, 32, hist, st);
     if (which) {
@@ -594,10 +678,11 @@ rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t*
     unsigned *hist = nullptr, *bounds = nullptr;
     int4* child = nullptr;
     int *parent = nullptr, *depth = nullptr;
+    bool keep_keys = false;
     auto cleanup = [&]() {
         (void)hipFree(raw);
         (void)hipFree(cen);
-        (void)hipFree(k0);
+        if (!keep_keys) (void)hipFree(k0);
         (void)hipFree(k1);
         (void)hipFree(v0);
         (void)hipFree(v1);
@@ -615,7 +700,7 @@ rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t*
     HIPCHK(hipMalloc(&k1, sizeof(uint64_t) * n));
     HIPCHK(hipMalloc(&v0, sizeof(uint32_t) * n));
     HIPCHK(hipMalloc(&v1, sizeof(uint32_t) * n));
-    HIPCHK(hipMalloc(&hist, sizeof(unsigned) * 256 * (size_t)rs_blocks));
+    HIPCHK(hipMalloc(&hist, sizeof(unsigned) * (size_t)rs_hist_len(n)));
     HIPCHK(hipMalloc(&bounds, sizeof(unsigned) * 8));
     HIPCHK(hipMalloc(&child, sizeof(int4) * std::max<int64_t>(1, n_int)));
     HIPCHK(hipMalloc(&parent, sizeof(int) * std::max<int64_t>(1, n_int)));
@@ -658,7 +743,7 @@ rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t*
     uint32_t *va = v0, *vb = v1;
     for (int shift = 0; shift < 64; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3(rs_blocks), dim3(kBlock), 0, st, ka, n, shift, hist, rs_blocks);
-        hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * rs_blocks);
+        scan_exclusive(hist, (int64_t)256 * rs_blocks, hist + (int64_t)256 * rs_blocks, st);
         hipLaunchKernelGGL(k_rs_scatter, dim3(rs_blocks), dim3(kBlock), 0, st, ka, va, kb, vb, n, shift, hist,
                            rs_blocks);
         HIPCHK(hipGetLastError());
@@ -714,7 +799,8 @@ rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t*
                            n_int);
         unsigned last_flag = 0, last_index = 0;
         HIPCHK(hipMemcpyAsync(&last_flag, index4 + n_int - 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-        hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, index4, n_int);
+        // the radix histogram (at least n / 16 values) is free again: it holds the tile sums
+        scan_exclusive(index4, n_int, hist, st);
         HIPCHK(hipMemcpyAsync(&last_index, index4 + n_int - 1, sizeof(unsigned), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         int64_t n4 = (int64_t)last_index + last_flag;
@@ -737,6 +823,10 @@ rt_status rt_build_lbvh(rt_scene* s, const float* V, int64_t n_v, const int32_t*
     (void)hipEventDestroy(e1);
     s->build_ms = ms;
     s->depth = maxdepth;
+    // the sorted Morton codes stay with the scene (rt_scene_export)
+    s->morton = k0;
+    s->bytes += sizeof(uint64_t) * n;
+    keep_keys = true;
     for (int a = 0; a < 3; a++) {
         s->lo[a] = lo[a];
         s->hi[a] = hi[a];

@@ -325,7 +325,8 @@ def large_scene(seed=3, n_buildings=2000, terrain_n=513, half=1000.0,
                 footprint=(10.0, 25.0), height=(8.0, 30.0), tile=4.0):
     """fBm terrain (513x513 vertices over [-1000,1000]^2) plus subdivided buildings.
 
-    Returns (scene, terrain_height_fn).  Terrain heights are normalised to mean 0,
+    Returns (scene, terrain_height_fn, buildings) with buildings as
+    (x0, y0, x1, y1, roof height) tuples.  Terrain heights are normalised to mean 0,
     std 5 m.  Buildings: centres uniform in [-950,950]^2 with non-overlap
     rejection (5 m gap, 60 m clearing around the origin); facades and roofs are
     subdivided into <= ``tile`` m quads; no bottom faces.  Footprint U(10,25) m
@@ -359,7 +360,7 @@ def large_scene(seed=3, n_buildings=2000, terrain_n=513, half=1000.0,
     faces = np.concatenate([np.stack([a, b, c], 1), np.stack([a, c, d], 1)], 0)
     mb.add(verts, faces, 0)
 
-    placed = []   # (x0, y0, x1, y1)
+    placed = []   # (x0, y0, x1, y1, roof height)
     tries = 0
     while len(placed) < n_buildings:
         tries += 1
@@ -376,13 +377,12 @@ def large_scene(seed=3, n_buildings=2000, terrain_n=513, half=1000.0,
         if math.hypot(nx, ny) < 60.0:
             continue
         ok = True
-        for (p0, q0, p1, q1) in placed:
+        for (p0, q0, p1, q1, _) in placed:
             if box[0] < p1 + 5.0 and p0 < box[2] + 5.0 and box[1] < q1 + 5.0 and q0 < box[3] + 5.0:
                 ok = False
                 break
         if not ok:
             continue
-        placed.append(box)
         mat = 0 if mat_u < 0.45 else (1 if mat_u < 0.90 else 2)
         # base below the lowest terrain point under the footprint
         gx = np.linspace(box[0], box[2], 9)
@@ -390,6 +390,7 @@ def large_scene(seed=3, n_buildings=2000, terrain_n=513, half=1000.0,
         GX, GY = np.meshgrid(gx, gy, indexing="ij")
         base = float(terrain(GX, GY).min()) - 1.0
         top = base + h
+        placed.append(box + (top,))
         nxq = max(1, int(math.ceil(wx / tile)))
         nyq = max(1, int(math.ceil(wy / tile)))
         nzq = max(1, int(math.ceil((top - base) / tile)))
@@ -410,6 +411,11 @@ def large_config(n_rays=100_000_000, max_depth=8, seed=3):
     return Config(scene, Tx((0.0, 0.0, tz)),
                   Plane(1.5, -1000.0, -1000.0, 2.0, 2.0, 1000, 1000),
                   Params(3.5e9, n_rays, max_depth), "large")
+
+
+def large_buildings(seed=3):
+    """(x0, y0, x1, y1, roof height) of every building of the large scene."""
+    return large_scene(seed)[2]
 
 
 def diff_config(n_rays=1_000_000, max_depth=4) -> Config:
