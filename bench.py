@@ -158,6 +158,14 @@ def trace_summary(path, steps):
     return out
 
 
+_T0 = time.perf_counter()
+
+
+def _progress(msg):
+    """One line on stderr per finished leg (the JSON result goes to stdout)."""
+    print("[bench %6.1f s] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.trace_summary:
@@ -282,11 +290,13 @@ def main():
         "roofline": roof,
     }
     result["hbm_model"] = result["roofline"].pop("hbm_model")
+    _progress("headline done: %.1f M ray-bounces/s, %.3f ms/step" % (value, ms_per_step))
     if not args.no_extras:
         try:
             result["large_extras"] = large_extras(rt, sg, lc, scene, eps, sig, dev, out)
         except rt.RtError as e:
             result["large_extras_error"] = str(e)
+        _progress("large-scene extras done")
     del scene, out
     torch.cuda.empty_cache()
 
@@ -296,15 +306,21 @@ def main():
         try:
             mscene, meps, msig, mout, mtune = setup_plain(rt, cfg, dev, "", args.no_tune, 2_000_000)
             result["manhattan"] = manhattan_leg(rt, cfg, mscene, meps, msig, mout, mtune, dev)
+            _progress("manhattan leg done")
             if not args.no_extras:
                 result.update(extra_legs(rt, sg, cfg, mscene, meps, msig, dev))
+                _progress("ratio legs done")
                 result["array"] = array_leg(rt, sg, cfg, mscene, meps, msig, mout)
+                _progress("array leg done")
                 result["refraction"] = refraction_leg(rt, sg, cfg, dev, mout)
+                _progress("refraction leg done")
                 result["diffuse"] = diffuse_leg(rt, sg, cfg, mscene, meps, msig, dev, mout)
+                _progress("diffuse leg done")
         except rt.RtError as e:
             result["manhattan_error"] = str(e)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(lc, args.cpu_seconds, args.cpu_workers)
+        _progress("cpu baseline done")
 
     print(json.dumps(result), flush=True)
 
