@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=0, help="only run N forward steps (for rocprofv3)")
     ap.add_argument("--profile-large", type=int, default=0,
                     help="only run N forward steps of the 1 M-triangle workload (for rocprofv3)")
+    ap.add_argument("--profile-legs", type=int, default=0,
+                    help="only run N repetitions of the adjoint and batched legs (for rocprofv3)")
     ap.add_argument("--large-counters", action="store_true",
                     help="with --ingest-counters: the CSVs are of a --profile-large run")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -210,6 +212,9 @@ def main():
         print(json.dumps({"profile_large": args.profile_large, "launch": "%d,%d,%d,%d,%d" % (
             inf.tuned_width, inf.tuned_order, inf.tuned_block, inf.tuned_deposit, inf.tuned_refill)}))
         return
+    if args.profile_legs:
+        profile_legs(rt, sg, dev, args.profile_legs)
+        return
     if args.profile_steps:
         # Manhattan forward steps only (for rocprofv3)
         cfg = sg.manhattan_config()
@@ -323,6 +328,69 @@ def main():
         _progress("cpu baseline done")
 
     print(json.dumps(result), flush=True)
+
+
+def profile_legs(rt, sg, dev, reps):
+    """`reps` repetitions of each kernel the ratio legs run, for rocprofv3:
+    forward with a tape plus the adjoint (differentiation workload), 64
+    rooftop transmitters in one batched call on the Manhattan city and on the
+    1.02 M-triangle scene, and 16 material samples forward + backward in one
+    batched call (geometry pass + per-sample field pass)."""
+    import numpy as np
+    import torch
+    cfg = sg.manhattan_config()
+    scene, eps, sig, _, _ = setup_plain(rt, cfg, dev, "", False, 2_000_000)
+    dc = sg.diff_config()
+    H, W = dc.plane.H, dc.plane.W
+    m = torch.empty((1, H, W), dtype=torch.float32, device=dev)
+    tape = rt.rt_tape_create(dc.params)
+    g = torch.randn((1, H, W), dtype=torch.float32, device=dev)
+    ge, gs, go = (torch.empty(n, dtype=torch.float32, device=dev) for n in (2, 2, 3))
+    for _ in range(reps):
+        rt.rt_radio_map(scene, eps, sig, dc.tx, dc.plane, dc.params, m, tape=tape)
+        rt.rt_radio_map_backward(scene, eps, sig, dc.tx, dc.plane, dc.params, tape, g, ge, gs, go)
+    torch.cuda.synchronize()
+    del tape
+    _progress("adjoint leg done")
+    txs, budgets = sg.rooftop_transmitters(64, seed=5, buildings=sg.manhattan_buildings(cfg.scene))
+    maps = torch.empty((len(txs), 1, H, W), dtype=torch.float32, device=dev)
+    for _ in range(reps):
+        rt.rt_radio_map_batched(scene, eps[None], sig[None], txs, budgets, cfg.plane,
+                                sg.Params(cfg.params.freq_hz, 1, 5), maps)
+    torch.cuda.synchronize()
+    _progress("batched transmitters (Manhattan) done")
+    # the per-transmitter loop the batched call is compared with, once, in
+    # budget order (the trace then pairs each call with its budget)
+    for k in np.argsort(-np.asarray(budgets), kind="stable"):
+        rt.rt_radio_map(scene, eps, sig, txs[k], cfg.plane, sg.Params(cfg.params.freq_hz, int(budgets[k]), 5),
+                        maps[k])
+    torch.cuda.synchronize()
+    del maps
+    _progress("per-transmitter loop (Manhattan) done")
+    S = 16
+    E, Sg = sg.random_materials(cfg.scene, S, seed=5)
+    eS = torch.tensor(E, dtype=torch.float32, device=dev)
+    sS = torch.tensor(Sg, dtype=torch.float32, device=dev)
+    maps = torch.empty((1, S, H, W), dtype=torch.float32, device=dev)
+    gm = torch.randn((1, S, H, W), dtype=torch.float32, device=dev)
+    grads = torch.empty((1, S, 2 * cfg.scene.n_materials + 3), dtype=torch.float32, device=dev)
+    for _ in range(reps):
+        rt.rt_radio_map_batched(scene, eS, sS, [dc.tx], [1_000_000], dc.plane, sg.Params(cfg.params.freq_hz, 1, 5),
+                                maps, grad_maps=gm, grads=grads)
+    torch.cuda.synchronize()
+    del maps, gm, scene
+    torch.cuda.empty_cache()
+    _progress("batched material samples done")
+    lc = sg.large_config()
+    ls, le, lg, _, _ = setup_plain(rt, lc, dev, "", False, 4_000_000)
+    txs, budgets = sg.rooftop_transmitters(64, seed=5, buildings=sg.large_buildings())
+    maps = torch.empty((len(txs), 1, lc.plane.H, lc.plane.W), dtype=torch.float32, device=dev)
+    for _ in range(reps):
+        rt.rt_radio_map_batched(ls, le[None], lg[None], txs, budgets, lc.plane, sg.Params(lc.params.freq_hz, 1, 5),
+                                maps)
+    torch.cuda.synchronize()
+    _progress("batched transmitters (large scene) done")
+    print(json.dumps({"profile_legs": reps, "large_batched_rays": int(np.sum(budgets))}))
 
 
 def setup_plain(rt, cfg, dev, launch, no_tune, tune_rays):

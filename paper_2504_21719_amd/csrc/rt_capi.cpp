@@ -552,11 +552,14 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     std::vector<int> order(n_tx);
     for (int i = 0; i < n_tx; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rays_per_tx[x] > rays_per_tx[y]; });
-    size_t need = sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1) + sizeof(int32_t) * n_tx;
+    // device tables: descriptors, budget prefix, wavefront prefix, slots
+    static_assert(sizeof(TxDesc) % 8 == 0, "TxDesc must keep the int64 tables after it aligned");
+    size_t need = sizeof(TxDesc) * n_tx + 2 * sizeof(int64_t) * (n_tx + 1) + sizeof(int32_t) * n_tx;
     std::vector<char> hb(need, 0);
     TxDesc* hd = (TxDesc*)hb.data();
     int64_t* hp = (int64_t*)(hb.data() + sizeof(TxDesc) * n_tx);
-    int32_t* hslot = (int32_t*)(hb.data() + sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1));
+    int64_t* hw = hp + (n_tx + 1);
+    int32_t* hslot = (int32_t*)(hw + (n_tx + 1));
     int64_t total = 0;
     // one launch-order chunk size for the whole batch (from the largest lattice)
     const int olog2m = rt_order_log2m(rays_per_tx[order[0]]);
@@ -573,6 +576,11 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
         total += rays_per_tx[t];
     }
     hp[n_tx] = total;
+    // wavefronts of 64 consecutive global ray indices that hold rays of each
+    // ordered transmitter: the batched gradients keep one partial sum per
+    // (transmitter, wavefront) and add them in order
+    hw[0] = 0;
+    for (int i = 0; i < n_tx; i++) hw[i + 1] = hw[i] + (hp[i + 1] - 1) / 64 - hp[i] / 64 + 1;
     const rt_scene::OrderTable* otab = nullptr;
     {
         rt_status ro = prepare_order(s, rays_per_tx[order[0]], (size_t)chunks_total, olog2m, hs, &otab);
@@ -589,6 +597,7 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     bl.n_samples = n_samples;
     bl.n_tx = n_tx;
     bl.total_rays = total;
+    bl.total_waves = hw[n_tx];
     fill_plane(plane, params->freq_hz, &bl.pl);
     bl.L = params->max_depth;
     bl.t_min = params->t_min;
@@ -669,7 +678,8 @@ extern "C" rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials ma
     char* db = (char*)s->tx_desc;
     bl.tx_dev = (const TxDesc*)db;
     bl.prefix_dev = (const int64_t*)(db + sizeof(TxDesc) * n_tx);
-    bl.tx_slot_dev = (const int32_t*)(db + sizeof(TxDesc) * n_tx + sizeof(int64_t) * (n_tx + 1));
+    bl.woff_dev = bl.prefix_dev + (n_tx + 1);
+    bl.tx_slot_dev = (const int32_t*)(bl.woff_dev + (n_tx + 1));
     r = rt_batched_workspace(bl, hs);
     if (r != RT_OK) return r;
     if (!use_graph) return rt_launch_batched(bl, hs);

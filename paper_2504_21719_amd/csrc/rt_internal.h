@@ -240,6 +240,9 @@ struct BatchLaunch {
     const TxDesc* tx_dev;    // device [n_tx], ordered largest budget first
     const int64_t* prefix_dev;  // device [n_tx + 1] exclusive prefix of budgets
     const int32_t* tx_slot_dev; // device [n_tx]: output slot of ordered tx
+    const int64_t* woff_dev;    // device [n_tx + 1]: exclusive prefix of the 64-ray
+                                // wavefronts each ordered tx's rays touch
+    int64_t total_waves;        // woff[n_tx]
     int64_t total_rays;
     PlaneDesc pl;
     int32_t L;

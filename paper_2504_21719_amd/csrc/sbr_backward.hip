@@ -27,7 +27,8 @@
 // Reduction: every thread owns a fixed set of rays (grid-stride order) and
 // registers for up to kMatChunk materials; sums go thread -> wave (butterfly)
 // -> block (waves in order) -> per-block partials in FP64 -> one final kernel
-// that adds the blocks in order.  The result does not depend on scheduling.
+// that adds the blocks in a fixed order.  The result does not depend on
+// scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -317,15 +318,19 @@ __global__ void __launch_bounds__(kBwdBlock) k_backward(const BwdArgs a) {
     }
 }
 
-// Sum the per-block partials in block order and scatter them to the outputs.
-__global__ void k_backward_final(const double* __restrict__ partials, int nblocks, int n_mat, int mat0,
-                                 int write_orient, float* __restrict__ g_eps, float* __restrict__ g_sig,
-                                 float* __restrict__ g_orient) {
+// Sum the per-block partials of parameter j = blockIdx.x in a fixed order
+// (lane i adds blocks i, i + 64, ... in turn, then a butterfly over the
+// lanes) and scatter the sum to the outputs.  One wavefront per parameter:
+// a single thread walking all blocks would chain hundreds of dependent loads.
+__global__ void __launch_bounds__(64) k_backward_final(const double* __restrict__ partials, int nblocks, int n_mat,
+                                                       int mat0, int write_orient, float* __restrict__ g_eps,
+                                                       float* __restrict__ g_sig, float* __restrict__ g_orient) {
     const int P = 2 * kMatChunk + 3;
-    int j = threadIdx.x;
-    if (j >= P) return;
+    const int j = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; b++) s += partials[(int64_t)b * P + j];
+    for (int b = threadIdx.x; b < nblocks; b += 64) s += partials[(int64_t)b * P + j];
+    s = wave_sum_d(s);
+    if (threadIdx.x != 0) return;
     if (j < kMatChunk) {
         int m = mat0 + j;
         if (m < n_mat && g_eps) g_eps[m] = (float)s;
@@ -384,7 +389,7 @@ rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
             hipLaunchKernelGGL(k_backward<true>, dim3(kBwdBlocks), dim3(kBwdBlock), 0, st, a);
         else
             hipLaunchKernelGGL(k_backward<false>, dim3(kBwdBlocks), dim3(kBwdBlock), 0, st, a);
-        hipLaunchKernelGGL(k_backward_final, dim3(1), dim3(64), 0, st, (const double*)s->grad_ws, kBwdBlocks,
+        hipLaunchKernelGGL(k_backward_final, dim3(P), dim3(64), 0, st, (const double*)s->grad_ws, kBwdBlocks,
                            s->n_mat, m0, a.write_orient, b.grad_eps, b.grad_sigma, b.grad_orient);
     }
     hipError_t e = hipGetLastError();

@@ -49,7 +49,9 @@ struct SampArgs {
     PlaneDesc pl;
     float* maps;            // [n_tx][S][H][W]
     const float* grad_maps; // [n_tx][S][H][W] or null
-    double* gws;            // [n_tx][S][P] FP64 accumulators (gradient mode)
+    const int64_t* woff;    // [n_tx + 1] prefix of the wavefronts each transmitter's rays touch
+    double* gws;            // gradient mode: FP64 partial sums, transmitter t's block at
+                            // woff[t] S P, laid out [s][j][wavefront of t]
     int P;                  // 2 n_mat + 3
     const float* thickness; // slab thickness per material (m, shared by the samples), or null
     float k0;               // 2 pi / lambda
@@ -83,13 +85,14 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
     for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < T; g0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t g = g0 + threadIdx.x;
         const bool valid = g < T;
-        int slot_out = -1, ns = 0;
+        int slot_out = -1, ns = 0, tx_i = -1;
         TxDesc td;
         float w00[kMaxSeg], w01[kMaxSeg], w10[kMaxSeg], w11[kMaxSeg], cth1[kMaxSeg], gk[kMaxSeg];
         int matl[kMaxSeg], cell[kMaxSeg];
         d3f cth = {0, 0, 0, 0}, cph = {0, 0, 0, 0};
         if (valid) {
             const int t = find_tx_s(a.prefix, a.n_tx, g);
+            tx_i = t;
             td = a.txs[t];
             slot_out = a.slots[t];
             const int64_t n = g - a.prefix[t];
@@ -194,27 +197,32 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                 }
             }
             if (GRAD) {
-                // peel the lanes of each transmitter slot (usually one per wave),
-                // sum them with a butterfly, one FP64 atomic per parameter
+                // one partial sum per (transmitter, wavefront, sample,
+                // parameter), summed later in a fixed order: the lanes of each
+                // transmitter in this wavefront (usually one) are summed with a
+                // butterfly and their leader stores the sums in that
+                // transmitter's entry for this wavefront
+                const int64_t gw = (g0 + (threadIdx.x & ~63)) >> 6;
                 unsigned long long pend = __ballot(valid);
                 bool done = !valid;
                 while (pend) {
                     int leader = __ffsll((long long)pend) - 1;
-                    int ls = __shfl(slot_out, leader);
-                    bool mine = !done && slot_out == ls;
+                    int lt = __shfl(tx_i, leader);
+                    bool mine = !done && tx_i == lt;
                     unsigned long long grp = __ballot(mine);
-                    double* dst = a.gws + ((int64_t)ls * S + s) * a.P;
+                    const int64_t w0 = a.woff[lt], nw = a.woff[lt + 1] - w0;
+                    double* dst = a.gws + w0 * S * a.P + (int64_t)s * a.P * nw + (gw - (a.prefix[lt] >> 6));
                     for (int j = 0; j < a.n_mat && j < kMaxMat; j++) {
                         double v = wsum(mine ? (double)ge[j] : 0.0);
                         double u = wsum(mine ? (double)gs[j] : 0.0);
                         if (lane == leader) {
-                            unsafeAtomicAdd(dst + j, v);
-                            unsafeAtomicAdd(dst + a.n_mat + j, u);
+                            dst[j * nw] = v;
+                            dst[(a.n_mat + j) * nw] = u;
                         }
                     }
                     for (int j = 0; j < 3; j++) {
                         double v = wsum(mine ? (double)go[j] : 0.0);
-                        if (lane == leader) unsafeAtomicAdd(dst + 2 * a.n_mat + j, v);
+                        if (lane == leader) dst[(2 * a.n_mat + j) * nw] = v;
                     }
                     if (mine) done = true;
                     pend &= ~grp;
@@ -266,14 +274,30 @@ __global__ void __launch_bounds__(kSampBlock) k_samples_deep(const SampArgs a) {
     }
 }
 
-__global__ void k_zero_d(double* __restrict__ p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
-}
-
-__global__ void k_grads_out(const double* __restrict__ ws, float* __restrict__ out, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (float)ws[i];
+// Gradient of parameter j = blockIdx.x for sample s = blockIdx.y of ordered
+// transmitter t = blockIdx.z: the sum of its per-wavefront partials in a fixed
+// order (thread i adds entries i, i + 256, ... in turn; butterflies within
+// wavefronts; the four wavefront sums in order), written to the caller's
+// [slot][s][j] entry.
+constexpr int kFinalBlock = 256;
+__global__ void __launch_bounds__(kFinalBlock) k_grads_final(const double* __restrict__ gws,
+                                                             const int64_t* __restrict__ woff,
+                                                             const int32_t* __restrict__ slots, int S, int P,
+                                                             float* __restrict__ out) {
+    __shared__ double part[kFinalBlock / 64];
+    const int j = blockIdx.x, s = blockIdx.y, t = blockIdx.z;
+    const int64_t w0 = woff[t], nw = woff[t + 1] - w0;
+    const double* src = gws + w0 * S * P + ((int64_t)s * P + j) * nw;
+    double acc = 0.0;
+    for (int64_t k = threadIdx.x; k < nw; k += kFinalBlock) acc += src[k];
+    acc = wsum(acc);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kFinalBlock / 64; w++) tot += part[w];
+        out[((int64_t)slots[t] * S + s) * P + j] = (float)tot;
+    }
 }
 
 }  // namespace
@@ -295,7 +319,7 @@ rt_status rt_batched_workspace(const BatchLaunch& b, hipStream_t st) {
         if (e != hipSuccess) return rt_hip_fail(e, "rt_radio_map_batched: geometry tape");
         s->geom_ws_bytes = need;
     }
-    size_t gneed = sizeof(double) * (size_t)b.n_tx * b.n_samples * (2 * s->n_mat + 3);
+    size_t gneed = sizeof(double) * (size_t)b.total_waves * b.n_samples * (2 * s->n_mat + 3);
     if (grad && s->bgrad_ws_bytes < gneed) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(s->bgrad_ws);
@@ -322,15 +346,10 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
     }
     size_t need = sizeof(float4) * 2 * (size_t)(b.L + 1) * (size_t)b.total_rays + sizeof(int) * (size_t)b.total_rays;
     const int P = 2 * s->n_mat + 3;
-    if (s->geom_ws_bytes < need || (grad && s->bgrad_ws_bytes < sizeof(double) * (size_t)b.n_tx * S * P))
+    if (s->geom_ws_bytes < need || (grad && s->bgrad_ws_bytes < sizeof(double) * (size_t)b.total_waves * S * P))
         return rt_fail(RT_EINVAL, "rt_radio_map_batched: workspace not prepared");
     float4* geom = (float4*)s->geom_ws;
     int* nseg = (int*)((char*)s->geom_ws + sizeof(float4) * 2 * (size_t)(b.L + 1) * (size_t)b.total_rays);
-    if (grad) {
-        int64_t ng = (int64_t)b.n_tx * S * P;
-        hipLaunchKernelGGL(k_zero_d, dim3((unsigned)std::min<int64_t>(1024, (ng + 255) / 256)), dim3(256), 0, st,
-                           (double*)s->bgrad_ws, ng);
-    }
     rt_status r = rt_launch_forward_multi(s, b.eps_r, b.sigma, b.pl, b.L, b.t_min, b.block, b.deposit, b.refill,
                                           b.order, b.max_chunks, b.tx_dev, b.prefix_dev, b.tx_slot_dev, b.n_tx,
                                           b.total_rays, true, b.maps, HW, HW * b.n_tx * S, geom, nseg, nullptr, st);
@@ -351,6 +370,7 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
     a.pl = b.pl;
     a.maps = b.maps;
     a.grad_maps = b.grad_maps;
+    a.woff = b.woff_dev;
     a.gws = (double*)s->bgrad_ws;
     a.P = P;
     a.thickness = b.ext.thickness;
@@ -377,11 +397,9 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
             hipLaunchKernelGGL(k_samples_deep, dim3(by, S), dim3(kSampBlock), 0, st, a);
         }
     }
-    if (grad) {
-        int64_t ng = (int64_t)b.n_tx * S * P;
-        hipLaunchKernelGGL(k_grads_out, dim3((unsigned)std::min<int64_t>(1024, (ng + 255) / 256)), dim3(256), 0, st,
-                           (const double*)s->bgrad_ws, b.grads, ng);
-    }
+    if (grad && b.total_rays > 0)
+        hipLaunchKernelGGL(k_grads_final, dim3(P, S, b.n_tx), dim3(kFinalBlock), 0, st, (const double*)s->bgrad_ws,
+                           b.woff_dev, b.tx_slot_dev, S, P, b.grads);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return rt_hip_fail(e, "batched launch");
     return RT_OK;
