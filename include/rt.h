@@ -395,6 +395,29 @@ rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials materials,
                                 const float* grad_map, float* grad_eps_r,
                                 float* grad_sigma, float* grad_orient, void* stream);
 
+/*
+ * rt_radio_map_backward_noalloc -- rt_radio_map_backward for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as rt_radio_map_backward; the caller still provides the tape, the
+ * upstream gradient and the outputs.  The per-block partial sums (512 blocks
+ * x 19 FP64 values = 77,824 bytes, independent of the ray count and of the
+ * number of materials, which are processed in chunks of 8) go to a static
+ * device array, one per GPU, held until the process ends, instead of the
+ * scene's workspace.  The call allocates nothing; its first call on a device
+ * resolves that device's array (that device must be current).  Every call on
+ * one GPU shares that array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and give wrong gradients; calls ordered on one
+ * stream are safe.  Errors as rt_radio_map_backward, plus RT_EOVERFLOW if
+ * the partial sums would not fit the array (they always do) and RT_EDEVICE
+ * if the device index is 64 or above.
+ */
+rt_status rt_radio_map_backward_noalloc(const rt_scene* scene, rt_materials materials,
+                                        const rt_tx* tx, const rt_plane* plane,
+                                        const rt_sbr_params* params, const rt_tape* tape,
+                                        const float* grad_map, float* grad_eps_r,
+                                        float* grad_sigma, float* grad_orient, void* stream);
+
 /* --------------------------------------------------------------- batched */
 /*
  * rt_radio_map_batched -- many transmitters and/or many material samples in

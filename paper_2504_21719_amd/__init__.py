@@ -25,6 +25,7 @@ RT_POL_V, RT_POL_H, RT_POL_DUAL = 0, 1, 2
 
 EXPORTED = ["rt_last_error", "rt_build_scene", "rt_scene_destroy", "rt_scene_info_get", "rt_radio_map",
             "rt_tape_bytes", "rt_tape_create", "rt_tape_destroy", "rt_radio_map_backward",
+            "rt_radio_map_backward_noalloc",
             "rt_radio_map_batched", "rt_tune", "rt_set_launch_config", "rt_scene_export"]
 
 
@@ -102,6 +103,8 @@ def lib():
     L.rt_radio_map_backward.restype = C.c_int
     L.rt_radio_map_backward.argtypes = [vp, rt_materials, C.POINTER(rt_tx), C.POINTER(rt_plane),
                                         C.POINTER(rt_sbr_params), vp, vp, vp, vp, vp, vp]
+    L.rt_radio_map_backward_noalloc.restype = C.c_int
+    L.rt_radio_map_backward_noalloc.argtypes = L.rt_radio_map_backward.argtypes
     L.rt_radio_map_batched.restype = C.c_int
     L.rt_radio_map_batched.argtypes = [vp, rt_materials, i32, C.POINTER(rt_tx), vp, i32,
                                        C.POINTER(rt_plane), C.POINTER(rt_sbr_params), vp, vp, vp, vp]
@@ -383,9 +386,11 @@ def rt_tape_create(params, **pkw) -> RtTape:
 
 def rt_radio_map_backward(scene: RtScene, eps_r, sigma, tx, plane, params, tape: RtTape, grad_map,
                           grad_eps_r=None, grad_sigma=None, grad_orient=None, stream=None, thickness=None,
-                          scattering=None, xpd=None, scatter_pattern=None, **pkw):
+                          scattering=None, xpd=None, scatter_pattern=None, noalloc=False, **pkw):
     """Adjoint of a forward call recorded on ``tape`` (same materials,
-    thickness, scattering, transmitter, plane and parameters)."""
+    thickness, scattering, transmitter, plane and parameters).  With
+    ``noalloc`` it calls rt_radio_map_backward_noalloc (partial sums in the
+    GPU's static workspace; nothing is allocated)."""
     p = params if isinstance(params, rt_sbr_params) else make_params(params, **pkw)
     pl = plane if isinstance(plane, rt_plane) else make_plane(plane)
     nm = scene.n_materials
@@ -394,8 +399,9 @@ def rt_radio_map_backward(scene: RtScene, eps_r, sigma, tx, plane, params, tape:
                 _f32spec(grad_eps_r, "grad_eps_r", nm), _f32spec(grad_sigma, "grad_sigma", nm),
                 _f32spec(grad_orient, "grad_orient", 3))
     t = tx if isinstance(tx, rt_tx) else make_tx(tx)
-    _check(lib().rt_radio_map_backward(scene.handle, rt_materials(*ptr[:6]), C.byref(t), C.byref(pl), C.byref(p),
-                                       tape.handle, *ptr[6:], _stream(stream)))
+    fn = lib().rt_radio_map_backward_noalloc if noalloc else lib().rt_radio_map_backward
+    _check(fn(scene.handle, rt_materials(*ptr[:6]), C.byref(t), C.byref(pl), C.byref(p),
+              tape.handle, *ptr[6:], _stream(stream)))
 
 
 def rt_radio_map_batched(scene: RtScene, eps_r, sigma, txs: Sequence, rays_per_tx: Sequence[int], plane, params,

@@ -461,10 +461,12 @@ extern "C" rt_status rt_tape_destroy(rt_tape* t) {
 }
 
 // ---------------------------------------------------------------- backward
-extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials materials, const rt_tx* tx,
-                                           const rt_plane* plane, const rt_sbr_params* params,
-                                           const rt_tape* tape, const float* grad_map, float* grad_eps_r,
-                                           float* grad_sigma, float* grad_orient, void* stream) {
+// `noalloc`: the per-block partial sums go to this GPU's static workspace
+// instead of the scene's (which is allocated on first use).
+static rt_status backward_call(const rt_scene* scene, rt_materials materials, const rt_tx* tx,
+                               const rt_plane* plane, const rt_sbr_params* params, const rt_tape* tape,
+                               const float* grad_map, float* grad_eps_r, float* grad_sigma, float* grad_orient,
+                               void* stream, bool noalloc) {
     CHECK_ARG(scene != nullptr, "rt_radio_map_backward: scene is NULL");
     CHECK_ARG(tape != nullptr, "rt_radio_map_backward: tape is NULL");
     CHECK_ARG(grad_map != nullptr, "rt_radio_map_backward: grad_map is NULL");
@@ -499,7 +501,27 @@ extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials m
     bl.scattering = materials.scattering;
     bl.xpd = materials.xpd;
     bl.seed = params->seed;
+    if (noalloc) {
+        if ((r = rt_backward_scratch(&bl.workspace)) != RT_OK) return r;
+        bl.workspace_bytes = rt_backward_scratch_bytes();
+    }
     return rt_launch_backward(bl, (hipStream_t)stream);
+}
+
+extern "C" rt_status rt_radio_map_backward(const rt_scene* scene, rt_materials materials, const rt_tx* tx,
+                                           const rt_plane* plane, const rt_sbr_params* params,
+                                           const rt_tape* tape, const float* grad_map, float* grad_eps_r,
+                                           float* grad_sigma, float* grad_orient, void* stream) {
+    return backward_call(scene, materials, tx, plane, params, tape, grad_map, grad_eps_r, grad_sigma, grad_orient,
+                         stream, false);
+}
+
+extern "C" rt_status rt_radio_map_backward_noalloc(const rt_scene* scene, rt_materials materials, const rt_tx* tx,
+                                                   const rt_plane* plane, const rt_sbr_params* params,
+                                                   const rt_tape* tape, const float* grad_map, float* grad_eps_r,
+                                                   float* grad_sigma, float* grad_orient, void* stream) {
+    return backward_call(scene, materials, tx, plane, params, tape, grad_map, grad_eps_r, grad_sigma, grad_orient,
+                         stream, true);
 }
 
 // ----------------------------------------------------------------- batched

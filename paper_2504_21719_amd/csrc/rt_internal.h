@@ -211,8 +211,14 @@ struct BwdLaunch {
     const float* scattering; // diffuse reflection: S and K_x per material, or null
     const float* xpd;
     uint32_t seed;           // key of the forward's random streams
+    void* workspace;         // per-block partial sums, or null (the scene's, grown on demand)
+    size_t workspace_bytes;
 };
 rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st);
+// Device address of this GPU's static backward workspace (resolved once per
+// device) and its size.
+rt_status rt_backward_scratch(void** out);
+size_t rt_backward_scratch_bytes();
 
 // The extensions of the single-transmitter forward (slab walls, refraction,
 // diffuse reflection, early termination) for a launch over several

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "sbr_common.h"
 
@@ -342,13 +343,49 @@ __global__ void __launch_bounds__(64) k_backward_final(const double* __restrict_
     }
 }
 
+constexpr int kBwdP = 2 * kMatChunk + 3;
+
 }  // namespace
+
+// Per-block partial sums of the backward for callers that cannot allocate
+// (rt_radio_map_backward_noalloc): one copy per GPU, kept until the process
+// ends.  Every launch overwrites all kBwdBlocks x P entries before the final
+// kernel reads them, so nothing needs clearing between calls; two calls that
+// overlap on one GPU race on it.  In host code `scratch` is only a symbol:
+// its device address comes from hipGetSymbolAddress (rt_backward_scratch).
+static __device__ __align__(256) double scratch[(size_t)kBwdBlocks * kBwdP];
+
+size_t rt_backward_scratch_bytes() { return sizeof(double) * (size_t)kBwdBlocks * kBwdP; }
+
+rt_status rt_backward_scratch(void** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return rt_hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return rt_fail(RT_EDEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // the current device is `dev`: this resolves that device's copy
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return rt_hip_fail(e, "hipGetSymbolAddress(scratch)");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return RT_OK;
+}
 
 rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
     rt_scene* s = const_cast<rt_scene*>(b.scene);
-    const int P = 2 * kMatChunk + 3;
+    const int P = kBwdP;
     size_t need = sizeof(double) * (size_t)kBwdBlocks * P;
-    if (s->grad_ws_bytes < need) {
+    double* partials = (double*)b.workspace;
+    if (partials) {
+        if (b.workspace_bytes < need)
+            return rt_fail(RT_EOVERFLOW, "rt_radio_map_backward: workspace smaller than the partial sums");
+    } else if (s->grad_ws_bytes < need) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(s->grad_ws);
         s->grad_ws = nullptr;
@@ -357,6 +394,7 @@ rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
         if (e != hipSuccess) return rt_hip_fail(e, "rt_radio_map_backward: workspace");
         s->grad_ws_bytes = need;
     }
+    if (!partials) partials = (double*)s->grad_ws;
     BwdArgs a;
     a.seg = b.tape->seg;
     a.nseg = b.tape->nseg;
@@ -380,7 +418,7 @@ rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
     a.map_stride = (int64_t)b.pl.W * b.pl.H;
     a.n_mat = s->n_mat;
     a.P = P;
-    a.partials = (double*)s->grad_ws;
+    a.partials = partials;
     const bool ext = a.thickness || a.refraction || a.scattering || a.rr_p_max > 0.0f;
     for (int m0 = 0; m0 < std::max(1, s->n_mat); m0 += kMatChunk) {
         a.mat0 = m0;
@@ -389,7 +427,7 @@ rt_status rt_launch_backward(const BwdLaunch& b, hipStream_t st) {
             hipLaunchKernelGGL(k_backward<true>, dim3(kBwdBlocks), dim3(kBwdBlock), 0, st, a);
         else
             hipLaunchKernelGGL(k_backward<false>, dim3(kBwdBlocks), dim3(kBwdBlock), 0, st, a);
-        hipLaunchKernelGGL(k_backward_final, dim3(P), dim3(64), 0, st, (const double*)s->grad_ws, kBwdBlocks,
+        hipLaunchKernelGGL(k_backward_final, dim3(P), dim3(64), 0, st, (const double*)partials, kBwdBlocks,
                            s->n_mat, m0, a.write_orient, b.grad_eps, b.grad_sigma, b.grad_orient);
     }
     hipError_t e = hipGetLastError();

@@ -134,6 +134,28 @@ def test_null_arguments_rejected():
     assert L.rt_tape_bytes(C.byref(_params(n_rays=100, max_depth=3))) == 100 * 4 * 64 + 100 * 4
 
 
+@pytest.mark.parametrize("name", ["rt_radio_map_backward", "rt_radio_map_backward_noalloc"])
+def test_backward_null_arguments_rejected(name):
+    # both backward entry points validate on the host before touching a device
+    import paper_2504_21719_amd as rt
+    L = rt.lib()
+    fn = getattr(L, name)
+    dummy = C.create_string_buffer(64)
+    out = C.create_string_buffer(64)
+    tx = rt.rt_tx()
+    tx.pos[:] = [0.0, 0.0, 10.0]
+    pl = rt.rt_plane(1.5, 0, 0, 1, 1, 10, 10)
+    m = rt.rt_materials(C.cast(out, C.c_void_p), C.cast(out, C.c_void_p))
+    o = C.cast(out, C.c_void_p)
+    d = C.cast(dummy, C.c_void_p)
+    assert fn(None, m, C.byref(tx), C.byref(pl), C.byref(_params()), d, o, o, o, o, None) == rt.RT_EINVAL
+    assert "scene" in L.rt_last_error().decode()
+    assert fn(d, m, C.byref(tx), C.byref(pl), C.byref(_params()), None, o, o, o, o, None) == rt.RT_EINVAL
+    assert "tape" in L.rt_last_error().decode()
+    assert fn(d, m, C.byref(tx), C.byref(pl), C.byref(_params()), d, None, o, o, o, None) == rt.RT_EINVAL
+    assert fn(d, m, C.byref(tx), C.byref(pl), C.byref(_params(max_depth=-1)), d, o, o, o, o, None) == rt.RT_EINVAL
+
+
 def test_batched_argument_checks():
     import paper_2504_21719_amd as rt
     L = rt.lib()
