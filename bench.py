@@ -32,6 +32,7 @@ transmitters on both scenes.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -153,9 +154,10 @@ def trace_summary(path, steps):
     out = {"kernel": "k_forward<false, MODE_SINGLE, wide, not extended>", "dispatches": len(rows)}
     for name, sel in (("timed_steps", rows[-2 * steps:-steps]), ("kernel_only", rows[-steps:])):
         d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
+        r0 = sel[0]
         out[name] = {"n": len(d), "avg_us": round(sum(d) / len(d), 1), "min_us": round(min(d), 1),
-                     "max_us": round(max(d), 1), "grid": int(sel[0]["Grid_Size"]),
-                     "workgroup": int(sel[0]["Workgroup_Size"])}
+                     "max_us": round(max(d), 1), "grid": int(r0.get("Grid_Size_X", r0.get("Grid_Size", 0))),
+                     "workgroup": int(r0.get("Workgroup_Size_X", r0.get("Workgroup_Size", 0)))}
     print(json.dumps(out))
     return out
 
@@ -825,6 +827,7 @@ def cpu_baseline(cfg, seconds, workers=0):
     stride = N // per_chunk
     workers = int(workers or min(16, os.cpu_count() or 1))
     oracle.lib()   # built before forking
+    gc.collect()   # collected before forking, so that no finalizer runs in a worker
     w0 = time.perf_counter()
     deadline = time.time() + seconds
     jobs = [(cfg, list(range(w, stride, workers)), stride, per_chunk, deadline) for w in range(workers)]

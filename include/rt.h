@@ -122,7 +122,10 @@ rt_status rt_scene_info_get(const rt_scene* scene, rt_scene_info* out);
  * library's own design; the paper delegates intersection to its renderer).
  * Every buffer may be NULL to skip it:
  *   morton  uint64 [n_triangles]    63-bit Morton codes of the triangle AABB
- *                                   centres, in sorted (slot) order
+ *                                   centres (21 bits per axis, one scale for
+ *                                   all axes: 2^21 - 1 over the largest
+ *                                   extent of the centres' box), in sorted
+ *                                   (slot) order
  *   nodes   float  [n_nodes][16]    binary internal nodes, four float4 each:
  *                                   (L.lo.x, L.hi.x, L.lo.y, L.hi.y),
  *                                   (R.lo.x, R.hi.x, R.lo.y, R.hi.y),

@@ -15,6 +15,7 @@ order).
 from __future__ import annotations
 
 import ctypes as C
+import gc
 import os
 import subprocess
 import threading
@@ -339,6 +340,7 @@ def radio_map_parallel(scene, tx, plane, params, workers=None, chunks_per_worker
             kwi["replay_hits"] = replay_hits[edges[i] - b0: edges[i + 1] - b0]
         jobs.append((scene, tx, plane, params, edges[i], edges[i + 1], kwi))
     lib()  # build before forking
+    gc.collect()  # collect before forking, so that no finalizer runs in a worker
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
         parts = pool.map(_worker, jobs)

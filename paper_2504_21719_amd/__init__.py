@@ -227,6 +227,7 @@ class RtScene:
     def __init__(self, handle, n_materials):
         self.handle = handle
         self.n_materials = n_materials
+        self._pid = os.getpid()
 
     def info(self) -> rt_scene_info:
         out = rt_scene_info()
@@ -253,9 +254,11 @@ class RtScene:
         return {"morton": morton, "nodes": nodes, "wide": wide, "tris": tris}
 
     def close(self):
-        if self.handle:
+        # a process forked from the owner (a host worker pool) must not call
+        # into HIP: there the handle is only dropped, the owner frees it
+        if self.handle and os.getpid() == self._pid:
             lib().rt_scene_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -342,33 +345,18 @@ def rt_radio_map(scene: RtScene, eps_r, sigma, tx, plane, params, out_map, *, ta
 
 
 class RtTape:
+    """Owner of an rt_tape* (device-resident forward records)."""
+
     def __init__(self, handle, nbytes):
         self.handle = handle
         self.nbytes = nbytes
-
-    def export(self, stream=None):
-        """Host copies of the acceleration structure (rt_scene_export):
-        morton uint64 [n_tri], nodes float32 [n_tri - 1][16] (binary tree),
-        wide float32 [n_wide][32] (4-wide tree, empty if none) and tris
-        float32 [n_tri][12] in slot order."""
-        import numpy as np
-        L = lib()
-        n_wide = C.c_int64(0)
-        _check(L.rt_scene_export(self.handle, None, None, None, None, C.byref(n_wide), _stream(stream)))
-        info = self.info()
-        n = int(info.n_triangles)
-        morton = np.zeros(n, np.uint64)
-        nodes = np.zeros((max(0, n - 1), 16), np.float32)
-        wide = np.zeros((int(n_wide.value), 32), np.float32)
-        tris = np.zeros((n, 12), np.float32)
-        _check(L.rt_scene_export(self.handle, morton.ctypes.data, nodes.ctypes.data, wide.ctypes.data,
-                                 tris.ctypes.data, C.byref(n_wide), _stream(stream)))
-        return {"morton": morton, "nodes": nodes, "wide": wide, "tris": tris}
+        self._pid = os.getpid()
 
     def close(self):
-        if self.handle:
+        # as RtScene.close: only the creating process frees the tape
+        if self.handle and os.getpid() == self._pid:
             lib().rt_tape_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:

@@ -240,7 +240,10 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
             while (leaves) {
                 const int c = __builtin_ctz(leaves);
                 leaves &= leaves - 1u;
-                test(~(c == 0 ? ref[0] : c == 1 ? ref[1] : c == 2 ? ref[2] : ref[3]));
+                // select by the bits of c (selects, not a branch per slot)
+                const int r01 = (c & 1) ? ref[1] : ref[0];
+                const int r23 = (c & 1) ? ref[3] : ref[2];
+                test(~((c & 2) ? r23 : r01));
             }
             // sort the four (key, ref) pairs by key (misses sort last)
 #define RT_CSWAP(i, j)                                  \

@@ -8,6 +8,8 @@ write past its end.  Every case below uses host tensors: a correctly sized
 host tensor gets as far as the device check, so the size and dtype checks are
 seen to come first.
 """
+import ctypes as C
+
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -120,3 +122,33 @@ def test_build_scene_rejects_bad_tensors():
 def test_tune_rejects_short_scratch_map():
     with pytest.raises(ValueError, match="scratch_map: needs at least"):
         rt.rt_tune(_FakeScene(), f32(2), f32(2), sg.Tx((0.0, 0.0, 10.0)), PLANE, PARAMS, 1000, f32(H * W - 1))
+
+
+class _StubLib:
+    def __init__(self):
+        self.calls = []
+
+    def rt_scene_destroy(self, h):
+        self.calls.append(("scene", h))
+
+    def rt_tape_destroy(self, h):
+        self.calls.append(("tape", h))
+
+
+@pytest.mark.parametrize("cls,kind", [("RtScene", "scene"), ("RtTape", "tape")])
+def test_handles_are_freed_only_by_their_creating_process(monkeypatch, cls, kind):
+    # a host worker pool forks the process: a scene or tape object that is
+    # garbage-collected in the child must not call into HIP (doing so crashed
+    # the child); only the creating process frees the handle
+    import os
+    stub = _StubLib()
+    monkeypatch.setattr(rt, "lib", lambda: stub)
+    obj = getattr(rt, cls)(C.c_void_p(0x1234), 1)
+    obj._pid = os.getpid() + 1           # as seen from a forked child
+    obj.close()
+    assert stub.calls == [] and obj.handle is None
+    own = getattr(rt, cls)(C.c_void_p(0x5678), 1)
+    own.close()
+    assert [c[0] for c in stub.calls] == [kind] and own.handle is None
+    own.close()                          # a second close does nothing
+    assert len(stub.calls) == 1

@@ -40,16 +40,17 @@ def _spread21(v):
 
 def reference_morton(V, F):
     """Morton codes of the AABB centres, in FP32 as the builder defines them:
-    centre = 0.5 (lo + hi) per axis, quantised to 21 bits over the centres'
-    bounding box with scale (2^21 - 1) / extent (0 for a flat axis)."""
+    centre = 0.5 (lo + hi) per axis, quantised to 21 bits from the lower
+    corner of the centres' bounding box with one scale for all axes,
+    (2^21 - 1) / (largest extent) (0 if every centre coincides)."""
     P = V[F].astype(np.float32)                      # [n, 3 vertices, 3 axes]
     lo = P.min(axis=1)
     hi = P.max(axis=1)
     c = np.float32(0.5) * (lo + hi)
     cl = c.min(axis=0)
-    ext = c.max(axis=0) - cl
+    ext = np.float32((c.max(axis=0) - cl).max())
     qmax = np.float32(2097151.0)
-    sc = np.where(ext > 0, qmax / np.where(ext > 0, ext, np.float32(1)), np.float32(0)).astype(np.float32)
+    sc = np.float32(qmax / ext) if ext > 0 else np.float32(0)
     q = np.minimum(np.maximum((c - cl) * sc, np.float32(0)), qmax).astype(np.uint32)
     return (_spread21(q[:, 0]) << np.uint64(2)) | (_spread21(q[:, 1]) << np.uint64(1)) | _spread21(q[:, 2])
 

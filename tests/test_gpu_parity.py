@@ -5,6 +5,7 @@ Protocol (see gpu_helpers): bit-exact hit sequences except oracle-flagged rays
 borders, per-crossing weights within 1e-5 relative, and per-cell maps within
 1e-3 relative for cells with >= 100 crossings (plus the border allowance).
 """
+import gc
 import math
 import os
 
@@ -271,18 +272,19 @@ def test_large_mesh_strided_rays():
     assert info.n_triangles == cfg.scene.n_triangles
     starts = np.linspace(0, cfg.params.n_rays - 512, 80).astype(np.int64) // 64 * 64 + 5
     chunks = [(int(b), int(b) + 256) for b in starts]
-    gh, gc, gw = [], [], []
+    gh, gcl, gw = [], [], []
     for b, e in chunks:
         g = gpu_radio_map(cfg, scene_handle=s, ray_begin=b, ray_end=e)
         assert int(g.stats[4]) == 0
         gh.append(g.hits)
-        gc.append(g.cells)
+        gcl.append(g.cells)
         gw.append(g.weights)
-    hits, cells, weights = np.concatenate(gh), np.concatenate(gc), np.concatenate(gw)
+    hits, cells, weights = np.concatenate(gh), np.concatenate(gcl), np.concatenate(gw)
     ids = np.concatenate([np.arange(b, e, dtype=np.int64) for b, e in chunks])
     print("gpu done", flush=True)
     _LARGE = cfg
     oracle.lib()
+    gc.collect()   # collect before forking, so that no finalizer runs in a worker
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
         parts = pool.map(_large_chunk, chunks)
     print("oracle done", flush=True)
