@@ -19,6 +19,13 @@
 //    kept in registers.  Slab walls without refraction (eq. fresnel_slab)
 //    and transmit arrays fit this split: neither changes a ray's path, only
 //    its coefficients or its weight.
+//    The geometry records are kept in the launch order of the traversal
+//    (azimuth-sorted chunks of each lattice), so the lanes of a wavefront of
+//    the field pass hold nearby directions: they read consecutive records,
+//    and without gradients their same-cell crossings are summed across the
+//    wavefront before the atomics (measured on 16 samples of 1e6 rays:
+//    1.31 -> 0.81 ms forward; 1.65 -> 1.41 ms forward + backward, where the
+//    gradient variant keeps per-lane atomics for its registers' sake).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,7 +62,50 @@ struct SampArgs {
     int P;                  // 2 n_mat + 3
     const float* thickness; // slab thickness per material (m, shared by the samples), or null
     float k0;               // 2 pi / lambda
+    // launch order of the geometry tape: record g of transmitter t holds work
+    // item n = g - prefix[t], whose lattice index is the chunk permutation of n
+    const int* operm;       // null: records are in lattice order
+    const int* oshift;
+    int olog2m;
 };
+
+// Lattice index of work item n of transmitter td (the forward's launch order).
+__device__ __forceinline__ int64_t lattice_index(const SampArgs& a, const TxDesc& td, int64_t n) {
+    if (a.operm && (n >> a.olog2m) < td.n_chunks) {
+        const int64_t M = (int64_t)1 << a.olog2m, c = n >> a.olog2m, c0 = c << a.olog2m;
+        n = c0 + a.operm[((n - c0) + a.oshift[td.shift0 + c]) & (M - 1)];
+    }
+    return n;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Deposit of one crossing per lane (cell < 0: none) into the map of the
+// lane's transmitter slot: at most four groups of lanes with the same slot
+// and cell are summed across the wavefront before one atomic each; lanes
+// left over add their own crossings.  Every lane of the wavefront calls it.
+__device__ __forceinline__ void deposit_wave(float* map, int cell, float w, int slot) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long pend = __ballot(cell >= 0);
+    bool done = cell < 0;
+    for (int groups = 0; pend; groups++) {
+        if (groups == 4) {
+            if (!done) unsafeAtomicAdd(map + cell, w);
+            break;
+        }
+        const int leader = __ffsll((long long)pend) - 1;
+        const int lc = __shfl(cell, leader), ls = __shfl(slot, leader);
+        const bool mine = !done && cell == lc && slot == ls;
+        const unsigned long long grp = __ballot(mine);
+        const float v = wave_sum_f(mine ? w : 0.0f);
+        if (lane == leader) unsafeAtomicAdd(map + lc, v);
+        if (mine) done = true;
+        pend &= ~grp;
+    }
+}
 
 __device__ __forceinline__ int find_tx_s(const int64_t* __restrict__ prefix, int n_tx, int64_t g) {
     int lo = 0, hi = n_tx;
@@ -95,7 +145,7 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
             tx_i = t;
             td = a.txs[t];
             slot_out = a.slots[t];
-            const int64_t n = g - a.prefix[t];
+            const int64_t n = lattice_index(a, td, g - a.prefix[t]);
             ns = a.nseg[g];
             Launch Lr = fib_launch(n, td.n_rays);
             if (GRAD) {
@@ -131,16 +181,28 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                 ge[j] = 0.f;
                 gs[j] = 0.f;
             }
-            if (valid) {
+            cf E0[kMaxSeg], E1[kMaxSeg];
+            {
+                // forward field pass: every lane takes part in the wavefront
+                // deposits (invalid lanes have ns = 0)
                 const float* eps = a.eps_r + (int64_t)s * a.n_mat;
                 const float* sig = a.sigma + (int64_t)s * a.n_mat;
-                float* map = a.maps + ((int64_t)slot_out * S + s) * HW;
+                float* map = a.maps + ((int64_t)max(slot_out, 0) * S + s) * HW;
                 cf e0 = {cth.v, 0.f}, e1 = {cph.v, 0.f};
-                cf E0[kMaxSeg], E1[kMaxSeg];
 #pragma unroll
                 for (int l = 0; l < kMaxSeg; l++) {
-                    if (l >= ns) break;
-                    if (cell[l] >= 0) unsafeAtomicAdd(map + cell[l], gk[l] * (cabs2(e0) + cabs2(e1)));
+                    if (GRAD) {
+                        // gradient variant: per-lane atomics (the wavefront
+                        // sums' registers would cost occupancy here)
+                        if (l >= ns) break;
+                        if (cell[l] >= 0) unsafeAtomicAdd(map + cell[l], gk[l] * (cabs2(e0) + cabs2(e1)));
+                    } else {
+                        if (__ballot(l < ns) == 0ull) break;
+                        const bool live = l < ns;
+                        const int dc = live ? cell[l] : -1;
+                        deposit_wave(map, dc, dc >= 0 ? gk[l] * (cabs2(e0) + cabs2(e1)) : 0.0f, slot_out);
+                        if (!live) continue;
+                    }
                     E0[l] = e0;
                     E1[l] = e1;
                     if (l + 1 < ns) {
@@ -156,6 +218,10 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                         e1 = cmul(cf{-F.rpar.re, -F.rpar.im}, u1);
                     }
                 }
+            }
+            if (valid) {
+                const float* eps = a.eps_r + (int64_t)s * a.n_mat;
+                const float* sig = a.sigma + (int64_t)s * a.n_mat;
                 if (GRAD) {
                     const float* G = a.grad_maps + ((int64_t)slot_out * S + s) * HW;
                     cf lam0 = {0, 0}, lam1 = {0, 0};
@@ -243,10 +309,11 @@ __global__ void __launch_bounds__(kSampBlock) k_samples_deep(const SampArgs a) {
         const TxDesc td = a.txs[t];
         const int slot_out = a.slots[t];
         const int ns = a.nseg[g];
+        const int64_t nl = lattice_index(a, td, g - a.prefix[t]);
         const float* eps = a.eps_r + (int64_t)s * a.n_mat;
         const float* sig = a.sigma + (int64_t)s * a.n_mat;
         float* map = a.maps + ((int64_t)slot_out * a.S + s) * HW;
-        Launch Lr = fib_launch(g - a.prefix[t], td.n_rays);
+        Launch Lr = fib_launch(nl, td.n_rays);
         float ct, cp;
         tx_pattern<float>(Lr, td, td.pol == 1 ? 1 : 0, ct, cp);
         const float kap = td.n_ant > 0 ? td.kappa * array_gain(Lr, td) : td.kappa;
@@ -375,6 +442,9 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
     a.P = P;
     a.thickness = b.ext.thickness;
     a.k0 = b.ext.k0;
+    a.operm = b.order ? b.order->perm : nullptr;
+    a.oshift = s->shifts;
+    a.olog2m = b.order ? b.order->log2m : 0;
     unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1 << 20, (b.total_rays + kSampBlock - 1) / kSampBlock));
     if (b.total_rays > 0) {
         // slab walls and transmit arrays each get their own variant, so that

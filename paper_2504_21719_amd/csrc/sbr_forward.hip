@@ -422,7 +422,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
                             if (a.operm && (n >> a.olog2m) < td.n_chunks) {
                                 int64_t c = n >> a.olog2m, c0 = c << a.olog2m;
                                 n = c0 + a.operm[((n - c0) + a.oshift[td.shift0 + c]) & (M - 1)];
-                                rid = a.prefix[t] + n;   // the geometry tape is indexed by lattice index
+                                // the geometry tape stays in launch order (a
+                                // wavefront of the field pass then reads
+                                // consecutive records of nearby directions)
+                                if (MODE != MODE_GEOM) rid = a.prefix[t] + n;
                             }
                             kap = td.kappa;
                             mapb = a.map + (int64_t)a.slots[t] * a.slot_stride;
