@@ -224,6 +224,11 @@ __device__ __forceinline__ void tx_pattern(const Launch& L, const TxDesc& t, int
 }
 
 // ------------------------------------------------------------ geometry
+// Relative slack of the slab test, above the rounding of the slab distances
+// and of the triangle distance, so that a box is never culled while a
+// triangle inside it can still win.
+constexpr float kBoxSlack = 1.0f + 1e-5f;
+
 struct Ray {
     float ox, oy, oz;
     float dx, dy, dz;
@@ -231,6 +236,7 @@ struct Ray {
     float sx, sy, sz;          // watertight shear constants
     int kx, ky, kz;            // watertight axis permutation
     unsigned nx, ny, nz;       // byte offsets of the near planes in a 4-wide node
+    float jx, jy, jz;          // reciprocal direction times kBoxSlack (far planes of box4)
 };
 
 __device__ __forceinline__ float pick(float a, float b, float c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
@@ -263,6 +269,9 @@ __device__ __forceinline__ void ray_setup(Ray& r) {
     r.ix = safe_inv(r.dx);
     r.iy = safe_inv(r.dy);
     r.iz = safe_inv(r.dz);
+    r.jx = r.ix * kBoxSlack;
+    r.jy = r.iy * kBoxSlack;
+    r.jz = r.iz * kBoxSlack;
     r.nx = r.ix < 0.0f ? 16u : 0u;
     r.ny = r.iy < 0.0f ? 48u : 32u;
     r.nz = r.iz < 0.0f ? 80u : 64u;
@@ -300,10 +309,6 @@ __device__ __forceinline__ float tri_hit(const Ray& r, float4 a, float4 b, float
     return t > t_min ? t : -1.0f;
 }
 
-// Relative slack of the slab test, above the rounding of the slab distances
-// and of the triangle distance, so that a box is never culled while a
-// triangle inside it can still win.
-constexpr float kBoxSlack = 1.0f + 1e-5f;
 
 // Slab test of the two children of a node.  lo/hi layout as in rt_internal.h.
 __device__ __forceinline__ void box2(const Ray& r, float4 q0, float4 q1, float4 q2, float tmin, float tmax,
@@ -357,7 +362,7 @@ __device__ __forceinline__ void box4(const Ray& r, __amdgpu_buffer_rsrc_t rs, un
 #pragma unroll
     for (int c = 0; c < 4; c++) {
         float a = fmaxf(fmaxf((nxa[c] - r.ox) * r.ix, (nya[c] - r.oy) * r.iy), fmaxf((nza[c] - r.oz) * r.iz, tmin));
-        float b = fminf(fminf((fxa[c] - r.ox) * r.ix, (fya[c] - r.oy) * r.iy), (fza[c] - r.oz) * r.iz) * kBoxSlack;
+        float b = fminf(fminf((fxa[c] - r.ox) * r.jx, (fya[c] - r.oy) * r.jy), (fza[c] - r.oz) * r.jz);
         hit[c] = a <= fminf(b, tmax);
         tent[c] = a;
     }

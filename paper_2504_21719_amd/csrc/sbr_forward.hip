@@ -190,7 +190,12 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
     t_best = INFINITY;
     id_best = 0x7fffffff;
     int slot_best = -1;
-    const float tmin = a.t_min;
+    // cull limit: t_best times the slack, kept finite so that the INFINITY
+    // keys of missed, leaf and empty slots never pass it, also before the
+    // first hit; updated with t_best
+    float lim = FLT_MAX;
+    // canonical once, so that the min/max below need no per-use quieting
+    const float tmin = __builtin_canonicalizef(a.t_min);
     if (a.n_tri == 0) return -1;
     auto test = [&](int s) {
         if (s == last) return;
@@ -203,6 +208,7 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
                 t_best = t;
                 id_best = id;
                 slot_best = s;
+                lim = fminf(t * kBoxSlack, FLT_MAX);
             }
         }
     };
@@ -227,7 +233,7 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
             bool h[4];
             float te[4];
             int ref[4];
-            box4(r, rs, (unsigned)node << 7, tmin, t_best * kBoxSlack, h, te, ref);
+            box4(r, rs, (unsigned)node << 7, tmin, lim, h, te, ref);
             float key[4];
             unsigned leaves = 0;
 #pragma unroll
@@ -258,10 +264,7 @@ __device__ __forceinline__ int closest_hit(const FwdArgs& a, const Ray& r, int l
             RT_CSWAP(0, 1) RT_CSWAP(2, 3) RT_CSWAP(0, 2) RT_CSWAP(1, 3) RT_CSWAP(1, 2)
 #undef RT_CSWAP
             // children entered beyond the closest hit so far are dropped (the
-            // same outcome as a box test with the new bound); the limit stays
-            // finite so that the INFINITY keys of missed, leaf and empty slots
-            // never pass it, also before the first hit
-            const float lim = fminf(t_best * kBoxSlack, FLT_MAX);
+            // same outcome as a box test with the new bound)
             if (key[0] <= lim) {
 #pragma unroll
                 for (int c = 3; c >= 1; c--)
