@@ -505,10 +505,11 @@ def traffic_from_profile(path=PROFILE_COUNTERS):
 
 def large_extras(rt, sg, cfg, scene, eps, sig, dev, out, reps=3):
     """Side legs on the 1.02 M-triangle scene: Russian roulette from depth 2
-    (p_max 0.5) against the plain run, and 64 rooftop transmitters with ray
+    (p_max 0.5) against the plain run; 64 rooftop transmitters with ray
     budgets log-uniform in [1e5, 1e7] (L = 5, 64 x 1000 x 1000 maps) in one
     batched call against the per-transmitter loop of rt_radio_map calls on one
-    stream (same outputs, one synchronisation)."""
+    stream (same outputs, one synchronisation); 16 material samples forward +
+    backward in one batched call against 16 taped forwards and adjoints."""
     import dataclasses
     import numpy as np
     import torch
@@ -541,6 +542,39 @@ def large_extras(rt, sg, cfg, scene, eps, sig, dev, out, reps=3):
                                     "batched_ms": round(t_batch, 3), "plain_loop_ms": round(t_plain, 3),
                                     "ratio": round(t_plain / t_batch, 3)}
     del maps
+    # 16 material samples forward + backward from the headline transmitter
+    # (1e6 rays, L = 5): one batched call against 16 taped forwards + adjoints
+    S, n_rays = 16, 1_000_000
+    H, W = cfg.plane.H, cfg.plane.W
+    E, Sg = sg.random_materials(cfg.scene, S, seed=5)
+    eS = torch.tensor(E, dtype=torch.float32, device=dev)
+    sS = torch.tensor(Sg, dtype=torch.float32, device=dev)
+    p1 = sg.Params(cfg.params.freq_hz, n_rays, 5)
+    smaps = torch.empty((1, S, H, W), dtype=torch.float32, device=dev)
+    gm = torch.randn((1, S, H, W), dtype=torch.float32, device=dev)
+    grads = torch.empty((1, S, 2 * cfg.scene.n_materials + 3), dtype=torch.float32, device=dev)
+    nm = cfg.scene.n_materials
+    ge, gs, go = (torch.empty(n, dtype=torch.float32, device=dev) for n in (nm, nm, 3))
+    tape = rt.rt_tape_create(p1)
+    es_list = [eS[k].contiguous() for k in range(S)]
+    ss_list = [sS[k].contiguous() for k in range(S)]
+    g_list = [gm[0, k][None].contiguous() for k in range(S)]
+
+    def plain_samples():
+        for k in range(S):
+            rt.rt_radio_map(scene, es_list[k], ss_list[k], cfg.tx, cfg.plane, p1, smaps[0, k][None], tape=tape)
+            rt.rt_radio_map_backward(scene, es_list[k], ss_list[k], cfg.tx, cfg.plane, p1, tape, g_list[k], ge, gs, go)
+
+    def batched_samples():
+        rt.rt_radio_map_batched(scene, eS, sS, [cfg.tx], [n_rays], cfg.plane, sg.Params(cfg.params.freq_hz, 1, 5),
+                                smaps, grad_maps=gm, grads=grads)
+
+    t_ps = _time(plain_samples, reps, 1)
+    t_bs = _time(batched_samples, reps, 1)
+    res["batched_samples_over_plain"] = {"workload": "16 material samples forward + backward, headline Tx, "
+                                                     "1e6 rays, L = 5", "batched_ms": round(t_bs, 3),
+                                         "plain_loop_ms": round(t_ps, 3), "ratio": round(t_ps / t_bs, 3)}
+    del smaps, gm, tape
     torch.cuda.empty_cache()
     return res
 
