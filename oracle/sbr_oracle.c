@@ -120,7 +120,7 @@ typedef double complex cplx;
 #define OR_FLAG_CHOICE 64u   /* interaction-type draw within 1e-5 of a class boundary */
 
 #define OR_MAX_PARAMS 64
-#define OR_MAX_DEPTH 64
+#define OR_MAX_DEPTH 64   /* largest max_depth L (L + 1 segments), as the library accepts */
 
 /* ---------------------------------------------------------------- vectors */
 typedef struct { double x, y, z; } vec3;
@@ -624,7 +624,7 @@ int or_radio_map(const float* V, int64_t n_v, const int32_t* F, int64_t n_tri,
                  const int64_t* ray_ids, int64_t n_ids, int64_t ray_begin, int64_t ray_end,
                  or_out* out)
 {
-    if (prm->n_rays < 1 || prm->max_depth < 0 || prm->max_depth >= OR_MAX_DEPTH) return 1;
+    if (prm->n_rays < 1 || prm->max_depth < 0 || prm->max_depth > OR_MAX_DEPTH) return 1;
     if (pl->W < 1 || pl->H < 1 || !(pl->dx > 0) || !(pl->dy > 0)) return 1;
     if (n_mat < 1 || 2 * n_mat + 3 > OR_MAX_PARAMS) return 1;
     if (prm->refraction && !thickness) return 1;
