@@ -237,6 +237,7 @@ struct Ray {
     int kx, ky, kz;            // watertight axis permutation
     unsigned nx, ny, nz;       // byte offsets of the near planes in a 4-wide node
     float jx, jy, jz;          // reciprocal direction times kBoxSlack (far planes of box4)
+    float cnx, cny, cnz;       // -o i lowered past its rounding (near planes of box4)
 };
 
 __device__ __forceinline__ float pick(float a, float b, float c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
@@ -272,6 +273,20 @@ __device__ __forceinline__ void ray_setup(Ray& r) {
     r.jx = r.ix * kBoxSlack;
     r.jy = r.iy * kBoxSlack;
     r.jz = r.iz * kBoxSlack;
+    // near planes are evaluated as p i + cn, one fma: cn is the rounded -o i
+    // lowered by 2^-22 |o i|, which exceeds the rounding of -o i and of the
+    // lowering itself (each at most 2^-24 |o i|), so p i + cn lies below
+    // (p - o) i and the fma's own rounding is relative, like the product's
+    // before, and covered by kBoxSlack: an entry distance can only come out
+    // smaller, never culling a box.  Far planes keep the difference and
+    // product, so boxes behind the origin (exit below tmin) stay culled as
+    // sharply as before.
+    {
+        const float cx = -r.ox * r.ix, cy = -r.oy * r.iy, cz = -r.oz * r.iz;
+        r.cnx = __builtin_fmaf(fabsf(cx), -0x1p-22f, cx);
+        r.cny = __builtin_fmaf(fabsf(cy), -0x1p-22f, cy);
+        r.cnz = __builtin_fmaf(fabsf(cz), -0x1p-22f, cz);
+    }
     r.nx = r.ix < 0.0f ? 16u : 0u;
     r.ny = r.iy < 0.0f ? 48u : 32u;
     r.nz = r.iz < 0.0f ? 80u : 64u;
@@ -348,7 +363,9 @@ __device__ __forceinline__ float4 ld16(__amdgpu_buffer_rsrc_t rs, unsigned off) 
 // Per axis the ray reads its near planes (lo for a positive direction
 // component, else hi) and its far planes, so that no min/max per axis is
 // needed: entry = max(near distances, tmin), exit = min(far distances) times
-// the slack.  Also returns the four child references.
+// the slack.  Near distances take one fma each against the lowered offsets
+// of ray_setup; far distances a difference and a product.  Also returns the
+// four child references.
 __device__ __forceinline__ void box4(const Ray& r, __amdgpu_buffer_rsrc_t rs, unsigned base, float tmin, float tmax,
                                      bool hit[4], float tent[4], int ref[4]) {
     const unsigned bx = base | r.nx, by = base | r.ny, bz = base | r.nz;
@@ -361,7 +378,8 @@ __device__ __forceinline__ void box4(const Ray& r, __amdgpu_buffer_rsrc_t rs, un
     const float nza[4] = {nz.x, nz.y, nz.z, nz.w}, fza[4] = {fz.x, fz.y, fz.z, fz.w};
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-        float a = fmaxf(fmaxf((nxa[c] - r.ox) * r.ix, (nya[c] - r.oy) * r.iy), fmaxf((nza[c] - r.oz) * r.iz, tmin));
+        float a = fmaxf(fmaxf(__builtin_fmaf(nxa[c], r.ix, r.cnx), __builtin_fmaf(nya[c], r.iy, r.cny)),
+                        fmaxf(__builtin_fmaf(nza[c], r.iz, r.cnz), tmin));
         float b = fminf(fminf((fxa[c] - r.ox) * r.jx, (fya[c] - r.oy) * r.jy), (fza[c] - r.oz) * r.jz);
         hit[c] = a <= fminf(b, tmax);
         tent[c] = a;
