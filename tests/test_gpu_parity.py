@@ -92,6 +92,35 @@ def test_tree_widths_match_brute_force(scene_kind):
                 assert np.array_equal(ref.weights, g.weights), (accel, b)
 
 
+def test_tree_widths_match_brute_force_far_from_origin():
+    """The Manhattan city, its transmitter and plane moved to (4096.3,
+    -3072.7, 1000.25) m: slab distances of boxes near a ray's origin are then
+    small differences of large products, and the box tests must still keep
+    every box that holds the closest hit.  Binary LBVH, 4-wide tree and brute
+    force: bit-identical hits, cells and weights."""
+    import dataclasses
+    base = sg.manhattan_config(n_rays=400_000)
+    off = np.array([4096.3, -3072.7, 1000.25])
+    scene = dataclasses.replace(base.scene, vertices=(base.scene.vertices + off).astype(np.float32))
+    pl = base.plane
+    cfg = sg.Config(scene, sg.Tx(tuple(np.asarray(base.tx.pos) + off)),
+                    sg.Plane(pl.z + off[2], pl.x0 + off[0], pl.y0 + off[1], 5.0, 5.0, 200, 200), base.params,
+                    "manhattan-far")
+    s = gpu_scene(scene)
+    ref = None
+    for accel in (1, 2, 3):
+        g = gpu_radio_map(cfg, scene_handle=s, accel=accel)
+        assert int(g.stats[4]) == 0, accel
+        if ref is None:
+            ref = g
+            assert (g.hits >= 0).sum() > 400_000      # most rays hit something
+            assert (g.cells >= 0).sum() > 100_000     # and the plane is crossed
+        else:
+            assert np.array_equal(ref.hits, g.hits), accel
+            assert np.array_equal(ref.cells, g.cells), accel
+            assert np.array_equal(ref.weights, g.weights), accel
+
+
 def test_dual_pol_matches_single_pols():
     cfg = sg.tiny_config(n_rays=50_000)
     s = gpu_scene(cfg.scene)
