@@ -11,21 +11,25 @@
 //    every ray once and records its geometry (hit slot, crossed cell,
 //    direction and basis per segment).  The hit sequence does not depend on
 //    the materials or the antenna, so one traversal serves every sample.  A
-//    second kernel runs one thread per (ray, sample): it propagates the field
-//    through the recorded bounces with that sample's permittivities
-//    (eq. fresnel_vac, eq. eta), deposits into the sample's map, and, given
-//    upstream gradients, runs the same reverse sweep as the plain adjoint
-//    (dJ/dp = 2 Re(lambda^H dR/dp E)) with the fields of the forward pass
-//    kept in registers.  Slab walls without refraction (eq. fresnel_slab)
-//    and transmit arrays fit this split: neither changes a ray's path, only
-//    its coefficients or its weight.
+//    second kernel takes the rays 64 at a time: their launch patterns and
+//    bounce geometry are computed once into LDS, and each wavefront of the
+//    block then runs one sample at a time for the 64 rays (lane = ray): it
+//    propagates the field through the recorded bounces with that sample's
+//    permittivities (eq. fresnel_vac, eq. eta), deposits into the sample's
+//    map, and, given upstream gradients, runs the same reverse sweep as the
+//    plain adjoint (dJ/dp = 2 Re(lambda^H dR/dp E)) with the fields of the
+//    forward pass kept in registers.  Slab walls without refraction
+//    (eq. fresnel_slab) and transmit arrays fit this split: neither changes
+//    a ray's path, only its coefficients or its weight.
 //    The geometry records are kept in the launch order of the traversal
 //    (azimuth-sorted chunks of each lattice), so the lanes of a wavefront of
 //    the field pass hold nearby directions: they read consecutive records,
-//    and without gradients their same-cell crossings are summed across the
-//    wavefront before the atomics (measured on 16 samples of 1e6 rays:
-//    1.31 -> 0.81 ms forward; 1.65 -> 1.41 ms forward + backward, where the
-//    gradient variant keeps per-lane atomics for its registers' sake).
+//    and their same-cell crossings are summed across the wavefront before
+//    the atomics.  Measured on 16 samples of 1e6 rays forward + backward:
+//    one thread per ray looping over the samples with every bounce's
+//    geometry in registers (227 VGPRs, per-lane atomics with gradients)
+//    took 1.13 ms; geometry in LDS shared by the block's wavefronts (157
+//    VGPRs) with wavefront deposits takes 0.74 ms.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -122,59 +126,93 @@ __device__ __forceinline__ double wsum(double v) {
     return v;
 }
 
-// One thread per ray: the launch pattern and the geometry of every bounce
-// (basis change W, cos(theta_1), material, crossed cell, deposit factor) are
-// computed once and kept in registers; the loop over material samples then
-// only evaluates Fresnel coefficients and 2-vector field updates.
+// A block is up to four wavefronts over the same 64 consecutive rays.  The
+// rays' launch patterns and the geometry of every bounce (basis change W,
+// cos(theta_1), material, crossed cell, 1 / |cos| of the plane crossing) are
+// computed once per ray, cooperatively, into LDS; wavefront w then runs
+// samples w, w + n_w, ... for the 64 rays (lane = ray), so that a lane keeps
+// only one sample's fields in registers, and a wavefront's deposits go to one
+// sample's map.
+constexpr int kSampRays = 64;
+struct SampShared {
+    float geo[kMaxSeg][6][kSampRays];   // w00, w01, w10, w11, cos(theta_1), 1 / |cos| at the plane
+    int mc[kMaxSeg][2][kSampRays];      // material of the bounce ending the segment, crossed cell
+    float hdr[9][kSampRays];            // C_theta (value, d/d yaw, pitch, roll), C_phi (same), kappa
+    int ns[kSampRays], slot[kSampRays], txi[kSampRays];
+};
+
 template <bool GRAD, bool SLAB, bool ARR>
 __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
-    const int lane = threadIdx.x & 63;
+    __shared__ SampShared sh;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n_wv = blockDim.x >> 6;
     const int64_t HW = (int64_t)a.pl.W * a.pl.H;
     const int64_t T = a.total;
     const int S = a.S;
-    for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < T; g0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t g = g0 + threadIdx.x;
-        const bool valid = g < T;
-        int slot_out = -1, ns = 0, tx_i = -1;
-        TxDesc td;
-        float w00[kMaxSeg], w01[kMaxSeg], w10[kMaxSeg], w11[kMaxSeg], cth1[kMaxSeg], gk[kMaxSeg];
-        int matl[kMaxSeg], cell[kMaxSeg];
-        d3f cth = {0, 0, 0, 0}, cph = {0, 0, 0, 0};
-        if (valid) {
-            const int t = find_tx_s(a.prefix, a.n_tx, g);
-            tx_i = t;
-            td = a.txs[t];
-            slot_out = a.slots[t];
-            const int64_t n = lattice_index(a, td, g - a.prefix[t]);
-            ns = a.nseg[g];
-            Launch Lr = fib_launch(n, td.n_rays);
-            if (GRAD) {
-                tx_pattern<d3f>(Lr, td, td.pol == 1 ? 1 : 0, cth, cph);
-            } else {
-                tx_pattern<float>(Lr, td, td.pol == 1 ? 1 : 0, cth.v, cph.v);
-            }
-            // |alpha|^2 of a transmit array depends on the direction only
-            const float kap = ARR && td.n_ant > 0 ? td.kappa * array_gain(Lr, td) : td.kappa;
-#pragma unroll
-            for (int l = 0; l < kMaxSeg; l++) {
-                if (l >= ns) break;
-                const float4* sp = a.geom + (int64_t)l * 2 * T + g;
-                float4 s0 = sp[0], s1 = sp[T];
-                cell[l] = __float_as_int(s1.w);
-                gk[l] = kap * __builtin_amdgcn_rcpf(fabsf(s0.z));
-                if (l + 1 < ns) {
-                    float4 nm = a.normals[__float_as_int(s0.w)];
-                    matl[l] = __float_as_int(nm.w);
-                    Bounce b = bounce_geometry(f3(s0.x, s0.y, s0.z), f3(s1.x, s1.y, s1.z), f3(nm.x, nm.y, nm.z));
-                    w00[l] = b.w00;
-                    w01[l] = b.w01;
-                    w10[l] = b.w10;
-                    w11[l] = b.w11;
-                    cth1[l] = b.c;
+    for (int64_t g0 = (int64_t)blockIdx.x * kSampRays; g0 < T; g0 += (int64_t)gridDim.x * kSampRays) {
+        // ---- per ray: transmitter, segment count, launch pattern (wavefront 0)
+        if (wv == 0) {
+            const int64_t g = g0 + lane;
+            int ns = 0, slot_out = -1, tx_i = -1;
+            d3f cth = {0, 0, 0, 0}, cph = {0, 0, 0, 0};
+            float kap = 0.0f;
+            if (g < T) {
+                const int t = find_tx_s(a.prefix, a.n_tx, g);
+                const TxDesc td = a.txs[t];
+                tx_i = t;
+                slot_out = a.slots[t];
+                ns = a.nseg[g];
+                const int64_t n = lattice_index(a, td, g - a.prefix[t]);
+                Launch Lr = fib_launch(n, td.n_rays);
+                if (GRAD) {
+                    tx_pattern<d3f>(Lr, td, td.pol == 1 ? 1 : 0, cth, cph);
+                } else {
+                    tx_pattern<float>(Lr, td, td.pol == 1 ? 1 : 0, cth.v, cph.v);
                 }
+                // |alpha|^2 of a transmit array depends on the direction only
+                kap = ARR && td.n_ant > 0 ? td.kappa * array_gain(Lr, td) : td.kappa;
+            }
+            sh.ns[lane] = ns;
+            sh.slot[lane] = slot_out;
+            sh.txi[lane] = tx_i;
+            sh.hdr[0][lane] = cth.v;
+            sh.hdr[1][lane] = cth.d0;
+            sh.hdr[2][lane] = cth.d1;
+            sh.hdr[3][lane] = cth.d2;
+            sh.hdr[4][lane] = cph.v;
+            sh.hdr[5][lane] = cph.d0;
+            sh.hdr[6][lane] = cph.d1;
+            sh.hdr[7][lane] = cph.d2;
+            sh.hdr[8][lane] = kap;
+        }
+        // ---- bounce geometry of every (segment, ray), all lanes of the block
+        for (int it = threadIdx.x; it < kMaxSeg * kSampRays; it += blockDim.x) {
+            const int l = it / kSampRays, r = it % kSampRays;
+            const int64_t g = g0 + r;
+            if (g >= T) continue;
+            const int ns = a.nseg[g];
+            if (l >= ns) continue;
+            const float4* sp = a.geom + (int64_t)l * 2 * T + g;
+            const float4 s0 = sp[0], s1 = sp[T];
+            sh.mc[l][1][r] = __float_as_int(s1.w);
+            sh.geo[l][5][r] = __builtin_amdgcn_rcpf(fabsf(s0.z));
+            if (l + 1 < ns) {
+                const float4 nm = a.normals[__float_as_int(s0.w)];
+                sh.mc[l][0][r] = __float_as_int(nm.w);
+                Bounce b = bounce_geometry(f3(s0.x, s0.y, s0.z), f3(s1.x, s1.y, s1.z), f3(nm.x, nm.y, nm.z));
+                sh.geo[l][0][r] = b.w00;
+                sh.geo[l][1][r] = b.w01;
+                sh.geo[l][2][r] = b.w10;
+                sh.geo[l][3][r] = b.w11;
+                sh.geo[l][4][r] = b.c;
             }
         }
-        for (int s = 0; s < S; s++) {
+        __syncthreads();
+        const int ns = sh.ns[lane], slot_out = sh.slot[lane], tx_i = sh.txi[lane];
+        const bool valid = tx_i >= 0;
+        const d3f cth = {sh.hdr[0][lane], sh.hdr[1][lane], sh.hdr[2][lane], sh.hdr[3][lane]};
+        const d3f cph = {sh.hdr[4][lane], sh.hdr[5][lane], sh.hdr[6][lane], sh.hdr[7][lane]};
+        const float kap = sh.hdr[8][lane];
+        for (int s = wv; s < S; s += n_wv) {
             float ge[kMaxMat], gs[kMaxMat], go[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int j = 0; j < kMaxMat; j++) {
@@ -182,93 +220,87 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                 gs[j] = 0.f;
             }
             cf E0[kMaxSeg], E1[kMaxSeg];
+            const float* eps = a.eps_r + (int64_t)s * a.n_mat;
+            const float* sig = a.sigma + (int64_t)s * a.n_mat;
             {
                 // forward field pass: every lane takes part in the wavefront
-                // deposits (invalid lanes have ns = 0)
-                const float* eps = a.eps_r + (int64_t)s * a.n_mat;
-                const float* sig = a.sigma + (int64_t)s * a.n_mat;
+                // deposits (lanes without a ray have ns = 0)
                 float* map = a.maps + ((int64_t)max(slot_out, 0) * S + s) * HW;
                 cf e0 = {cth.v, 0.f}, e1 = {cph.v, 0.f};
 #pragma unroll
                 for (int l = 0; l < kMaxSeg; l++) {
-                    if (GRAD) {
-                        // gradient variant: per-lane atomics (the wavefront
-                        // sums' registers would cost occupancy here)
-                        if (l >= ns) break;
-                        if (cell[l] >= 0) unsafeAtomicAdd(map + cell[l], gk[l] * (cabs2(e0) + cabs2(e1)));
-                    } else {
-                        if (__ballot(l < ns) == 0ull) break;
-                        const bool live = l < ns;
-                        const int dc = live ? cell[l] : -1;
-                        deposit_wave(map, dc, dc >= 0 ? gk[l] * (cabs2(e0) + cabs2(e1)) : 0.0f, slot_out);
-                        if (!live) continue;
-                    }
+                    const int cl = l < ns ? sh.mc[l][1][lane] : -1;
+                    const float gk = kap * sh.geo[l][5][lane];
+                    if (__ballot(l < ns) == 0ull) break;
+                    deposit_wave(map, cl, cl >= 0 ? gk * (cabs2(e0) + cabs2(e1)) : 0.0f, slot_out);
+                    if (l >= ns) continue;
                     E0[l] = e0;
                     E1[l] = e1;
                     if (l + 1 < ns) {
-                        int m = matl[l];
-                        Fresnel F = fresnel<false>(cth1[l], cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
+                        const int m = sh.mc[l][0][lane];
+                        Fresnel F = fresnel<false>(sh.geo[l][4][lane], cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
                         if (SLAB) {
                             cf tp, tl;
                             slab(F, a.k0 * a.thickness[m], tp, tl);
                         }
-                        cf u0 = cadd(cscale(e0, w00[l]), cscale(e1, w01[l]));
-                        cf u1 = cadd(cscale(e0, w10[l]), cscale(e1, w11[l]));
+                        const float w00 = sh.geo[l][0][lane], w01 = sh.geo[l][1][lane];
+                        const float w10 = sh.geo[l][2][lane], w11 = sh.geo[l][3][lane];
+                        cf u0 = cadd(cscale(e0, w00), cscale(e1, w01));
+                        cf u1 = cadd(cscale(e0, w10), cscale(e1, w11));
                         e0 = cmul(F.rperp, u0);
                         e1 = cmul(cf{-F.rpar.re, -F.rpar.im}, u1);
                     }
                 }
             }
-            if (valid) {
-                const float* eps = a.eps_r + (int64_t)s * a.n_mat;
-                const float* sig = a.sigma + (int64_t)s * a.n_mat;
-                if (GRAD) {
-                    const float* G = a.grad_maps + ((int64_t)slot_out * S + s) * HW;
-                    cf lam0 = {0, 0}, lam1 = {0, 0};
+            if (GRAD && valid) {
+                const float* G = a.grad_maps + ((int64_t)slot_out * S + s) * HW;
+                cf lam0 = {0, 0}, lam1 = {0, 0};
 #pragma unroll
-                    for (int l = kMaxSeg - 1; l >= 0; l--) {
-                        if (l >= ns) continue;
-                        if (cell[l] >= 0) {
-                            float al = G[cell[l]] * gk[l];
-                            lam0 = cadd(lam0, cscale(E0[l], al));
-                            lam1 = cadd(lam1, cscale(E1[l], al));
-                        }
-                        if (l == 0) continue;
-                        const int k = l - 1;      // the bounce that ends segment l-1
-                        int m = matl[k];
-                        Fresnel F = fresnel<true>(cth1[k], cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
-                        if (SLAB) {
-                            cf tp, tl, dtp, dtl;
-                            slab_grad(F, a.k0 * a.thickness[m], tp, tl, dtp, dtl);
-                        }
-                        cf u0 = cadd(cscale(E0[k], w00[k]), cscale(E1[k], w01[k]));
-                        cf u1 = cadd(cscale(E0[k], w10[k]), cscale(E1[k], w11[k]));
-                        cf z = csub(cmulc(lam0, cmul(F.drperp, u0)), cmulc(lam1, cmul(F.drpar, u1)));
-#pragma unroll
-                        for (int jj = 0; jj < kMaxMat; jj++) {
-                            if (jj == m) {
-                                ge[jj] += 2.0f * z.re;
-                                gs[jj] += 2.0f * z.im * a.pl.inv_eps0_omega;
-                            }
-                        }
-                        cf v0 = cmulc(F.rperp, lam0);
-                        cf v1 = cmulc(F.rpar, lam1);
-                        v1 = cf{-v1.re, -v1.im};
-                        lam0 = cadd(cscale(v0, w00[k]), cscale(v1, w10[k]));
-                        lam1 = cadd(cscale(v0, w01[k]), cscale(v1, w11[k]));
+                for (int l = kMaxSeg - 1; l >= 0; l--) {
+                    if (l >= ns) continue;
+                    const int cl = sh.mc[l][1][lane];
+                    if (cl >= 0) {
+                        float al = G[cl] * (kap * sh.geo[l][5][lane]);
+                        lam0 = cadd(lam0, cscale(E0[l], al));
+                        lam1 = cadd(lam1, cscale(E1[l], al));
                     }
-                    go[0] = 2.0f * (lam0.re * cth.d0 + lam1.re * cph.d0);
-                    go[1] = 2.0f * (lam0.re * cth.d1 + lam1.re * cph.d1);
-                    go[2] = 2.0f * (lam0.re * cth.d2 + lam1.re * cph.d2);
+                    if (l == 0) continue;
+                    const int k = l - 1;      // the bounce that ends segment l-1
+                    const int m = sh.mc[k][0][lane];
+                    Fresnel F = fresnel<true>(sh.geo[k][4][lane], cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
+                    if (SLAB) {
+                        cf tp, tl, dtp, dtl;
+                        slab_grad(F, a.k0 * a.thickness[m], tp, tl, dtp, dtl);
+                    }
+                    const float w00 = sh.geo[k][0][lane], w01 = sh.geo[k][1][lane];
+                    const float w10 = sh.geo[k][2][lane], w11 = sh.geo[k][3][lane];
+                    cf u0 = cadd(cscale(E0[k], w00), cscale(E1[k], w01));
+                    cf u1 = cadd(cscale(E0[k], w10), cscale(E1[k], w11));
+                    cf z = csub(cmulc(lam0, cmul(F.drperp, u0)), cmulc(lam1, cmul(F.drpar, u1)));
+#pragma unroll
+                    for (int jj = 0; jj < kMaxMat; jj++) {
+                        if (jj == m) {
+                            ge[jj] += 2.0f * z.re;
+                            gs[jj] += 2.0f * z.im * a.pl.inv_eps0_omega;
+                        }
+                    }
+                    cf v0 = cmulc(F.rperp, lam0);
+                    cf v1 = cmulc(F.rpar, lam1);
+                    v1 = cf{-v1.re, -v1.im};
+                    lam0 = cadd(cscale(v0, w00), cscale(v1, w10));
+                    lam1 = cadd(cscale(v0, w01), cscale(v1, w11));
                 }
+                go[0] = 2.0f * (lam0.re * cth.d0 + lam1.re * cph.d0);
+                go[1] = 2.0f * (lam0.re * cth.d1 + lam1.re * cph.d1);
+                go[2] = 2.0f * (lam0.re * cth.d2 + lam1.re * cph.d2);
             }
             if (GRAD) {
-                // one partial sum per (transmitter, wavefront, sample,
+                // one partial sum per (transmitter, 64-ray group, sample,
                 // parameter), summed later in a fixed order: the lanes of each
-                // transmitter in this wavefront (usually one) are summed with a
+                // transmitter in this group (usually one) are summed with a
                 // butterfly and their leader stores the sums in that
-                // transmitter's entry for this wavefront
-                const int64_t gw = (g0 + (threadIdx.x & ~63)) >> 6;
+                // transmitter's entry for this group
+                const int64_t gw = g0 >> 6;
                 unsigned long long pend = __ballot(valid);
                 bool done = !valid;
                 while (pend) {
@@ -295,6 +327,8 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                 }
             }
         }
+        // the next group of rays overwrites the shared records
+        __syncthreads();
     }
 }
 
@@ -445,7 +479,8 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
     a.operm = b.order ? b.order->perm : nullptr;
     a.oshift = s->shifts;
     a.olog2m = b.order ? b.order->log2m : 0;
-    unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1 << 20, (b.total_rays + kSampBlock - 1) / kSampBlock));
+    unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1 << 20, (b.total_rays + 63) / 64));
+    const unsigned sblock = 64u * (unsigned)std::min(4, S);   // wavefronts of one 64-ray group, one per sample
     if (b.total_rays > 0) {
         // slab walls and transmit arrays each get their own variant, so that
         // the plain one keeps its registers
@@ -453,14 +488,14 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
         if (grad || b.L + 1 <= kMaxSeg) {
             const int v = (grad ? 4 : 0) + (slab_walls ? 2 : 0) + (arrays ? 1 : 0);
             switch (v) {
-            case 0: hipLaunchKernelGGL((k_samples<false, false, false>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
-            case 1: hipLaunchKernelGGL((k_samples<false, false, true>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
-            case 2: hipLaunchKernelGGL((k_samples<false, true, false>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
-            case 3: hipLaunchKernelGGL((k_samples<false, true, true>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
-            case 4: hipLaunchKernelGGL((k_samples<true, false, false>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
-            case 5: hipLaunchKernelGGL((k_samples<true, false, true>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
-            case 6: hipLaunchKernelGGL((k_samples<true, true, false>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
-            default: hipLaunchKernelGGL((k_samples<true, true, true>), dim3(bx), dim3(kSampBlock), 0, st, a); break;
+            case 0: hipLaunchKernelGGL((k_samples<false, false, false>), dim3(bx), dim3(sblock), 0, st, a); break;
+            case 1: hipLaunchKernelGGL((k_samples<false, false, true>), dim3(bx), dim3(sblock), 0, st, a); break;
+            case 2: hipLaunchKernelGGL((k_samples<false, true, false>), dim3(bx), dim3(sblock), 0, st, a); break;
+            case 3: hipLaunchKernelGGL((k_samples<false, true, true>), dim3(bx), dim3(sblock), 0, st, a); break;
+            case 4: hipLaunchKernelGGL((k_samples<true, false, false>), dim3(bx), dim3(sblock), 0, st, a); break;
+            case 5: hipLaunchKernelGGL((k_samples<true, false, true>), dim3(bx), dim3(sblock), 0, st, a); break;
+            case 6: hipLaunchKernelGGL((k_samples<true, true, false>), dim3(bx), dim3(sblock), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_samples<true, true, true>), dim3(bx), dim3(sblock), 0, st, a); break;
             }
         } else {
             unsigned by = (unsigned)std::min<int64_t>(65535, (b.total_rays + kSampBlock - 1) / kSampBlock);
