@@ -5,7 +5,8 @@
   ray of every transmitter was traced exactly once;
 * several material samples (one traversal) equal per-sample rt_radio_map;
 * forward + backward for material samples equals per-sample rt_radio_map +
-  rt_radio_map_backward;
+  rt_radio_map_backward, for sample counts that split unevenly over the
+  wavefronts of a 64-ray group, and repeats bit for bit;
 * the captured HIP graph replays: every replay, with eager work in between,
   equals the first (eager) result.
 """
@@ -110,6 +111,49 @@ def test_material_samples_fwd_bwd_match_plain_adjoint():
             ge = torch.empty(nm, device="cuda")
             gs = torch.empty(nm, device="cuda")
             go = torch.empty(3, device="cuda")
+            rt.rt_radio_map_backward(s, e_k, s_k, txs[t], plane, p, tape, g[t, k].contiguous()[None], ge, gs, go)
+            torch.cuda.synchronize()
+            ref = torch.cat([ge, gs, go]).cpu().numpy().astype(np.float64)
+            got = grads[t, k].cpu().numpy().astype(np.float64)
+            assert np.all(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-6 * np.abs(ref).max()), (t, k, got, ref)
+            a, b = out[t, k].cpu().numpy(), m[0].cpu().numpy()
+            big = b > 1e-9 * b.max()
+            np.testing.assert_allclose(a[big], b[big], rtol=2e-5)
+
+
+@pytest.mark.parametrize("S", [1, 6])
+def test_material_samples_uneven_wavefront_share_and_determinism(S):
+    """The sample kernel gives each group of 64 rays to min(4, S) wavefronts
+    that take every fourth sample: S = 1 runs one wavefront per group, S = 6
+    two wavefronts with two samples and two with one.  Maps and gradients of
+    the first and last sample equal per-sample forward + adjoint calls, and a
+    second call reproduces every gradient bit for bit (partial sums in a
+    fixed order)."""
+    rt, torch, scene, s, txs, budgets, plane, params = _setup(n_tx=2)
+    txs = [sg.Tx(t.pos, yaw=0.2 + 0.5 * i, pitch=-0.1, pattern=sg.PATTERN_DIRECTIONAL) for i, t in enumerate(txs)]
+    E, Sg = sg.random_materials(scene, S, seed=8)
+    eps = torch.tensor(E, dtype=torch.float32, device="cuda")
+    sig = torch.tensor(Sg, dtype=torch.float32, device="cuda")
+    T = len(txs)
+    g = torch.randn((T, S, plane.H, plane.W), generator=torch.Generator().manual_seed(9)).to("cuda")
+    g = torch.nn.functional.avg_pool2d(g.view(T * S, 1, plane.H, plane.W), 9, 1, 4).view_as(g).contiguous()
+    out = torch.empty((T, S, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    nm = scene.n_materials
+    grads = torch.empty((T, S, 2 * nm + 3), dtype=torch.float32, device="cuda")
+    grads2 = torch.empty_like(grads)
+    rt.rt_radio_map_batched(s, eps, sig, txs, budgets, plane, params, out, grad_maps=g, grads=grads)
+    rt.rt_radio_map_batched(s, eps, sig, txs, budgets, plane, params, torch.empty_like(out), grad_maps=g,
+                            grads=grads2)
+    torch.cuda.synchronize()
+    assert torch.equal(grads, grads2)
+    for t in range(T):
+        p = sg.Params(params.freq_hz, int(budgets[t]), params.max_depth)
+        for k in sorted({0, S - 1}):
+            m = torch.empty((1, plane.H, plane.W), dtype=torch.float32, device="cuda")
+            tape = rt.rt_tape_create(p)
+            e_k, s_k = eps[k].contiguous(), sig[k].contiguous()
+            rt.rt_radio_map(s, e_k, s_k, txs[t], plane, p, m, tape=tape)
+            ge, gs, go = (torch.empty(n, device="cuda") for n in (nm, nm, 3))
             rt.rt_radio_map_backward(s, e_k, s_k, txs[t], plane, p, tape, g[t, k].contiguous()[None], ge, gs, go)
             torch.cuda.synchronize()
             ref = torch.cat([ge, gs, go]).cpu().numpy().astype(np.float64)
