@@ -29,7 +29,9 @@
 //    one thread per ray looping over the samples with every bounce's
 //    geometry in registers (227 VGPRs, per-lane atomics with gradients)
 //    took 1.13 ms; geometry in LDS shared by the block's wavefronts (157
-//    VGPRs) with wavefront deposits takes 0.74 ms.
+//    VGPRs) with wavefront deposits took 0.74 ms; with the forward fields
+//    in LDS as well for paths of at most six segments (124 VGPRs, four
+//    wavefronts per SIMD) it takes 0.66 ms.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -134,16 +136,26 @@ __device__ __forceinline__ double wsum(double v) {
 // only one sample's fields in registers, and a wavefront's deposits go to one
 // sample's map.
 constexpr int kSampRays = 64;
+constexpr int kShortSeg = 6;    // paths of at most 6 segments (L <= 5): the short variant
+template <int NSEG>
 struct SampShared {
-    float geo[kMaxSeg][6][kSampRays];   // w00, w01, w10, w11, cos(theta_1), 1 / |cos| at the plane
-    int mc[kMaxSeg][2][kSampRays];      // material of the bounce ending the segment, crossed cell
+    float geo[NSEG][6][kSampRays];      // w00, w01, w10, w11, cos(theta_1), 1 / |cos| at the plane
+    int mc[NSEG][2][kSampRays];         // material of the bounce ending the segment, crossed cell
     float hdr[9][kSampRays];            // C_theta (value, d/d yaw, pitch, roll), C_phi (same), kappa
     int ns[kSampRays], slot[kSampRays], txi[kSampRays];
 };
 
-template <bool GRAD, bool SLAB, bool ARR>
+// NSEG: segments per path the variant holds (kShortSeg or kMaxSeg).  With
+// gradients the short variant keeps the forward fields for the reverse sweep
+// in LDS too (a lane's four floats per segment), which leaves it few enough
+// registers for four wavefronts per SIMD; the long one keeps them in
+// registers.
+template <bool GRAD, bool SLAB, bool ARR, int NSEG>
 __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
-    __shared__ SampShared sh;
+    __shared__ SampShared<NSEG> sh;
+    constexpr bool kLdsFields = GRAD && NSEG <= kShortSeg;
+    // [segment][wavefront][Re E0, Im E0, Re E1, Im E1][lane]
+    __shared__ float fld[kLdsFields ? NSEG * 4 * 4 * kSampRays : 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n_wv = blockDim.x >> 6;
     const int64_t HW = (int64_t)a.pl.W * a.pl.H;
     const int64_t T = a.total;
@@ -185,7 +197,7 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
             sh.hdr[8][lane] = kap;
         }
         // ---- bounce geometry of every (segment, ray), all lanes of the block
-        for (int it = threadIdx.x; it < kMaxSeg * kSampRays; it += blockDim.x) {
+        for (int it = threadIdx.x; it < NSEG * kSampRays; it += blockDim.x) {
             const int l = it / kSampRays, r = it % kSampRays;
             const int64_t g = g0 + r;
             if (g >= T) continue;
@@ -219,7 +231,8 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                 ge[j] = 0.f;
                 gs[j] = 0.f;
             }
-            cf E0[kMaxSeg], E1[kMaxSeg];
+            cf E0[NSEG], E1[NSEG];
+            float* const fl = fld + (kLdsFields ? wv * 4 * kSampRays + lane : 0);
             const float* eps = a.eps_r + (int64_t)s * a.n_mat;
             const float* sig = a.sigma + (int64_t)s * a.n_mat;
             {
@@ -228,14 +241,22 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                 float* map = a.maps + ((int64_t)max(slot_out, 0) * S + s) * HW;
                 cf e0 = {cth.v, 0.f}, e1 = {cph.v, 0.f};
 #pragma unroll
-                for (int l = 0; l < kMaxSeg; l++) {
+                for (int l = 0; l < NSEG; l++) {
                     const int cl = l < ns ? sh.mc[l][1][lane] : -1;
                     const float gk = kap * sh.geo[l][5][lane];
                     if (__ballot(l < ns) == 0ull) break;
                     deposit_wave(map, cl, cl >= 0 ? gk * (cabs2(e0) + cabs2(e1)) : 0.0f, slot_out);
                     if (l >= ns) continue;
-                    E0[l] = e0;
-                    E1[l] = e1;
+                    if (kLdsFields) {
+                        float* f = fl + l * 16 * kSampRays;
+                        f[0] = e0.re;
+                        f[kSampRays] = e0.im;
+                        f[2 * kSampRays] = e1.re;
+                        f[3 * kSampRays] = e1.im;
+                    } else {
+                        E0[l] = e0;
+                        E1[l] = e1;
+                    }
                     if (l + 1 < ns) {
                         const int m = sh.mc[l][0][lane];
                         Fresnel F = fresnel<false>(sh.geo[l][4][lane], cf{eps[m], -sig[m] * a.pl.inv_eps0_omega});
@@ -255,14 +276,26 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
             if (GRAD && valid) {
                 const float* G = a.grad_maps + ((int64_t)slot_out * S + s) * HW;
                 cf lam0 = {0, 0}, lam1 = {0, 0};
+                auto field = [&](int l, cf& f0, cf& f1) {
+                    if (kLdsFields) {
+                        const float* f = fl + l * 16 * kSampRays;
+                        f0 = cf{f[0], f[kSampRays]};
+                        f1 = cf{f[2 * kSampRays], f[3 * kSampRays]};
+                    } else {
+                        f0 = E0[l];
+                        f1 = E1[l];
+                    }
+                };
 #pragma unroll
-                for (int l = kMaxSeg - 1; l >= 0; l--) {
+                for (int l = NSEG - 1; l >= 0; l--) {
                     if (l >= ns) continue;
                     const int cl = sh.mc[l][1][lane];
                     if (cl >= 0) {
                         float al = G[cl] * (kap * sh.geo[l][5][lane]);
-                        lam0 = cadd(lam0, cscale(E0[l], al));
-                        lam1 = cadd(lam1, cscale(E1[l], al));
+                        cf f0, f1;
+                        field(l, f0, f1);
+                        lam0 = cadd(lam0, cscale(f0, al));
+                        lam1 = cadd(lam1, cscale(f1, al));
                     }
                     if (l == 0) continue;
                     const int k = l - 1;      // the bounce that ends segment l-1
@@ -274,8 +307,10 @@ __global__ void __launch_bounds__(kSampBlock) k_samples(const SampArgs a) {
                     }
                     const float w00 = sh.geo[k][0][lane], w01 = sh.geo[k][1][lane];
                     const float w10 = sh.geo[k][2][lane], w11 = sh.geo[k][3][lane];
-                    cf u0 = cadd(cscale(E0[k], w00), cscale(E1[k], w01));
-                    cf u1 = cadd(cscale(E0[k], w10), cscale(E1[k], w11));
+                    cf f0, f1;
+                    field(k, f0, f1);
+                    cf u0 = cadd(cscale(f0, w00), cscale(f1, w01));
+                    cf u1 = cadd(cscale(f0, w10), cscale(f1, w11));
                     cf z = csub(cmulc(lam0, cmul(F.drperp, u0)), cmulc(lam1, cmul(F.drpar, u1)));
 #pragma unroll
                     for (int jj = 0; jj < kMaxMat; jj++) {
@@ -487,15 +522,28 @@ rt_status rt_launch_batched(const BatchLaunch& b, hipStream_t st) {
         const bool slab_walls = a.thickness != nullptr, arrays = b.has_arrays;
         if (grad || b.L + 1 <= kMaxSeg) {
             const int v = (grad ? 4 : 0) + (slab_walls ? 2 : 0) + (arrays ? 1 : 0);
-            switch (v) {
-            case 0: hipLaunchKernelGGL((k_samples<false, false, false>), dim3(bx), dim3(sblock), 0, st, a); break;
-            case 1: hipLaunchKernelGGL((k_samples<false, false, true>), dim3(bx), dim3(sblock), 0, st, a); break;
-            case 2: hipLaunchKernelGGL((k_samples<false, true, false>), dim3(bx), dim3(sblock), 0, st, a); break;
-            case 3: hipLaunchKernelGGL((k_samples<false, true, true>), dim3(bx), dim3(sblock), 0, st, a); break;
-            case 4: hipLaunchKernelGGL((k_samples<true, false, false>), dim3(bx), dim3(sblock), 0, st, a); break;
-            case 5: hipLaunchKernelGGL((k_samples<true, false, true>), dim3(bx), dim3(sblock), 0, st, a); break;
-            case 6: hipLaunchKernelGGL((k_samples<true, true, false>), dim3(bx), dim3(sblock), 0, st, a); break;
-            default: hipLaunchKernelGGL((k_samples<true, true, true>), dim3(bx), dim3(sblock), 0, st, a); break;
+            if (b.L + 1 <= kShortSeg) {
+                switch (v) {
+                case 0: hipLaunchKernelGGL((k_samples<false, false, false, kShortSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 1: hipLaunchKernelGGL((k_samples<false, false, true, kShortSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 2: hipLaunchKernelGGL((k_samples<false, true, false, kShortSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 3: hipLaunchKernelGGL((k_samples<false, true, true, kShortSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 4: hipLaunchKernelGGL((k_samples<true, false, false, kShortSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 5: hipLaunchKernelGGL((k_samples<true, false, true, kShortSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 6: hipLaunchKernelGGL((k_samples<true, true, false, kShortSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                default: hipLaunchKernelGGL((k_samples<true, true, true, kShortSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                }
+            } else {
+                switch (v) {
+                case 0: hipLaunchKernelGGL((k_samples<false, false, false, kMaxSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 1: hipLaunchKernelGGL((k_samples<false, false, true, kMaxSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 2: hipLaunchKernelGGL((k_samples<false, true, false, kMaxSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 3: hipLaunchKernelGGL((k_samples<false, true, true, kMaxSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 4: hipLaunchKernelGGL((k_samples<true, false, false, kMaxSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 5: hipLaunchKernelGGL((k_samples<true, false, true, kMaxSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                case 6: hipLaunchKernelGGL((k_samples<true, true, false, kMaxSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                default: hipLaunchKernelGGL((k_samples<true, true, true, kMaxSeg>), dim3(bx), dim3(sblock), 0, st, a); break;
+                }
             }
         } else {
             unsigned by = (unsigned)std::min<int64_t>(65535, (b.total_rays + kSampBlock - 1) / kSampBlock);

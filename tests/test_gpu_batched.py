@@ -121,15 +121,18 @@ def test_material_samples_fwd_bwd_match_plain_adjoint():
             np.testing.assert_allclose(a[big], b[big], rtol=2e-5)
 
 
-@pytest.mark.parametrize("S", [1, 6])
-def test_material_samples_uneven_wavefront_share_and_determinism(S):
+@pytest.mark.parametrize("S,L", [(1, 5), (6, 5), (2, 7)])
+def test_material_samples_uneven_wavefront_share_and_determinism(S, L):
     """The sample kernel gives each group of 64 rays to min(4, S) wavefronts
     that take every fourth sample: S = 1 runs one wavefront per group, S = 6
     two wavefronts with two samples and two with one.  Maps and gradients of
     the first and last sample equal per-sample forward + adjoint calls, and a
     second call reproduces every gradient bit for bit (partial sums in a
-    fixed order)."""
+    fixed order).  Paths of up to six segments take the variant that keeps
+    the forward fields in LDS, longer ones (L = 7) the one that keeps them in
+    registers."""
     rt, torch, scene, s, txs, budgets, plane, params = _setup(n_tx=2)
+    params = sg.Params(params.freq_hz, 1, L)
     txs = [sg.Tx(t.pos, yaw=0.2 + 0.5 * i, pitch=-0.1, pattern=sg.PATTERN_DIRECTIONAL) for i, t in enumerate(txs)]
     E, Sg = sg.random_materials(scene, S, seed=8)
     eps = torch.tensor(E, dtype=torch.float32, device="cuda")
