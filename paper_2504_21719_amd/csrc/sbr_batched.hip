@@ -42,7 +42,7 @@ using namespace rtd;
 
 namespace {
 
-constexpr int kMaxSeg = 9;      // register-resident fields for L <= 8 in gradient mode
+constexpr int kMaxSeg = 9;      // segments per path of the sample kernel (L <= 8 with gradients)
 constexpr int kMaxMat = 8;      // materials with gradients in batched mode
 constexpr int kSampBlock = 256;
 
