@@ -427,7 +427,9 @@ rt_status rt_radio_map_backward_noalloc(const rt_scene* scene, rt_materials mate
  * one call ("radio maps for multiple sources in parallel", Sec. "Radio Map
  * Solver").
  *   materials   device float32 [n_samples][n_materials]
- *   txs         host [n_tx] transmitters (pol V or H; DUAL is rejected)
+ *   n_samples   1..64 material samples
+ *   txs         host [n_tx] transmitters, n_tx 1..4096 (pol V or H; DUAL is
+ *               rejected)
  *   rays_per_tx host int64 [n_tx]: N_S of each transmitter's lattice
  *   params      n_rays, ray_begin and ray_end are ignored
  *   out_maps    device float32 [n_tx][n_samples][H][W]
@@ -449,7 +451,9 @@ rt_status rt_radio_map_backward_noalloc(const rt_scene* scene, rt_materials mate
  * samples or gradients share one traversal per ray, so they take only what
  * leaves the paths unchanged: transmit arrays and slab walls without
  * refraction (one thickness array for all samples); refraction, diffuse
- * reflection and early termination give RT_EUNSUPPORTED there.
+ * reflection and early termination give RT_EUNSUPPORTED there, and so do
+ * gradients with max_depth above 8 or more than 8 materials.  Out-of-range
+ * counts give RT_EINVAL before any device work.
  */
 rt_status rt_radio_map_batched(const rt_scene* scene, rt_materials materials,
                                int32_t n_samples, const rt_tx* txs,
