@@ -19,10 +19,11 @@ of the same lattice; its time is reported separately.
 Printed: one JSON line with the metric, a roofline object for the forward
 kernel, and the FP64 oracle timed on a strided sample of the same lattice on
 the host cores.  Roofline: the forward kernel issues VALU instructions on
-about 87 % of its cycles and moves about 1.5 % of the HBM peak (the 341 MB
-tree is served from the L2 caches and the 256 MB MALL), so it is reported
-against the VALU issue rate (256 CUs x 64 lanes x 2.4 GHz = 39.3 T FP32
-lane-operations/s) with an algorithmic operation count per segment (see
+about 92 % of its cycles and moves about 2 % of the HBM peak (the 326 MB of
+tree, triangles and normals are served from the vector L1 caches, the L2
+and the 256 MB MALL), so it is reported against the VALU issue rate (256
+CUs x 64 lanes x 2.4 GHz = 39.3 T FP32 lane-operations/s) with an
+algorithmic operation count per segment (see
 ALU_OPS below); the algorithmic HBM byte model and the measured DRAM bytes
 are reported beside it ("hbm_model").  Side legs: the Manhattan city (1e7
 rays, L = 5), differentiation and batching ratios, transmit arrays, slab
