@@ -27,8 +27,9 @@ algorithmic operation count per segment (see
 ALU_OPS below); the algorithmic HBM byte model and the measured DRAM bytes
 are reported beside it ("hbm_model").  Side legs: the Manhattan city (1e7
 rays, L = 5), differentiation and batching ratios, transmit arrays, slab
-walls with refraction, diffuse reflection, Russian roulette, and 64 rooftop
-transmitters on both scenes.
+walls with refraction, diffuse reflection, Russian roulette, 64 rooftop
+transmitters on both scenes, and the time per map against N_S (up to 1e9)
+and the number of transmit antennas (up to 512).
 """
 from __future__ import annotations
 
@@ -320,6 +321,8 @@ def main():
                 _progress("ratio legs done")
                 result["array"] = array_leg(rt, sg, cfg, mscene, meps, msig, mout)
                 _progress("array leg done")
+                result["samples_sweep"] = samples_leg(rt, sg, cfg, mscene, meps, msig, mout)
+                _progress("samples sweep done")
                 result["refraction"] = refraction_leg(rt, sg, cfg, dev, mout)
                 _progress("refraction leg done")
                 result["diffuse"] = diffuse_leg(rt, sg, cfg, mscene, meps, msig, dev, mout)
@@ -694,6 +697,45 @@ def array_leg(rt, sg, cfg, scene, eps, sig, out, sizes=(1, 16, 64, 256, 1024)):
             st = int(stats[0])
         res["ms"][str(n)] = round(t, 3)
         res["M ray-bounces/s"][str(n)] = round(st / (t * 1e-3) / 1e6, 1)
+    return res
+
+
+def samples_leg(rt, sg, cfg, scene, eps, sig, out, n_rays=(10 ** 6, 10 ** 7, 10 ** 8, 10 ** 9), sizes=(1, 64, 512)):
+    """Time per radio map against the number of samples N_S and the number of
+    transmit antennas, the shape of the paper's radio-map timing experiment
+    (Sec. "Radio Map Solver": one source 20 m above the ground of a street
+    scene, N_S up to 1e9, arrays of up to 512 antennas): the Manhattan city
+    stands in for the street scene, with an isotropic V-pol source at
+    (0, 0, 20) m and, for several antennas, a half-wavelength uniform linear
+    array along x steered to x-cosine 0.5."""
+    import math
+    import numpy as np
+    import torch
+    lam = 299792458.0 / cfg.params.freq_hz
+    pos = (0.0, 0.0, 20.0)
+    res = {"workload": "manhattan (street-scene stand-in), iso V-pol source at (0, 0, 20) m, L = %d, %dx%d cells "
+                       "of %g m; ULA along x, half-wavelength spacing, steered to x-cosine 0.5"
+                       % (cfg.params.max_depth, cfg.plane.W, cfg.plane.H, cfg.plane.dx),
+           "ms": {}, "M ray-bounces/s": {}, "segments": {}}
+    for N in n_rays:
+        p = sg.Params(cfg.params.freq_hz, int(N), cfg.params.max_depth)
+        stats = torch.zeros(8, dtype=torch.int64, device=out.device)
+        rt.rt_radio_map(scene, eps, sig, sg.Tx(pos), cfg.plane, p, out, stats=stats)
+        torch.cuda.synchronize()
+        seg = int(stats[0])
+        res["segments"]["%.0e" % N] = seg
+        for n in sizes:
+            if n == 1:
+                tx = sg.Tx(pos)
+            else:
+                base = sg.linear_array(n, 0.5 * lam)
+                u = np.exp(-2j * math.pi * base.positions[:, 0] / lam * 0.5) / math.sqrt(n)
+                tx = sg.Tx(pos, array=sg.TxArray(base.positions, u.astype(np.complex64)))
+            reps = 2 if N >= 10 ** 9 else 3
+            t = _time(lambda: rt.rt_radio_map(scene, eps, sig, tx, cfg.plane, p, out), reps, 1)
+            key = "N_S=%.0e,N_A=%d" % (N, n)
+            res["ms"][key] = round(t, 3)
+            res["M ray-bounces/s"][key] = round(seg / (t * 1e-3) / 1e6, 1)
     return res
 
 
