@@ -321,8 +321,8 @@ def main():
                 _progress("ratio legs done")
                 result["array"] = array_leg(rt, sg, cfg, mscene, meps, msig, mout)
                 _progress("array leg done")
-                result["samples_sweep"] = samples_leg(rt, sg, cfg, mscene, meps, msig, mout)
-                _progress("samples sweep done")
+                result["n_s_sweep"] = n_s_leg(rt, sg, cfg, mscene, meps, msig, mout)
+                _progress("N_S sweep done")
                 result["refraction"] = refraction_leg(rt, sg, cfg, dev, mout)
                 _progress("refraction leg done")
                 result["diffuse"] = diffuse_leg(rt, sg, cfg, mscene, meps, msig, dev, mout)
@@ -700,7 +700,7 @@ def array_leg(rt, sg, cfg, scene, eps, sig, out, sizes=(1, 16, 64, 256, 1024)):
     return res
 
 
-def samples_leg(rt, sg, cfg, scene, eps, sig, out, n_rays=(10 ** 6, 10 ** 7, 10 ** 8, 10 ** 9), sizes=(1, 64, 512)):
+def n_s_leg(rt, sg, cfg, scene, eps, sig, out, n_rays=(10 ** 6, 10 ** 7, 10 ** 8, 10 ** 9), sizes=(1, 64, 512)):
     """Time per radio map against the number of samples N_S and the number of
     transmit antennas, the shape of the paper's radio-map timing experiment
     (Sec. "Radio Map Solver": one source 20 m above the ground of a street
