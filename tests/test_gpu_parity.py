@@ -199,6 +199,35 @@ def test_degenerate_inputs():
     assert g2.hits.shape == (1, 1) and int(g2.hits[0, 0]) == int(o2.hits[0, 0])
 
 
+def test_empty_ray_range():
+    """An empty sub-range [5, 5) of the lattice: the forward zeroes the map
+    (or leaves it as it was with accumulate = 1), traces nothing, and the
+    adjoint of its tape returns zero gradients."""
+    import torch
+    import paper_2504_21719_amd as rt
+    cfg = sg.tiny_config(n_rays=1000, max_depth=3)
+    s = gpu_scene(cfg.scene)
+    eps = torch.tensor(cfg.scene.eps_r, dtype=torch.float32, device="cuda")
+    sig = torch.tensor(cfg.scene.sigma, dtype=torch.float32, device="cuda")
+    p = sg.Params(3.5e9, 1000, 3, ray_begin=5, ray_end=5)
+    out = torch.full((1, cfg.plane.H, cfg.plane.W), 7.0, dtype=torch.float32, device="cuda")
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    tape = rt.rt_tape_create(p)
+    rt.rt_radio_map(s, eps, sig, cfg.tx, cfg.plane, p, out, tape=tape, stats=stats)
+    torch.cuda.synchronize()
+    assert int(out.abs().max()) == 0 and int(stats.abs().max()) == 0
+    out.fill_(7.0)
+    rt.rt_radio_map(s, eps, sig, cfg.tx, cfg.plane, p, out, accumulate=1)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+    nm = cfg.scene.n_materials
+    ge, gs, go = (torch.full((n,), 3.0, device="cuda") for n in (nm, nm, 3))
+    g = torch.ones((1, cfg.plane.H, cfg.plane.W), dtype=torch.float32, device="cuda")
+    rt.rt_radio_map_backward(s, eps, sig, cfg.tx, cfg.plane, p, tape, g, ge, gs, go)
+    torch.cuda.synchronize()
+    assert float(torch.cat([ge, gs, go]).abs().max()) == 0.0
+
+
 # launch configuration the benchmark's autotuner picks for the Manhattan
 # workload (tree width, order, workgroup, deposit, refill); results do not
 # depend on it beyond FP32 summation order
