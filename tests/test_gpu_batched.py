@@ -66,6 +66,49 @@ def test_multi_transmitter_matches_plain_loop():
         np.testing.assert_allclose(out.cpu().numpy(), first.cpu().numpy(), rtol=2e-5, atol=1e-30)
 
 
+def test_tiny_budgets_at_wavefront_boundaries():
+    """Budgets of 1 (the one-ray lattice), 2, 63, 64, 65 and 129 rays, so that
+    transmitters start and end inside and on the edges of 64-ray groups: every
+    transmitter's batched map equals its own call, forward only and with
+    gradients of two material samples."""
+    rt, torch, scene, s, txs, _, plane, params = _setup(n_tx=6)
+    budgets = [1, 2, 63, 64, 65, 129]
+    eps = torch.tensor(scene.eps_r, dtype=torch.float32, device="cuda")
+    sig = torch.tensor(scene.sigma, dtype=torch.float32, device="cuda")
+    T = len(txs)
+    out = torch.full((T, 1, plane.H, plane.W), float("nan"), dtype=torch.float32, device="cuda")
+    rt.rt_radio_map_batched(s, eps[None], sig[None], txs, budgets, plane, params, out)
+    torch.cuda.synchronize()
+    for t in range(T):
+        ref = _plain(rt, torch, s, eps, sig, txs[t], budgets[t], plane, params)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(out[t, 0].cpu().numpy(), ref[0].cpu().numpy(), rtol=2e-5, atol=1e-30)
+    S = 2
+    E, Sg = sg.random_materials(scene, S, seed=10)
+    eS = torch.tensor(E, dtype=torch.float32, device="cuda")
+    sS = torch.tensor(Sg, dtype=torch.float32, device="cuda")
+    g = torch.ones((T, S, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    outs = torch.empty((T, S, plane.H, plane.W), dtype=torch.float32, device="cuda")
+    nm = scene.n_materials
+    grads = torch.empty((T, S, 2 * nm + 3), dtype=torch.float32, device="cuda")
+    rt.rt_radio_map_batched(s, eS, sS, txs, budgets, plane, params, outs, grad_maps=g, grads=grads)
+    torch.cuda.synchronize()
+    for t in range(T):
+        p = sg.Params(params.freq_hz, budgets[t], params.max_depth)
+        for k in range(S):
+            m = torch.empty((1, plane.H, plane.W), dtype=torch.float32, device="cuda")
+            tape = rt.rt_tape_create(p)
+            e_k, s_k = eS[k].contiguous(), sS[k].contiguous()
+            rt.rt_radio_map(s, e_k, s_k, txs[t], plane, p, m, tape=tape)
+            ge, gs, go = (torch.empty(n, device="cuda") for n in (nm, nm, 3))
+            rt.rt_radio_map_backward(s, e_k, s_k, txs[t], plane, p, tape, g[t, k].contiguous()[None], ge, gs, go)
+            torch.cuda.synchronize()
+            np.testing.assert_allclose(outs[t, k].cpu().numpy(), m[0].cpu().numpy(), rtol=2e-5, atol=1e-30)
+            ref = torch.cat([ge, gs, go]).cpu().numpy().astype(np.float64)
+            got = grads[t, k].cpu().numpy().astype(np.float64)
+            assert np.all(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-6 * np.abs(ref).max() + 1e-30), (t, k)
+
+
 def test_material_samples_match_plain_calls():
     rt, torch, scene, s, txs, budgets, plane, params = _setup(n_tx=3)
     S = 4
