@@ -41,6 +41,12 @@
  *     writes no output.
  *   - The library never takes ownership of caller memory.  Objects it creates
  *     (rt_scene, rt_tape) are released only by their destroy calls.
+ *   - Calls on one rt_scene share its device work state (work-queue
+ *     counters, traversal spill area, launch-order tables, workspaces and
+ *     the captured batched graph): queue them on one stream, or order them
+ *     across streams and host threads; calls on different scenes are
+ *     independent.  Likewise a tape belongs to one forward-backward pair at
+ *     a time.
  *   - Environment overrides of the launch configuration, for experiments
  *     (each changes results only up to FP32 summation order):
  *     RTMAP_WIDTH (2: binary tree, else 4-wide), RTMAP_ORDER (0: lattice
