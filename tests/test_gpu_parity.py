@@ -228,6 +228,46 @@ def test_empty_ray_range():
     assert float(torch.cat([ge, gs, go]).abs().max()) == 0.0
 
 
+def test_two_scenes_on_two_streams():
+    """Calls on different scenes are independent: the Manhattan city and the
+    tiny scene traced at the same time on two non-default streams (each
+    call's inputs made on its own stream) give the maps and the adjoint they
+    give one after the other on the default stream."""
+    import torch
+    import paper_2504_21719_amd as rt
+    cfgs = [sg.manhattan_config(n_rays=2_000_000, max_depth=5), sg.tiny_config(n_rays=500_000, max_depth=3)]
+    cfgs[0].plane = sg.Plane(1.5, -500.0, -500.0, 5.0, 5.0, 200, 200)
+    scenes = [gpu_scene(c.scene) for c in cfgs]
+    mats = [(torch.tensor(c.scene.eps_r, dtype=torch.float32, device="cuda"),
+             torch.tensor(c.scene.sigma, dtype=torch.float32, device="cuda")) for c in cfgs]
+    txs = [sg.Tx(c.tx.pos, yaw=0.3, pitch=-0.1, pattern=sg.PATTERN_DIRECTIONAL) for c in cfgs]
+
+    def run(k, stream):
+        c, (e, g) = cfgs[k], mats[k]
+        with torch.cuda.stream(stream):
+            out = torch.empty((1, c.plane.H, c.plane.W), dtype=torch.float32, device="cuda")
+            tape = rt.rt_tape_create(c.params)
+            rt.rt_radio_map(scenes[k], e, g, txs[k], c.plane, c.params, out, tape=tape, stream=stream)
+            up = torch.ones_like(out)
+            n = c.scene.n_materials
+            ge, gs, go = (torch.empty(m, device="cuda") for m in (n, n, 3))
+            rt.rt_radio_map_backward(scenes[k], e, g, txs[k], c.plane, c.params, tape, up, ge, gs, go,
+                                     stream=stream)
+            grads = torch.cat([ge, gs, go])     # on the same stream, after the adjoint
+        return out, grads, tape
+
+    ref = [run(k, torch.cuda.current_stream()) for k in (0, 1)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    got = [run(k, streams[k]) for k in (0, 1)]
+    torch.cuda.synchronize()
+    for k in (0, 1):
+        a, b = got[k][0].cpu().numpy(), ref[k][0].cpu().numpy()
+        np.testing.assert_allclose(a, b, rtol=2e-5, atol=1e-30 + 1e-9 * float(b.max()))
+        assert torch.equal(got[k][1], ref[k][1]), k      # the adjoint sums in a fixed order
+
+
 # launch configuration the benchmark's autotuner picks for the Manhattan
 # workload (tree width, order, workgroup, deposit, refill); results do not
 # depend on it beyond FP32 summation order
